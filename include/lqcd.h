@@ -1,0 +1,192 @@
+/*
+ * lqcd.h -- C ABI of the MI355X (gfx950) even-odd Wilson/clover operator and
+ * its Krylov solvers.
+ *
+ * The library takes over the calculation of fermion propagators from a host
+ * application, converting data to its own layout on the way in and back on the
+ * way out (the paper, Sec. 1 and Sec. 2: machine-specific code plugged in as an
+ * alternative to the generic code, with data conversion before and after).
+ *
+ * Operator (Sec. 2, Eq. (1); matrix elements are the textbook Wilson and
+ * Sheikholeslami-Wohlert ones, which the paper names but does not print):
+ *
+ *   D psi(x) = A(x) psi(x) - kappa * sum_mu [ eta (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                           + eta (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *   A(x)     = 1 + kappa c_SW sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x)   (A = 1 for c_SW = 0)
+ *   sigma_{mu nu} = [gamma_mu, gamma_nu]/(2i),  F_{mu nu} = (Q_{mu nu} - Q_{mu nu}^dag)/(8i),
+ *   Q_{mu nu} = sum of the four plaquettes in the (mu, nu) plane that start and end at x.
+ *
+ * gamma matrices are Dirac-Pauli: gamma_j = [[0, -i s_j], [i s_j, 0]] (j = x, y, z),
+ * gamma_t = diag(1, 1, -1, -1). eta = t_bc on a hop in t that crosses the
+ * lattice boundary, 1 otherwise; all other directions are periodic.
+ *
+ * Even-odd blocks (Eq. (1)): with P_e, P_o the projectors on even
+ * ((x+y+z+t) mod 2 = 0) and odd sites, D_pq = P_p D P_q. The solver works on
+ * the Schur complement S = D_ee - D_eo D_oo^-1 D_oe; the paper's form is
+ * D^(eo) = 1 - D_ee^-1 D_eo D_oo^-1 D_oe = D_ee^-1 S.
+ *
+ * Canonical layouts at this boundary (complex128 = two doubles, re then im):
+ *   spinor  psi[t][z][y][x][spin 0..3][colour 0..2]            (12 complex per site)
+ *   gauge   U[t][z][y][x][mu 0..3 = x,y,z,t][row 0..2][col 0..2] (9 complex per link)
+ * Parity operators take and return full-lattice vectors; D_pq reads parity q of
+ * its input and writes parity p of its output, and sets the other parity of the
+ * output to zero, so D = D_ee + D_eo + D_oe + D_oo holds exactly.
+ *
+ * Conventions for every call:
+ *   - Return value: LQCD_OK (0) or a negative lqcd_status. No exception crosses
+ *     the ABI. lqcd_strerror() names a status; lqcd_last_error() gives detail.
+ *   - Ownership: the caller owns every pointer it passes; the library copies what
+ *     it keeps (gauge, clover) and keeps no caller pointer after a call returns.
+ *   - on_device = 1: the pointer is device memory of the context's GPU (e.g. a
+ *     torch tensor's data_ptr()); on_device = 0: host memory.
+ *   - Streams: all GPU work is enqueued on the context's stream. Calls with host
+ *     pointers, lqcd_solve* and lqcd_set_* return after that stream is
+ *     synchronised; lqcd_apply_native and device-pointer lqcd_apply return
+ *     without synchronising.
+ *   - Threads: a context is used by one host thread at a time.
+ */
+#ifndef LQCD_H
+#define LQCD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lqcd_ctx lqcd_ctx;
+
+enum lqcd_status {
+  LQCD_OK = 0,
+  LQCD_EINVAL = -1,     /* bad argument: dims, null pointer, NaN/Inf input, unknown op */
+  LQCD_ENOMEM = -2,     /* device allocation failed */
+  LQCD_EHIP = -3,       /* a HIP runtime call failed */
+  LQCD_ESTATE = -4,     /* call out of order (e.g. apply before set_gauge) */
+  LQCD_ENOCONV = -5,    /* solver hit max_iter / max_outer; stats are filled */
+  LQCD_EBREAKDOWN = -6, /* BiCGStab breakdown persisted after restarts */
+  LQCD_ENOTSU3 = -7,    /* a link is not special unitary to 1e-12 */
+  LQCD_ESINGULAR = -8   /* a clover block is singular */
+};
+
+enum lqcd_prec { LQCD_F64 = 0, LQCD_F32 = 1, LQCD_F16 = 2 };
+
+enum lqcd_op {
+  LQCD_D = 0,            /* full operator D */
+  LQCD_DEE = 1,          /* D_ee = P_e A P_e */
+  LQCD_DOO = 2,          /* D_oo = P_o A P_o */
+  LQCD_DEO = 3,          /* D_eo = -kappa P_e H P_o */
+  LQCD_DOE = 4,          /* D_oe = -kappa P_o H P_e */
+  LQCD_DPREC_PAPER = 5,  /* Eq. (1): D^(eo) = 1 - D_ee^-1 D_eo D_oo^-1 D_oe on even sites */
+  LQCD_DPREC_SCHUR = 6,  /* S = D_ee - D_eo D_oo^-1 D_oe on even sites */
+  LQCD_DEE_INV = 7,      /* D_ee^-1 */
+  LQCD_DOO_INV = 8,      /* D_oo^-1 */
+  LQCD_HOP_EO = 9,       /* P_e H P_o (the bare hopping term, "Dslash", no -kappa) */
+  LQCD_HOP_OE = 10       /* P_o H P_e */
+};
+
+/* Create a context for an Lx x Ly x Lz x Lt lattice (dims = {Lx, Ly, Lz, Lt},
+ * every extent even and >= 2; up to 2^31 sites per parity). t_bc = -1
+ * (antiperiodic in t) or +1 (periodic). hip_stream: a hipStream_t to enqueue
+ * on, or NULL for a stream the context creates and owns. On success *out owns
+ * all device state; release it with lqcd_destroy. EINVAL on bad dims or t_bc. */
+int lqcd_create(const int dims[4], int t_bc, void* hip_stream, lqcd_ctx** out);
+
+/* Free every device buffer of the context (NULL is accepted). */
+int lqcd_destroy(lqcd_ctx* ctx);
+
+/* Load the gauge field (canonical layout, 36 complex = 72 doubles per site). Every link is
+ * checked to be SU(3) (max |U U^dag - 1| and |det U - 1| below 1e-12) and
+ * finite; otherwise ENOTSU3 or EINVAL and the context has no gauge field
+ * (later calls return ESTATE until a valid field is set). Stored as
+ * rows 0 and 1 of each link (row 2 = conj(row0 x row1) is rebuilt in
+ * registers) in FP64, FP32 and FP16. Invalidates the clover term: call
+ * lqcd_set_clover next. */
+int lqcd_set_gauge(lqcd_ctx* ctx, const double* U, int on_device);
+
+/* Set kappa and c_SW and build the site matrices A from the stored gauge field
+ * (c_SW = 0 gives the Wilson operator, A = 1, and nothing is built). Builds
+ * A and A^-1 on both parities in FP64, FP32 and FP16 as two 6x6 Hermitian
+ * blocks per site (A commutes with gamma5). ESTATE before set_gauge; ESINGULAR if a
+ * block cannot be inverted; EINVAL for non-finite kappa or c_SW. */
+int lqcd_set_clover(lqcd_ctx* ctx, double kappa, double csw);
+
+/* out = op(in) on canonical full-lattice spinors (12 complex per site) in
+ * precision prec (LQCD_F64/F32/F16: the precision of the stored fields and of
+ * the arithmetic; FP16 uses FP16 storage with FP32 arithmetic). in and out must
+ * not overlap. */
+int lqcd_apply(lqcd_ctx* ctx, int op, int prec, const double* in, double* out, int on_device);
+
+typedef struct {
+  double tol;           /* stop when ||b - D x|| <= tol ||b|| (full FP64 D); default 1e-10 */
+  int max_iter;         /* cap on inner BiCGStab iterations over the whole solve */
+  int max_outer;        /* cap on outer (defect-correction) iterations */
+  int inner_prec;       /* LQCD_F64: plain FP64 BiCGStab; F32/F16: mixed precision */
+  double inner_tol;     /* relative tolerance of each inner solve (mixed only) */
+  int check_every;      /* iterations between host convergence checks (>= 1) */
+  int use_graph;        /* 1: replay check_every iterations from a captured hipGraph */
+  const double* x0;     /* optional initial guess (canonical, same residency as b) */
+  int on_device;        /* 1: b, x and x0 are device pointers; 0: host pointers */
+} lqcd_solve_params;
+
+typedef struct {
+  int outer_iters;      /* defect-correction passes (1 for plain FP64) */
+  int inner_iters;      /* BiCGStab iterations, summed over passes */
+  int restarts;         /* BiCGStab restarts (true-residual or breakdown) */
+  double true_rel_resid;/* ||b - D x|| / ||b||, full operator, FP64, on return */
+  double seconds_solve; /* wall time from entry to return */
+  double seconds_setup; /* part of it spent on source preparation and reconstruction */
+} lqcd_solve_stats;
+
+/* Fill *p with the defaults (tol 1e-10, max_iter 100000, max_outer 100,
+ * inner_prec LQCD_F64, inner_tol 1e-6 for F32 / 1e-3 for F16 when 0,
+ * check_every 8, use_graph 1, x0 NULL, on_device 0). */
+void lqcd_default_params(lqcd_solve_params* p);
+
+/* Solve D x = b (canonical full-lattice vectors) by even-odd preconditioning:
+ * b_e' = b_e - D_eo D_oo^-1 b_o, S x_e = b_e' by BiCGStab (FP64, or FP32/FP16
+ * inner iterations inside an FP64 defect-correction loop), then
+ * x_o = D_oo^-1 (b_o - D_oe x_e). Returns after the stream is synchronised.
+ * ENOCONV if the caps are hit (x holds the last iterate, stats are filled). */
+int lqcd_solve(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_params* prm,
+               lqcd_solve_stats* stats);
+
+/* Batched solve: for each lattice k < nlattices, nrhs[k] right-hand sides
+ * b[k] (nrhs[k] canonical vectors back to back) on context ctxs[k]; solutions
+ * to x[k]. All contexts must share one stream. Each RHS runs its own
+ * BiCGStab (own alpha, beta, omega; not block Krylov) but every operator step
+ * of every unconverged RHS of every lattice is one persistent kernel launch that
+ * loads each link once per site for all RHS of that lattice. Converged RHS are
+ * masked out. stats has one entry per RHS, lattice-major. */
+int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const* b,
+                     double* const* x, int nlattices, const lqcd_solve_params* prm,
+                     lqcd_solve_stats* stats);
+
+/* Native fast path (benchmarks, solvers in the caller): half-lattice fields of
+ * one parity in the library's internal layout on the device. */
+size_t lqcd_field_bytes(lqcd_ctx* ctx, int prec);
+/* canonical full-lattice device vector -> native half field of the given parity */
+int lqcd_import(lqcd_ctx* ctx, int prec, int parity, const double* canon, void* native);
+/* native half field of the given parity -> parity sites of a canonical device
+ * vector (the other parity's sites are left untouched) */
+int lqcd_export(lqcd_ctx* ctx, int prec, int parity, const void* native, double* canon);
+/* out = op(in) on native half fields, enqueued without synchronising. op is one
+ * of LQCD_DEO, LQCD_DOE, LQCD_HOP_EO, LQCD_HOP_OE (one hop), LQCD_DEE, LQCD_DOO,
+ * LQCD_DEE_INV, LQCD_DOO_INV (site terms) or LQCD_DPREC_SCHUR (even -> even). */
+int lqcd_apply_native(lqcd_ctx* ctx, int op, int prec, const void* in, void* out);
+
+/* Autotune the launch shape of the hop for (op, prec) on this lattice: times
+ * each candidate workgroup size and block-to-XCD mapping on native scratch
+ * fields and keeps the fastest in the context. If path is not NULL the choice
+ * is merged into that JSON cache file and read back from it by later contexts
+ * of the same lattice and precision. */
+int lqcd_autotune(lqcd_ctx* ctx, int prec, const char* path);
+
+/* Name of a status code; detail of the last error on this thread. */
+const char* lqcd_strerror(int status);
+const char* lqcd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQCD_H */

@@ -1,0 +1,381 @@
+// The C ABI (include/lqcd.h): context life cycle, field set-up, operator
+// application through the canonical layout, and the solve entry points.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "blas.h"
+#include "internal.h"
+#include "ops.h"
+#include "solver.h"
+#include "tune.h"
+
+namespace lq {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+static int dalloc(void** p, size_t bytes) {
+  if (*p) return LQCD_OK;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return set_error(LQCD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return LQCD_OK;
+}
+
+static void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+static size_t full_sites(const lqcd_ctx* c) { return (size_t)c->g.vh * 2; }
+
+static int ensure_apply_buffers(lqcd_ctx* c, int prec) {
+  LQ_TRY(dalloc(&c->canon_a, full_sites(c) * 192));
+  LQ_TRY(dalloc(&c->canon_b, full_sites(c) * 192));
+  const size_t b = spinor_bytes(prec, c->g.vh);
+  LQ_TRY(dalloc(&c->half_a[prec], b));
+  LQ_TRY(dalloc(&c->half_b[prec], b));
+  LQ_TRY(dalloc(&c->half_c[prec], b));
+  LQ_TRY(dalloc(&c->half_d[prec], b));
+  return LQCD_OK;
+}
+
+static void invalidate_graphs(lqcd_ctx* c) {
+  if (!c->ws) return;
+  for (auto& iv : c->ws->inner) {
+    if (iv.exec) (void)hipGraphExecDestroy(iv.exec);
+    if (iv.graph) (void)hipGraphDestroy(iv.graph);
+    iv.exec = nullptr;
+    iv.graph = nullptr;
+    iv.graph_k = 0;
+  }
+}
+
+// Copy a canonical vector (n doubles) to device staging if it lives on the host.
+static int stage_in(lqcd_ctx* c, const double* src, int on_device, void* staging, size_t bytes, const double** dev) {
+  if (on_device) {
+    *dev = src;
+    return LQCD_OK;
+  }
+  LQ_HIP(hipMemcpyAsync(staging, src, bytes, hipMemcpyHostToDevice, c->stream));
+  *dev = reinterpret_cast<const double*>(staging);
+  return LQCD_OK;
+}
+
+static int check_finite(lqcd_ctx* c, const double* p, size_t n) {
+  unsigned long long* flag = reinterpret_cast<unsigned long long*>(c->dscal) + 4;
+  LQ_HIP(hipMemsetAsync(flag, 0, sizeof(unsigned long long), c->stream));
+  LQ_TRY(launch_check_finite(c, p, n, reinterpret_cast<double*>(flag)));
+  unsigned long long h = 0;
+  LQ_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  if (h) return set_error(LQCD_EINVAL, "input holds NaN or Inf");
+  return LQCD_OK;
+}
+
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" {
+
+const char* lqcd_strerror(int s) {
+  switch (s) {
+    case LQCD_OK: return "ok";
+    case LQCD_EINVAL: return "invalid argument";
+    case LQCD_ENOMEM: return "out of device memory";
+    case LQCD_EHIP: return "HIP runtime error";
+    case LQCD_ESTATE: return "call out of order";
+    case LQCD_ENOCONV: return "solver did not converge";
+    case LQCD_EBREAKDOWN: return "solver breakdown";
+    case LQCD_ENOTSU3: return "gauge link is not SU(3)";
+    case LQCD_ESINGULAR: return "singular clover block";
+  }
+  return "unknown status";
+}
+
+const char* lqcd_last_error(void) { return g_last_error.c_str(); }
+
+void lqcd_default_params(lqcd_solve_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tol = 1e-10;
+  p->max_iter = 100000;
+  p->max_outer = 100;
+  p->inner_prec = LQCD_F64;
+  p->inner_tol = 0.0;
+  p->check_every = 8;
+  p->use_graph = 1;
+  p->x0 = nullptr;
+  p->on_device = 0;
+}
+
+int lqcd_create(const int dims[4], int t_bc, void* hip_stream, lqcd_ctx** out) {
+  if (!dims || !out) return set_error(LQCD_EINVAL, "null argument");
+  *out = nullptr;
+  size_t v = 1;
+  for (int k = 0; k < 4; ++k) {
+    if (dims[k] < 2 || dims[k] % 2 != 0)
+      return set_error(LQCD_EINVAL, "every lattice extent must be even and >= 2");
+    v *= (size_t)dims[k];
+  }
+  if (v / 2 >= (size_t)1 << 31) return set_error(LQCD_EINVAL, "lattice too large (2^31 sites per parity max)");
+  if (t_bc != 1 && t_bc != -1) return set_error(LQCD_EINVAL, "t_bc must be +1 or -1");
+  lqcd_ctx* c = new lqcd_ctx();
+  c->g.lx = dims[0];
+  c->g.ly = dims[1];
+  c->g.lz = dims[2];
+  c->g.lt = dims[3];
+  c->g.lxh = dims[0] / 2;
+  c->g.vh = (int)(v / 2);
+  c->g.t_bc = t_bc;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return set_error(LQCD_EHIP, "no HIP device");
+  }
+  if (hip_stream) {
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return set_error(LQCD_EHIP, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  int s = LQCD_OK;
+  for (int p = 0; p < 3 && s == LQCD_OK; ++p) s = dalloc(&c->gauge[p], 8 * link_bytes(p, c->g.vh));
+  if (s == LQCD_OK) s = dalloc(reinterpret_cast<void**>(&c->dscal), 64 * sizeof(double));
+  if (s == LQCD_OK && hipHostMalloc(reinterpret_cast<void**>(&c->hscal), 64 * sizeof(double)) != hipSuccess)
+    s = set_error(LQCD_ENOMEM, "hipHostMalloc failed");
+  if (s == LQCD_OK) s = tune_load_defaults(c);
+  if (s != LQCD_OK) {
+    lqcd_destroy(c);
+    return s;
+  }
+  *out = c;
+  return LQCD_OK;
+}
+
+int lqcd_destroy(lqcd_ctx* c) {
+  if (!c) return LQCD_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->ws) {
+    c->ws->release();
+    delete c->ws;
+  }
+  for (int p = 0; p < 3; ++p) {
+    dfree(c->gauge[p]);
+    for (int s = 0; s < 4; ++s) dfree(c->clov[p][s]);
+    dfree(c->half_a[p]);
+    dfree(c->half_b[p]);
+    dfree(c->half_c[p]);
+    dfree(c->half_d[p]);
+  }
+  dfree(c->canon_a);
+  dfree(c->canon_b);
+  void* d = c->dscal;
+  dfree(d);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return LQCD_OK;
+}
+
+int lqcd_set_gauge(lqcd_ctx* c, const double* U, int on_device) {
+  if (!c || !U) return set_error(LQCD_EINVAL, "null argument");
+  c->have_gauge = false;
+  c->have_clover = false;
+  invalidate_graphs(c);
+  const size_t bytes = full_sites(c) * 72 * sizeof(double);  // 4 links x 9 complex per site
+  void* staging = nullptr;
+  const double* dev = U;
+  if (!on_device) {
+    LQ_TRY(dalloc(&staging, bytes));
+    if (hipMemcpyAsync(staging, U, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+      dfree(staging);
+      return set_error(LQCD_EHIP, "gauge upload failed");
+    }
+    dev = reinterpret_cast<const double*>(staging);
+  }
+  int s = check_finite(c, dev, full_sites(c) * 72);
+  if (s == LQCD_OK) {
+    double* chk = c->dscal;
+    if (hipMemsetAsync(chk, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess)
+      s = set_error(LQCD_EHIP, "memset failed");
+    if (s == LQCD_OK) s = launch_import_gauge(c, dev, chk);
+    unsigned long long h[2] = {0, 0};
+    if (s == LQCD_OK && hipMemcpyAsync(h, chk, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      s = set_error(LQCD_EHIP, "readback failed");
+    if (s == LQCD_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = set_error(LQCD_EHIP, "sync failed");
+    if (s == LQCD_OK) {
+      double err;
+      std::memcpy(&err, &h[0], sizeof(err));
+      if (h[1]) s = set_error(LQCD_EINVAL, "gauge field holds NaN or Inf");
+      else if (!(err <= 1e-12))
+        s = set_error(LQCD_ENOTSU3, "a link is not SU(3): max deviation " + std::to_string(err));
+    }
+  }
+  if (staging) {
+    (void)hipStreamSynchronize(c->stream);
+    dfree(staging);
+  }
+  if (s == LQCD_OK) c->have_gauge = true;
+  return s;
+}
+
+int lqcd_set_clover(lqcd_ctx* c, double kappa, double csw) {
+  if (!c) return set_error(LQCD_EINVAL, "null argument");
+  if (!std::isfinite(kappa) || !std::isfinite(csw)) return set_error(LQCD_EINVAL, "kappa and c_SW must be finite");
+  if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
+  invalidate_graphs(c);
+  c->have_clover = false;
+  c->kappa = kappa;
+  c->csw = csw;
+  c->is_wilson = (csw == 0.0 || kappa == 0.0);
+  if (!c->is_wilson) {
+    for (int p = 0; p < 3; ++p)
+      for (int s = 0; s < 4; ++s) LQ_TRY(dalloc(&c->clov[p][s], clover_bytes(p, c->g.vh)));
+    LQ_TRY(build_clover(c, kappa, csw));
+  }
+  c->have_clover = true;
+  return LQCD_OK;
+}
+
+static int apply_halves(lqcd_ctx* c, int op, int prec, void* in_e, void* in_o, void* out_e, void* out_o,
+                        bool* write_e, bool* write_o) {
+  const double k = c->kappa;
+  *write_e = *write_o = true;
+  switch (op) {
+    case LQCD_D: return op_full(c, prec, in_e, in_o, out_e, out_o);
+    case LQCD_DEE: *write_o = false; return launch_site(c, prec, clover_slot(c, prec, 0), in_e, out_e);
+    case LQCD_DOO: *write_e = false; return launch_site(c, prec, clover_slot(c, prec, 1), in_o, out_o);
+    case LQCD_DEE_INV: *write_o = false; return launch_site(c, prec, clover_slot(c, prec, 2), in_e, out_e);
+    case LQCD_DOO_INV: *write_e = false; return launch_site(c, prec, clover_slot(c, prec, 3), in_o, out_o);
+    case LQCD_DEO: *write_o = false; return op_hop(c, prec, 0, in_o, out_e, -k);
+    case LQCD_DOE: *write_e = false; return op_hop(c, prec, 1, in_e, out_o, -k);
+    case LQCD_HOP_EO: *write_o = false; return op_hop(c, prec, 0, in_o, out_e, 1.0);
+    case LQCD_HOP_OE: *write_e = false; return op_hop(c, prec, 1, in_e, out_o, 1.0);
+    case LQCD_DPREC_SCHUR:
+      *write_o = false;
+      return op_schur(c, prec, in_e, out_e, out_o, RED_NONE, nullptr, nullptr, nullptr, nullptr);
+    case LQCD_DPREC_PAPER:
+      // D^(eo) = A_ee^-1 S; S into in_o's buffer (free once the input's odd part is unused)
+      *write_o = false;
+      LQ_TRY(op_schur(c, prec, in_e, in_o, out_o, RED_NONE, nullptr, nullptr, nullptr, nullptr));
+      return launch_site(c, prec, clover_slot(c, prec, 2), in_o, out_e);
+  }
+  return set_error(LQCD_EINVAL, "unknown operator");
+}
+
+int lqcd_apply(lqcd_ctx* c, int op, int prec, const double* in, double* out, int on_device) {
+  if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  if (op < LQCD_D || op > LQCD_HOP_OE) return set_error(LQCD_EINVAL, "unknown operator");
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  LQ_TRY(ensure_apply_buffers(c, prec));
+  const size_t bytes = full_sites(c) * 192;
+  const double* din = nullptr;
+  LQ_TRY(stage_in(c, in, on_device, c->canon_a, bytes, &din));
+  double* dout = on_device ? out : reinterpret_cast<double*>(c->canon_b);
+  void *ie = c->half_a[prec], *io = c->half_b[prec], *oe = c->half_c[prec], *oo = c->half_d[prec];
+  LQ_TRY(launch_import_spinor(c, prec, 0, din, ie));
+  LQ_TRY(launch_import_spinor(c, prec, 1, din, io));
+  bool we = true, wo = true;
+  LQ_TRY(apply_halves(c, op, prec, ie, io, oe, oo, &we, &wo));
+  if (we) LQ_TRY(launch_export_spinor(c, prec, 0, oe, dout));
+  else LQ_TRY(launch_zero_parity(c, 0, dout));
+  if (wo) LQ_TRY(launch_export_spinor(c, prec, 1, oo, dout));
+  else LQ_TRY(launch_zero_parity(c, 1, dout));
+  if (!on_device) {
+    LQ_HIP(hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, c->stream));
+    LQ_HIP(hipStreamSynchronize(c->stream));
+  }
+  return LQCD_OK;
+}
+
+static int validate_params(const lqcd_solve_params* p) {
+  if (!p) return LQCD_OK;
+  if (!(p->tol > 0) || p->inner_prec < 0 || p->inner_prec > 2 || p->max_iter < 1 || p->max_outer < 1 ||
+      p->inner_tol < 0 || !(p->inner_tol < 1))
+    return set_error(LQCD_EINVAL, "bad solver parameters");
+  return LQCD_OK;
+}
+
+int lqcd_solve(lqcd_ctx* c, const double* b, double* x, const lqcd_solve_params* prm_in, lqcd_solve_stats* stats) {
+  if (!c || !b || !x) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_params(prm_in));
+  lqcd_solve_params prm;
+  if (prm_in) prm = *prm_in;
+  else lqcd_default_params(&prm);
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  LQ_TRY(ensure_apply_buffers(c, 0));
+  LQ_TRY(ensure_workspace(c, prm.inner_prec));
+  Workspace* w = c->ws;
+  const size_t bytes = full_sites(c) * 192;
+  const double* db = nullptr;
+  LQ_TRY(stage_in(c, b, prm.on_device, c->canon_a, bytes, &db));
+  LQ_TRY(check_finite(c, db, full_sites(c) * 24));
+  LQ_TRY(launch_import_spinor(c, 0, 0, db, w->b_e));
+  LQ_TRY(launch_import_spinor(c, 0, 1, db, w->b_o));
+  if (prm.x0) {
+    const double* dx0 = nullptr;
+    LQ_TRY(stage_in(c, prm.x0, prm.on_device, c->canon_b, bytes, &dx0));
+    LQ_TRY(launch_import_spinor(c, 0, 0, dx0, w->x_e));
+  } else {
+    LQ_TRY(blas_zero(c, 0, w->x_e));
+  }
+  lqcd_solve_stats st{};
+  const int status = solve_native(c, prm, st);
+  if (status != LQCD_OK && status != LQCD_ENOCONV && status != LQCD_EBREAKDOWN) return status;
+  double* dx = prm.on_device ? x : reinterpret_cast<double*>(c->canon_b);
+  LQ_TRY(launch_export_spinor(c, 0, 0, w->x_e, dx));
+  LQ_TRY(launch_export_spinor(c, 0, 1, w->x_o, dx));
+  if (!prm.on_device) LQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  if (stats) *stats = st;
+  return status;
+}
+
+size_t lqcd_field_bytes(lqcd_ctx* c, int prec) {
+  if (!c || prec < 0 || prec > 2) return 0;
+  return spinor_bytes(prec, c->g.vh);
+}
+
+int lqcd_import(lqcd_ctx* c, int prec, int parity, const double* canon, void* native) {
+  if (!c || !canon || !native) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2 || (parity != 0 && parity != 1)) return set_error(LQCD_EINVAL, "bad precision or parity");
+  return launch_import_spinor(c, prec, parity, canon, native);
+}
+
+int lqcd_export(lqcd_ctx* c, int prec, int parity, const void* native, double* canon) {
+  if (!c || !canon || !native) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2 || (parity != 0 && parity != 1)) return set_error(LQCD_EINVAL, "bad precision or parity");
+  return launch_export_spinor(c, prec, parity, native, canon);
+}
+
+int lqcd_apply_native(lqcd_ctx* c, int op, int prec, const void* in, void* out) {
+  if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  if (in == out) return set_error(LQCD_EINVAL, "in and out must differ");
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  void* tmp = nullptr;
+  if (op == LQCD_DPREC_SCHUR) {
+    LQ_TRY(dalloc(&c->half_d[prec], spinor_bytes(prec, c->g.vh)));
+    tmp = c->half_d[prec];
+  }
+  return op_native(c, op, prec, in, out, tmp);
+}
+
+int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const* b, double* const* x,
+                     int nlattices, const lqcd_solve_params* prm, lqcd_solve_stats* stats);
+
+}  // extern "C"

@@ -1,0 +1,263 @@
+// Device-side loads and stores of the native field layouts (see internal.h),
+// one specialisation per storage precision: 0 = FP64, 1 = FP32, 2 = FP16.
+// FP64 fields compute in double, FP32 and FP16 fields in float.
+#pragma once
+
+#include "internal.h"
+
+namespace lq {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+struct IO;
+
+// ------------------------------------------------------------------ FP64
+template <>
+struct IO<0> {
+  using T = double;
+  __device__ static inline void load_spinor(const void* f, size_t vh, size_t i, cx<T> s[12]) {
+    const double2* b = reinterpret_cast<const double2*>(f);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      double2 v = b[k * vh + i];
+      s[k] = {v.x, v.y};
+    }
+  }
+  // spins 0,1 (upper = true) or spins 2,3 into s[0..5]
+  __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
+    const double2* b = reinterpret_cast<const double2*>(f) + (upper ? 0 : 6 * vh);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double2 v = b[k * vh + i];
+      s[k] = {v.x, v.y};
+    }
+  }
+  __device__ static inline void store_spinor(void* f, size_t vh, size_t i, const cx<T> s[12]) {
+    double2* b = reinterpret_cast<double2*>(f);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) b[k * vh + i] = make_double2(s[k].r, s[k].i);
+  }
+  __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
+    const double2* b = reinterpret_cast<const double2*>(g);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double2 v = b[k * vh + i];
+      u[k] = {v.x, v.y};
+    }
+  }
+  // 18 complex slots of one chiral block (blk = 0: +, 1: -)
+  __device__ static inline void load_clover_block(const void* c, size_t vh, size_t i, int blk, cx<T> m[18]) {
+    const double2* b = reinterpret_cast<const double2*>(c) + (size_t)blk * 18 * vh;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+      double2 v = b[k * vh + i];
+      m[k] = {v.x, v.y};
+    }
+  }
+};
+
+// ------------------------------------------------------------------ FP32
+template <>
+struct IO<1> {
+  using T = float;
+  __device__ static inline void load_spinor(const void* f, size_t vh, size_t i, cx<T> s[12]) {
+    const float4* b = reinterpret_cast<const float4*>(f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float4 v = b[k * vh + i];
+      s[2 * k] = {v.x, v.y};
+      s[2 * k + 1] = {v.z, v.w};
+    }
+  }
+  __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
+    const float4* b = reinterpret_cast<const float4*>(f) + (upper ? 0 : 3 * vh);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float4 v = b[k * vh + i];
+      s[2 * k] = {v.x, v.y};
+      s[2 * k + 1] = {v.z, v.w};
+    }
+  }
+  __device__ static inline void store_spinor(void* f, size_t vh, size_t i, const cx<T> s[12]) {
+    float4* b = reinterpret_cast<float4*>(f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      b[k * vh + i] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
+  }
+  __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
+    const float4* b = reinterpret_cast<const float4*>(g);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float4 v = b[k * vh + i];
+      u[2 * k] = {v.x, v.y};
+      u[2 * k + 1] = {v.z, v.w};
+    }
+  }
+  __device__ static inline void load_clover_block(const void* c, size_t vh, size_t i, int blk, cx<T> m[18]) {
+    const float4* b = reinterpret_cast<const float4*>(c) + (size_t)blk * 9 * vh;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float4 v = b[k * vh + i];
+      m[2 * k] = {v.x, v.y};
+      m[2 * k + 1] = {v.z, v.w};
+    }
+  }
+};
+
+// ------------------------------------------------------------------ FP16
+template <>
+struct IO<2> {
+  using T = float;
+  __device__ static inline const float* norms(const void* f, size_t vh) {
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(f) + 48 * vh);
+  }
+  __device__ static inline void load_spinor(const void* f, size_t vh, size_t i, cx<T> s[12]) {
+    const half8* b = reinterpret_cast<const half8*>(f);
+    const float n = norms(f, vh)[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      half8 v = b[k * vh + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[4 * k + j] = {n * (float)v[2 * j], n * (float)v[2 * j + 1]};
+    }
+  }
+  __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
+    cx<T> all[12];
+    load_spinor(f, vh, i, all);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = all[(upper ? 0 : 6) + k];
+  }
+  __device__ static inline void store_spinor(void* f, size_t vh, size_t i, const cx<T> s[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].r), fabsf(s[k].i)));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    half8* b = reinterpret_cast<half8*>(f);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      half8 v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[2 * j] = (_Float16)(s[4 * k + j].r * inv);
+        v[2 * j + 1] = (_Float16)(s[4 * k + j].i * inv);
+      }
+      b[k * vh + i] = v;
+    }
+    reinterpret_cast<float*>(reinterpret_cast<char*>(f) + 48 * vh)[i] = m;
+  }
+  __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
+    const half4* b = reinterpret_cast<const half4*>(g);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      half4 v = b[k * vh + i];
+      u[2 * k] = {(float)v[0], (float)v[1]};
+      u[2 * k + 1] = {(float)v[2], (float)v[3]};
+    }
+  }
+  // block + is complex 0..17 (planes 0..4), block - is complex 18..35 (planes 4..8)
+  __device__ static inline void load_clover_block(const void* c, size_t vh, size_t i, int blk, cx<T> m[18]) {
+    const half8* b = reinterpret_cast<const half8*>(c) + (size_t)(blk * 4) * vh;
+    cx<T> part[20];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      half8 v = b[k * vh + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[4 * k + j] = {(float)v[2 * j], (float)v[2 * j + 1]};
+    }
+    const int off = blk * 2;  // complex 18 is element 2 of plane 4
+#pragma unroll
+    for (int k = 0; k < 18; ++k) m[k] = part[k + off];
+  }
+};
+
+// Rebuild row 2 of an SU(3) matrix from rows 0, 1: row2 = conj(row0 x row1).
+template <typename T>
+__device__ inline void reconstruct(const cx<T> u[6], cx<T> r2[3]) {
+  r2[0] = conj(u[1] * u[5] - u[2] * u[4]);
+  r2[1] = conj(u[2] * u[3] - u[0] * u[5]);
+  r2[2] = conj(u[0] * u[4] - u[1] * u[3]);
+}
+
+// y = M x for a Hermitian 6x6 block in the 18-slot packed form.
+template <typename T>
+__device__ inline void herm6_mul(const cx<T> m[18], const cx<T> x[6], cx<T> y[6]) {
+  const T d[6] = {m[0].r, m[0].i, m[1].r, m[1].i, m[2].r, m[2].i};
+#pragma unroll
+  for (int a = 0; a < 6; ++a) y[a] = d[a] * x[a];
+  int k = 3;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+#pragma unroll
+    for (int b = a + 1; b < 6; ++b) {
+      const cx<T> c = m[k++];
+      y[a] = y[a] + c * x[b];
+      y[b] = y[b] + cmulc(c, x[a]);
+    }
+  }
+}
+
+// out = A psi with A given by its two chiral blocks (1/2 of the basis change folded in).
+template <int P>
+__device__ inline void clover_apply(const void* clov, size_t vh, size_t i, const cx<typename IO<P>::T> in[12],
+                                    cx<typename IO<P>::T> out[12]) {
+  using T = typename IO<P>::T;
+  cx<T> chp[6], chm[6], yp[6], ym[6], m[18];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    chp[k] = in[k] - in[k + 6];
+    chm[k] = in[k] + in[k + 6];
+  }
+  IO<P>::load_clover_block(clov, vh, i, 0, m);
+  herm6_mul(m, chp, yp);
+  IO<P>::load_clover_block(clov, vh, i, 1, m);
+  herm6_mul(m, chm, ym);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    out[k] = yp[k] + ym[k];
+    out[k + 6] = ym[k] - yp[k];
+  }
+}
+
+// blockIdx -> logical block: with remap on, each of the 8 XCDs (which receive
+// blocks round-robin) gets one contiguous range of logical blocks, so that
+// neighbouring sites share that XCD's L2.
+__device__ inline int logical_block(int remap) {
+  const int b = blockIdx.x;
+  if (!remap) return b;
+  const int nb = gridDim.x;
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+// Deterministic block reduction of N doubles: wavefront butterfly, then the
+// waves' partials summed in wave order by thread 0. Result written to out[0..N).
+template <int N>
+__device__ inline void block_reduce(double v[N], double* out) {
+  __shared__ double red[16][N > 0 ? N : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    v[k] = x;
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[wave][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[w][k];
+      out[k] = s;
+    }
+  }
+}
+
+}  // namespace lq

@@ -1,0 +1,173 @@
+// Launch-shape autotuner for the hop kernel, with a small JSON cache file.
+//
+// The paper measures the operator over several SIMD tile shapes and finds
+// little difference (Sec. 3); on gfx950 the equivalent knobs are the workgroup
+// size and whether blocks are mapped so that each XCD works on one contiguous
+// slab of the lattice (its own L2). The tuner times each candidate with HIP
+// events on scratch fields and keeps the fastest per (lattice, precision).
+//
+// Cache format: one JSON object, keys "Lx.Ly.Lz.Lt:prec", values
+// {"block": B, "remap": R, "us": T}. The path comes from lqcd_autotune's
+// argument or from the LQCD_TUNE_CACHE environment variable.
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+
+#include "internal.h"
+#include "ops.h"
+#include "tune.h"
+
+namespace lq {
+
+namespace {
+
+std::string key_of(const lqcd_ctx* c, int prec) {
+  std::ostringstream o;
+  o << c->g.lx << "." << c->g.ly << "." << c->g.lz << "." << c->g.lt << ":" << prec;
+  return o.str();
+}
+
+struct Entry {
+  int block = 256, remap = 1;
+  double us = 0;
+};
+
+// Minimal reader for the flat format written below.
+std::map<std::string, Entry> read_cache(const std::string& path) {
+  std::map<std::string, Entry> m;
+  std::ifstream f(path);
+  if (!f) return m;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    const size_t end = s.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = s.substr(pos + 1, end - pos - 1);
+    const size_t ob = s.find('{', end), cb = s.find('}', end);
+    if (ob == std::string::npos || cb == std::string::npos || key.find(':') == std::string::npos) {
+      pos = end + 1;
+      continue;
+    }
+    const std::string body = s.substr(ob, cb - ob);
+    Entry e;
+    auto num = [&](const char* name, double& out) {
+      const size_t k = body.find(std::string("\"") + name + "\"");
+      if (k == std::string::npos) return;
+      const size_t colon = body.find(':', k);
+      if (colon != std::string::npos) out = std::atof(body.c_str() + colon + 1);
+    };
+    double b = 256, r = 1, us = 0;
+    num("block", b);
+    num("remap", r);
+    num("us", us);
+    e.block = (int)b;
+    e.remap = (int)r;
+    e.us = us;
+    m[key] = e;
+    pos = cb + 1;
+  }
+  return m;
+}
+
+bool write_cache(const std::string& path, const std::map<std::string, Entry>& m) {
+  std::ofstream f(path);
+  if (!f) return false;
+  f << "{\n";
+  size_t n = 0;
+  for (const auto& kv : m) {
+    f << "  \"" << kv.first << "\": {\"block\": " << kv.second.block << ", \"remap\": " << kv.second.remap
+      << ", \"us\": " << kv.second.us << "}" << (++n < m.size() ? "," : "") << "\n";
+  }
+  f << "}\n";
+  return true;
+}
+
+bool valid(const Entry& e) { return (e.block == 64 || e.block == 128 || e.block == 192 || e.block == 256) && (e.remap == 0 || e.remap == 1); }
+
+}  // namespace
+
+int tune_load_defaults(lqcd_ctx* c) {
+  const char* env = std::getenv("LQCD_TUNE_CACHE");
+  if (!env || !*env) return LQCD_OK;
+  const auto m = read_cache(env);
+  for (int p = 0; p < 3; ++p) {
+    auto it = m.find(key_of(c, p));
+    if (it != m.end() && valid(it->second)) {
+      c->hop_block[p] = it->second.block;
+      c->hop_remap[p] = it->second.remap;
+    }
+  }
+  return LQCD_OK;
+}
+
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" int lqcd_autotune(lqcd_ctx* c, int prec, const char* path) {
+  if (!c) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  const size_t bytes = spinor_bytes(prec, c->g.vh);
+  void *in = nullptr, *out = nullptr;
+  if (hipMalloc(&in, bytes) != hipSuccess || hipMalloc(&out, bytes) != hipSuccess) {
+    if (in) (void)hipFree(in);
+    return set_error(LQCD_ENOMEM, "autotune scratch allocation failed");
+  }
+  (void)hipMemsetAsync(in, 0, bytes, c->stream);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int blocks[] = {64, 128, 192, 256};
+  Entry best;
+  best.us = 1e30;
+  const int save_b = c->hop_block[prec], save_r = c->hop_remap[prec];
+  int status = LQCD_OK;
+  for (int remap = 0; remap < 2 && status == LQCD_OK; ++remap)
+    for (int b : blocks) {
+      c->hop_block[prec] = b;
+      c->hop_remap[prec] = remap;
+      for (int w = 0; w < 3 && status == LQCD_OK; ++w) status = op_hop(c, prec, 0, in, out, 1.0);
+      (void)hipEventRecord(e0, c->stream);
+      const int reps = 20;
+      for (int r = 0; r < reps && status == LQCD_OK; ++r) status = op_hop(c, prec, r & 1, r & 1 ? out : in, r & 1 ? in : out, 1.0);
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      if (status != LQCD_OK) break;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1000.0 * ms / reps;
+      if (us < best.us) {
+        best.us = us;
+        best.block = b;
+        best.remap = remap;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(in);
+  (void)hipFree(out);
+  if (status != LQCD_OK) {
+    c->hop_block[prec] = save_b;
+    c->hop_remap[prec] = save_r;
+    return status;
+  }
+  c->hop_block[prec] = best.block;
+  c->hop_remap[prec] = best.remap;
+  std::string p = path ? path : "";
+  if (p.empty()) {
+    const char* env = std::getenv("LQCD_TUNE_CACHE");
+    if (env) p = env;
+  }
+  if (!p.empty()) {
+    auto m = read_cache(p);
+    m[key_of(c, prec)] = best;
+    if (!write_cache(p, m)) return set_error(LQCD_EINVAL, "cannot write tune cache " + p);
+  }
+  return LQCD_OK;
+}

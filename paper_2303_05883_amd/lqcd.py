@@ -1,0 +1,293 @@
+"""ctypes binding of liblqcd.so, the gfx950 Wilson/clover library (include/lqcd.h).
+
+Argument marshalling only: every step of the operator and the solvers runs in
+the library's HIP kernels. Arrays may be NumPy (host) or torch tensors on the
+GPU (device); complex128 with the canonical layouts:
+
+* spinor ``[Lt, Lz, Ly, Lx, 4, 3]``
+* gauge  ``[Lt, Lz, Ly, Lx, 4, 3, 3]``
+
+The library must have been built (``python -m paper_2303_05883_amd.build``);
+importing this module without it raises at once.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblqcd.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOCONV, EBREAKDOWN, ENOTSU3, ESINGULAR = 0, -1, -2, -3, -4, -5, -6, -7, -8
+F64, F32, F16 = 0, 1, 2
+(D, DEE, DOO, DEO, DOE, DPREC_PAPER, DPREC_SCHUR, DEE_INV, DOO_INV, HOP_EO, HOP_OE) = range(11)
+OPS = {"D": D, "DEE": DEE, "DOO": DOO, "DEO": DEO, "DOE": DOE, "DPREC_PAPER": DPREC_PAPER,
+       "DPREC_SCHUR": DPREC_SCHUR, "DEE_INV": DEE_INV, "DOO_INV": DOO_INV, "HOP_EO": HOP_EO, "HOP_OE": HOP_OE}
+
+EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply",
+            "lqcd_default_params", "lqcd_solve", "lqcd_solve_batch", "lqcd_field_bytes", "lqcd_import",
+            "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_strerror", "lqcd_last_error"]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("max_outer", C.c_int), ("inner_prec", C.c_int),
+                ("inner_tol", C.c_double), ("check_every", C.c_int), ("use_graph", C.c_int),
+                ("x0", C.c_void_p), ("on_device", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int), ("restarts", C.c_int),
+                ("true_rel_resid", C.c_double), ("seconds_solve", C.c_double), ("seconds_setup", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LqcdError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load the library (once). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2303_05883_amd.build`")
+    # torch ships its own HIP runtime under the same soname; loading torch first
+    # makes the library bind to that one, so that the process holds a single HIP
+    # runtime and torch's streams and allocations are valid in library calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    vp, ip, dp = C.c_void_p, C.c_int, C.c_double
+    lib.lqcd_create.argtypes = [C.POINTER(C.c_int), ip, vp, C.POINTER(vp)]
+    lib.lqcd_destroy.argtypes = [vp]
+    lib.lqcd_set_gauge.argtypes = [vp, vp, ip]
+    lib.lqcd_set_clover.argtypes = [vp, dp, dp]
+    lib.lqcd_apply.argtypes = [vp, ip, ip, vp, vp, ip]
+    lib.lqcd_default_params.argtypes = [C.POINTER(SolveParams)]
+    lib.lqcd_default_params.restype = None
+    lib.lqcd_solve.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
+    lib.lqcd_solve_batch.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), C.POINTER(vp), C.POINTER(vp), ip,
+                                     C.POINTER(SolveParams), C.POINTER(SolveStats)]
+    lib.lqcd_field_bytes.argtypes = [vp, ip]
+    lib.lqcd_field_bytes.restype = C.c_size_t
+    lib.lqcd_import.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_export.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_apply_native.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_autotune.argtypes = [vp, ip, C.c_char_p]
+    lib.lqcd_strerror.argtypes = [ip]
+    lib.lqcd_strerror.restype = C.c_char_p
+    lib.lqcd_last_error.argtypes = []
+    lib.lqcd_last_error.restype = C.c_char_p
+    for name in ("lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply", "lqcd_solve",
+                 "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune"):
+        getattr(lib, name).restype = ip
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str, allow=()):
+    if status != OK and status not in allow:
+        lib = load()
+        raise LqcdError(status, where, f"{lib.lqcd_strerror(status).decode()}: {lib.lqcd_last_error().decode()}")
+    return status
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """(pointer, on_device) of a contiguous complex128 array or tensor."""
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), 1 if a.is_cuda else 0
+    if not (isinstance(a, np.ndarray) and a.flags.c_contiguous):
+        raise ValueError("array must be a C-contiguous numpy array or torch tensor")
+    return a.ctypes.data, 0
+
+
+def default_params() -> SolveParams:
+    p = SolveParams()
+    load().lqcd_default_params(C.byref(p))
+    return p
+
+
+@dataclass
+class Stats:
+    outer_iters: int
+    inner_iters: int
+    restarts: int
+    true_rel_resid: float
+    seconds_solve: float
+    seconds_setup: float
+    status: int
+
+
+def _torch_cuda():
+    try:
+        import torch
+    except ImportError:
+        return None
+    return torch if torch.cuda.is_available() else None
+
+
+class Lattice:
+    """One lattice context: dims = (Lx, Ly, Lz, Lt), t_bc = -1 or +1.
+
+    With torch on a GPU the context runs on a torch stream of its own
+    (``self.stream``); every call orders it after torch's current stream on
+    entry and orders torch's current stream after it on exit, so tensors can
+    be passed freely. ``stream`` may instead give a hipStream_t handle.
+    """
+
+    def __init__(self, dims, t_bc: int = -1, stream=None):
+        lib = load()
+        self.dims = tuple(int(d) for d in dims)
+        arr = (C.c_int * 4)(*self.dims)
+        h = C.c_void_p()
+        self.stream = None
+        torch = _torch_cuda() if stream is None else None
+        if torch is not None:
+            self.stream = torch.cuda.Stream()
+            stream = self.stream.cuda_stream
+        s = C.c_void_p(int(stream)) if stream is not None else None
+        _check(lib.lqcd_create(arr, int(t_bc), s, C.byref(h)), "lqcd_create")
+        self.handle = h
+        self.lib = lib
+
+    def _enter(self):
+        if self.stream is not None:
+            import torch
+            self.stream.wait_stream(torch.cuda.current_stream())
+
+    def _exit(self):
+        if self.stream is not None:
+            import torch
+            torch.cuda.current_stream().wait_stream(self.stream)
+
+    def _call(self, fn, *args):
+        self._enter()
+        try:
+            return fn(*args)
+        finally:
+            self._exit()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lqcd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # set-up ----------------------------------------------------------------
+    def set_gauge(self, U):
+        p, dev = _ptr(U)
+        _check(self._call(self.lib.lqcd_set_gauge, self.handle, p, dev), "lqcd_set_gauge")
+
+    def set_clover(self, kappa: float, csw: float = 0.0):
+        _check(self._call(self.lib.lqcd_set_clover, self.handle, float(kappa), float(csw)), "lqcd_set_clover")
+
+    # operators -------------------------------------------------------------
+    def apply(self, op, prec, x, out):
+        op = OPS[op] if isinstance(op, str) else int(op)
+        pi, di = _ptr(x)
+        po, do = _ptr(out)
+        if di != do:
+            raise ValueError("in and out must both be host or both be device")
+        _check(self._call(self.lib.lqcd_apply, self.handle, op, int(prec), pi, po, di), "lqcd_apply")
+        return out
+
+    def field_bytes(self, prec: int) -> int:
+        return int(self.lib.lqcd_field_bytes(self.handle, int(prec)))
+
+    def import_field(self, prec, parity, canon, native):
+        _check(self._call(self.lib.lqcd_import, self.handle, int(prec), int(parity), _ptr(canon)[0],
+                          _ptr(native)[0]), "lqcd_import")
+
+    def export_field(self, prec, parity, native, canon):
+        _check(self._call(self.lib.lqcd_export, self.handle, int(prec), int(parity), _ptr(native)[0],
+                          _ptr(canon)[0]), "lqcd_export")
+
+    def apply_native(self, op, prec, native_in, native_out):
+        op = OPS[op] if isinstance(op, str) else int(op)
+        _check(self._call(self.lib.lqcd_apply_native, self.handle, op, int(prec), _ptr(native_in)[0],
+                          _ptr(native_out)[0]), "lqcd_apply_native")
+
+    def autotune(self, prec: int, path: str | None = None):
+        _check(self._call(self.lib.lqcd_autotune, self.handle, int(prec), path.encode() if path else None),
+               "lqcd_autotune")
+
+    # solver ----------------------------------------------------------------
+    def solve(self, b, x, tol=1e-10, inner_prec=F64, inner_tol=0.0, max_iter=100000, max_outer=100,
+              check_every=8, use_graph=True, x0=None, raise_on_fail=True) -> Stats:
+        prm = default_params()
+        pb, db = _ptr(b)
+        px, dx = _ptr(x)
+        if db != dx:
+            raise ValueError("b and x must both be host or both be device")
+        prm.tol, prm.inner_prec, prm.inner_tol = float(tol), int(inner_prec), float(inner_tol)
+        prm.max_iter, prm.max_outer, prm.check_every = int(max_iter), int(max_outer), int(check_every)
+        prm.use_graph, prm.on_device = int(bool(use_graph)), db
+        if x0 is not None:
+            prm.x0 = _ptr(x0)[0]
+        st = SolveStats()
+        status = self._call(self.lib.lqcd_solve, self.handle, pb, px, C.byref(prm), C.byref(st))
+        if raise_on_fail:
+            _check(status, "lqcd_solve")
+        return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
+                     st.seconds_setup, status)
+
+
+def solve_batch(lattices, bs, xs, tol=1e-10, inner_prec=F32, inner_tol=0.0, check_every=8, use_graph=True):
+    """Batched solve: bs[k] / xs[k] hold nrhs[k] canonical vectors of lattices[k] back to back
+    (arrays of shape [nrhs, Lt, Lz, Ly, Lx, 4, 3]); returns one Stats per RHS."""
+    lib = load()
+    n = len(lattices)
+    ctxs = (C.c_void_p * n)(*[lat.handle.value for lat in lattices])
+    nrhs = (C.c_int * n)(*[int(b.shape[0]) for b in bs])
+    pbs = [_ptr(b) for b in bs]
+    pxs = [_ptr(x) for x in xs]
+    devs = {d for _, d in pbs + pxs}
+    if len(devs) != 1:
+        raise ValueError("all b and x must be on the same side")
+    prm = default_params()
+    prm.tol, prm.inner_prec, prm.inner_tol = float(tol), int(inner_prec), float(inner_tol)
+    prm.check_every, prm.use_graph, prm.on_device = int(check_every), int(bool(use_graph)), devs.pop()
+    total = sum(int(b.shape[0]) for b in bs)
+    st = (SolveStats * total)()
+    for lat in lattices:
+        lat._enter()
+    try:
+        status = lib.lqcd_solve_batch(ctxs, nrhs, (C.c_void_p * n)(*[p for p, _ in pbs]),
+                                      (C.c_void_p * n)(*[p for p, _ in pxs]), n, C.byref(prm), st)
+    finally:
+        for lat in lattices:
+            lat._exit()
+    _check(status, "lqcd_solve_batch")
+    return [Stats(s.outer_iters, s.inner_iters, s.restarts, s.true_rel_resid, s.seconds_solve, s.seconds_setup,
+                  status) for s in st]
