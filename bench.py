@@ -75,14 +75,12 @@ def time_hop(torch, lat, prec, reps=40, nbuf=3):
     src = torch.from_numpy(fg.gaussian_spinor(lat.dims, 5)).cuda()
     for t in ins:
         lat.import_field(prec, 1, src, t)
-    for r in range(3):
-        lat.apply_native("HOP_EO", prec, ins[r % nbuf], outs[r % nbuf])
+    lat.apply_native_repeat("HOP_EO", prec, ins, outs, 3)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(lat.stream)
-    for r in range(reps):
-        lat.apply_native("HOP_EO", prec, ins[r % nbuf], outs[r % nbuf])
+    lat.apply_native_repeat("HOP_EO", prec, ins, outs, reps)
     e1.record(lat.stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -102,6 +100,39 @@ def copy_probe(torch, mib=1024):
     e1.synchronize()
     ms = e0.elapsed_time(e1)
     return 2 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x64.txt")
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hop.hip", "fieldio.h"):
+        with open(os.path.join(ROOT, "paper_2303_05883_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec_name):
+    """HBM bytes per launch of the Dslash kernel from the committed rocprofv3
+    counter summary (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy),
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    want = None
+    for ln in lines:
+        if ln.startswith("sources_sha256_16:"):
+            want = ln.split(":", 1)[1].strip()
+    if want != kernel_sources_hash():
+        return None
+    for ln in lines:
+        if ln.startswith(prec_name + ":"):
+            parts = ln.split()
+            return int(parts[parts.index("traffic_bytes") + 1])
+    return None
 
 
 def hop_applications(st, inner_prec):
@@ -135,6 +166,11 @@ def main():
     ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-vs-mixed solve comparison")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON launch-shape cache: read if present (no tuning sweep), written after tuning otherwise")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="set-up, autotune, the Dslash kernel timings and a copy of known size; no solves "
+                         "(the short program the hardware-counter profiles are taken on)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the lattice is not sharded across GPUs in this build "
@@ -151,16 +187,28 @@ def main():
     U, b = generate(DIMS, SEED)
     log(f"fields generated in {time.perf_counter() - t0:.1f} s")
     vh = int(np.prod(DIMS)) // 2
+    cached = bool(a.tune_cache) and os.path.exists(a.tune_cache)
+    if a.tune_cache:
+        os.environ["LQCD_TUNE_CACHE"] = os.path.abspath(a.tune_cache)
     lat = lqcd.Lattice(DIMS, -1)
     Ud = torch.from_numpy(U).cuda()
     bd = torch.from_numpy(b).cuda()
     lat.set_gauge(Ud)
     del Ud
     lat.set_clover(KAPPA, 0.0)
-    for p in (lqcd.F64, lqcd.F32, lqcd.F16):
-        lat.autotune(p)
-    log("autotuned")
+    if not cached:
+        for p in (lqcd.F64, lqcd.F32, lqcd.F16):
+            lat.autotune(p)
+        log("autotuned" + (f" (cache {a.tune_cache})" if a.tune_cache else ""))
+    else:
+        log(f"launch shapes from {a.tune_cache}")
     inner = lqcd.F32 if a.inner == "f32" else lqcd.F16
+    if a.kernels_only:
+        for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.F16, "f16")):
+            ms = time_hop(torch, lat, p, reps=10)
+            log(f"hop {name}: {1000 * ms:.2f} us, {HOP_BYTES[p] * vh / (ms * 1e-3) / 1e9:.1f} GB/s")
+        log(f"copy probe: {copy_probe(torch, mib=512):.1f} GB/s (512 MiB read + 512 MiB written per launch)")
+        return
     x = torch.zeros_like(bd)
     for _ in range(a.warmup):
         st = lat.solve(bd, x, inner_prec=inner)
@@ -194,7 +242,7 @@ def main():
     dom = "f32" if inner == lqcd.F32 else "f16"
     copy_gbs = copy_probe(torch)
     roofline = {"bound": "hbm", "achieved": hop[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hop[dom]["frac_hbm"], "traffic": None,
+                "frac": hop[dom]["frac_hbm"], "traffic": measured_traffic(dom),
                 "kernel": f"k_hop<{1 if dom == 'f32' else 2},EPI_SCALE> (Dslash, {dom} storage)",
                 "bytes_per_launch": HOP_BYTES[1 if dom == "f32" else 2] * vh,
                 "copy_gbs": round(copy_gbs, 1)}

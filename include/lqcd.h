@@ -181,6 +181,16 @@ int lqcd_apply_native(lqcd_ctx* ctx, int op, int prec, const void* in, void* out
  * of the same lattice and precision. */
 int lqcd_autotune(lqcd_ctx* ctx, int prec, const char* path);
 
+/* Fix the launch shape of the hop kernels for one precision (the knobs the
+ * autotuner searches): block = workgroup size (64, 128, 192 or 256 threads),
+ * split = lanes per output site (1, or 4 with one lattice direction per lane),
+ * xcd_map = 0 for blocks in site order, 1 to give each of the chip's 8 XCDs
+ * one contiguous range of sites, 2 to give each XCD one slab of Lz/8 z-planes
+ * walked z before t (needs Lz divisible by 8),
+ * nt = 1 to load the links non-temporally. EINVAL for any other value. The
+ * results do not depend on the shape beyond rounding of the fused reductions. */
+int lqcd_set_hop_shape(lqcd_ctx* ctx, int prec, int block, int split, int xcd_map, int nt);
+
 /* Name of a status code; detail of the last error on this thread. */
 const char* lqcd_strerror(int status);
 const char* lqcd_last_error(void);

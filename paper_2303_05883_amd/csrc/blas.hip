@@ -17,6 +17,7 @@ namespace lq {
 namespace {
 
 constexpr int BS = 256;
+constexpr int FBS = 1024;  // threads of the one-block finalize kernels
 
 __device__ inline bool is_done(const Scal* s) { return s && s->done; }
 
@@ -85,8 +86,8 @@ __global__ void __launch_bounds__(BS) k_xr_update(void* x, const void* p, const 
 #pragma unroll
     for (int k = 0; k < 12; ++k) sv[k] = sv[k] - omega * tv[k];
     IO<P>::store_spinor(r, vh, i, sv);
-    // reduce what was stored (the FP16 codes round the value)
-    IO<P>::load_spinor(r, vh, i, sv);
+    // FP16 codes round the stored value: reduce what was stored
+    if (P == 2) IO<P>::load_spinor(r, vh, i, sv);
     IO<P>::load_spinor(rhat, vh, i, tv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -194,16 +195,29 @@ __global__ void __launch_bounds__(BS) k_zero(void* dst, size_t vh) {
 // Sum n partial records of `width` doubles in a fixed order into out[0..width).
 template <int W>
 __device__ inline void sum_partials(const double* partials, int n, double out[W]) {
-  double v[W];
+  // four independent partial sums per thread keep four loads in flight; the
+  // order of additions is fixed by (n, blockDim), so the result is reproducible
+  double v[4][W];
 #pragma unroll
-  for (int k = 0; k < W; ++k) v[k] = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int k = 0; k < W; ++k) v[k] += partials[(size_t)j * W + k];
+    for (int k = 0; k < W; ++k) v[u][k] = 0.0;
+  const int step = blockDim.x;
+  int j = threadIdx.x;
+  for (; j + 3 * step < n; j += 4 * step)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < W; ++k) v[u][k] += partials[(size_t)(j + u * step) * W + k];
+  for (; j < n; j += step)
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[0][k] += partials[(size_t)j * W + k];
+#pragma unroll
+  for (int k = 0; k < W; ++k) v[0][k] = (v[0][k] + v[1][k]) + (v[2][k] + v[3][k]);
   __shared__ double res[W];
   double tmp[W];
 #pragma unroll
-  for (int k = 0; k < W; ++k) tmp[k] = v[k];
+  for (int k = 0; k < W; ++k) tmp[k] = v[0][k];
   block_reduce<W>(tmp, res);
   __syncthreads();
 #pragma unroll
@@ -217,7 +231,7 @@ __device__ inline void cdiv(double ar, double ai, double br, double bi, double& 
 }
 
 // alpha = rho / <rhat, v>
-__global__ void __launch_bounds__(BS) k_fin_alpha(Scal* sc, const double* partials, int n) {
+__global__ void __launch_bounds__(FBS) k_fin_alpha(Scal* sc, const double* partials, int n) {
   if (sc->done) return;
   double v[2];
   sum_partials<2>(partials, n, v);
@@ -232,7 +246,7 @@ __global__ void __launch_bounds__(BS) k_fin_alpha(Scal* sc, const double* partia
 }
 
 // omega = <t, s> / <t, t>
-__global__ void __launch_bounds__(BS) k_fin_omega(Scal* sc, const double* partials, int n) {
+__global__ void __launch_bounds__(FBS) k_fin_omega(Scal* sc, const double* partials, int n) {
   if (sc->done) return;
   double v[3];
   sum_partials<3>(partials, n, v);
@@ -248,7 +262,7 @@ __global__ void __launch_bounds__(BS) k_fin_omega(Scal* sc, const double* partia
 }
 
 // rho_new = <rhat, r>, rr = <r, r>; beta = (rho_new / rho)(alpha / omega); convergence test
-__global__ void __launch_bounds__(BS) k_fin_rho(Scal* sc, const double* partials, int n) {
+__global__ void __launch_bounds__(FBS) k_fin_rho(Scal* sc, const double* partials, int n) {
   if (sc->done) return;
   double v[3];
   sum_partials<3>(partials, n, v);
@@ -277,7 +291,7 @@ __global__ void __launch_bounds__(BS) k_fin_rho(Scal* sc, const double* partials
 }
 
 // Start of a (re)start: rho = <rhat, r>, rr = <r, r>, alpha = omega = 1.
-__global__ void __launch_bounds__(BS) k_fin_init(Scal* sc, const double* partials, int n, double target2,
+__global__ void __launch_bounds__(FBS) k_fin_init(Scal* sc, const double* partials, int n, double target2,
                                                  int max_iters) {
   double v[3];
   sum_partials<3>(partials, n, v);
@@ -300,7 +314,7 @@ __global__ void __launch_bounds__(BS) k_fin_init(Scal* sc, const double* partial
 }
 
 // out[0] = sum of n partials (width 1 or 3, component `comp`); out[1] = 1/sqrt(out[0]) (0 if out[0] == 0)
-__global__ void __launch_bounds__(BS) k_fin_norm(double* out, const double* partials, int n, int width, int comp) {
+__global__ void __launch_bounds__(FBS) k_fin_norm(double* out, const double* partials, int n, int width, int comp) {
   double v = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) v += partials[(size_t)j * width + comp];
   double tmp[1] = {v};
@@ -404,27 +418,27 @@ int blas_zero(lqcd_ctx* c, int prec, void* dst) {
 }
 
 int fin_alpha(lqcd_ctx* c, Scal* sc, const double* partials, int n) {
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(BS), 0, c->stream, sc, partials, n);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FBS), 0, c->stream, sc, partials, n);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }
 int fin_omega(lqcd_ctx* c, Scal* sc, const double* partials, int n) {
-  hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(BS), 0, c->stream, sc, partials, n);
+  hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(FBS), 0, c->stream, sc, partials, n);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }
 int fin_rho(lqcd_ctx* c, Scal* sc, const double* partials, int n) {
-  hipLaunchKernelGGL(k_fin_rho, dim3(1), dim3(BS), 0, c->stream, sc, partials, n);
+  hipLaunchKernelGGL(k_fin_rho, dim3(1), dim3(FBS), 0, c->stream, sc, partials, n);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }
 int fin_init(lqcd_ctx* c, Scal* sc, const double* partials, int n, double target2, int max_iters) {
-  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, c->stream, sc, partials, n, target2, max_iters);
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(FBS), 0, c->stream, sc, partials, n, target2, max_iters);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }
 int fin_norm(lqcd_ctx* c, double* out, const double* partials, int n, int width, int comp) {
-  hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(BS), 0, c->stream, out, partials, n, width, comp);
+  hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(FBS), 0, c->stream, out, partials, n, width, comp);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }

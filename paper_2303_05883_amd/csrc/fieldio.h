@@ -9,6 +9,32 @@ namespace lq {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+// 16- and 8-byte loads; NT = non-temporal (streamed once, kept out of the caches'
+// reuse set so that neighbour spinors stay resident).
+template <bool NT>
+__device__ inline double2 ld16(const double2* p) {
+  if (NT) {
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+    return make_double2(v.x, v.y);
+  }
+  return *p;
+}
+template <bool NT>
+__device__ inline float4 ld16(const float4* p) {
+  if (NT) {
+    const fvec4 v = __builtin_nontemporal_load(reinterpret_cast<const fvec4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  return *p;
+}
+template <bool NT>
+__device__ inline half4 ld8(const half4* p) {
+  if (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
 
 template <int P>
 struct IO;
@@ -22,6 +48,17 @@ struct IO<0> {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       double2 v = b[k * vh + i];
+      s[k] = {v.x, v.y};
+    }
+  }
+  // sel 0: the whole spinor; sel 1: spins 0,1 into both halves; sel 2: spins
+  // 2,3 into both halves (one instruction stream whatever the lane's sel)
+  __device__ static inline void load_spinor_sel(const void* f, size_t vh, size_t i, int sel, cx<T> s[12]) {
+    const double2* b = reinterpret_cast<const double2*>(f);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const int h = sel == 0 ? k / 6 : sel - 1;
+      double2 v = b[(size_t)(k % 6 + 6 * h) * vh + i];
       s[k] = {v.x, v.y};
     }
   }
@@ -39,11 +76,19 @@ struct IO<0> {
 #pragma unroll
     for (int k = 0; k < 12; ++k) b[k * vh + i] = make_double2(s[k].r, s[k].i);
   }
+  // planes k with k % nl == lane (the lanes of one site share the stores)
+  __device__ static inline void store_part(void* f, size_t vh, size_t i, const cx<T> s[12], int lane, int nl) {
+    double2* b = reinterpret_cast<double2*>(f);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      if (k % nl == lane) b[k * vh + i] = make_double2(s[k].r, s[k].i);
+  }
+  template <bool NT = false>
   __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
     const double2* b = reinterpret_cast<const double2*>(g);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double2 v = b[k * vh + i];
+      double2 v = ld16<NT>(b + k * vh + i);
       u[k] = {v.x, v.y};
     }
   }
@@ -71,6 +116,16 @@ struct IO<1> {
       s[2 * k + 1] = {v.z, v.w};
     }
   }
+  __device__ static inline void load_spinor_sel(const void* f, size_t vh, size_t i, int sel, cx<T> s[12]) {
+    const float4* b = reinterpret_cast<const float4*>(f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int h = sel == 0 ? k / 3 : sel - 1;
+      float4 v = b[(size_t)(k % 3 + 3 * h) * vh + i];
+      s[2 * k] = {v.x, v.y};
+      s[2 * k + 1] = {v.z, v.w};
+    }
+  }
   __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
     const float4* b = reinterpret_cast<const float4*>(f) + (upper ? 0 : 3 * vh);
 #pragma unroll
@@ -86,11 +141,18 @@ struct IO<1> {
     for (int k = 0; k < 6; ++k)
       b[k * vh + i] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
   }
+  __device__ static inline void store_part(void* f, size_t vh, size_t i, const cx<T> s[12], int lane, int nl) {
+    float4* b = reinterpret_cast<float4*>(f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k % nl == lane) b[k * vh + i] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
+  }
+  template <bool NT = false>
   __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
     const float4* b = reinterpret_cast<const float4*>(g);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float4 v = b[k * vh + i];
+      float4 v = ld16<NT>(b + k * vh + i);
       u[2 * k] = {v.x, v.y};
       u[2 * k + 1] = {v.z, v.w};
     }
@@ -123,6 +185,10 @@ struct IO<2> {
       for (int j = 0; j < 4; ++j) s[4 * k + j] = {n * (float)v[2 * j], n * (float)v[2 * j + 1]};
     }
   }
+  // the FP16 planes mix spins 1 and 2, so every selection loads the whole spinor
+  __device__ static inline void load_spinor_sel(const void* f, size_t vh, size_t i, int, cx<T> s[12]) {
+    load_spinor(f, vh, i, s);
+  }
   __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
     cx<T> all[12];
     load_spinor(f, vh, i, all);
@@ -147,11 +213,32 @@ struct IO<2> {
     }
     reinterpret_cast<float*>(reinterpret_cast<char*>(f) + 48 * vh)[i] = m;
   }
+  // planes 0..2 and the scale (as plane 3), k % nl == lane
+  __device__ static inline void store_part(void* f, size_t vh, size_t i, const cx<T> s[12], int lane, int nl) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].r), fabsf(s[k].i)));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    half8* b = reinterpret_cast<half8*>(f);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k % nl != lane) continue;
+      half8 v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[2 * j] = (_Float16)(s[4 * k + j].r * inv);
+        v[2 * j + 1] = (_Float16)(s[4 * k + j].i * inv);
+      }
+      b[k * vh + i] = v;
+    }
+    if (3 % nl == lane) reinterpret_cast<float*>(reinterpret_cast<char*>(f) + 48 * vh)[i] = m;
+  }
+  template <bool NT = false>
   __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
     const half4* b = reinterpret_cast<const half4*>(g);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      half4 v = b[k * vh + i];
+      half4 v = ld8<NT>(b + k * vh + i);
       u[2 * k] = {(float)v[0], (float)v[1]};
       u[2 * k + 1] = {(float)v[2], (float)v[3]};
     }
@@ -218,6 +305,27 @@ __device__ inline void clover_apply(const void* clov, size_t vh, size_t i, const
     out[k] = yp[k] + ym[k];
     out[k + 6] = ym[k] - yp[k];
   }
+}
+
+// Exchange with the neighbouring lane of a quad: CTRL = 0xB1 swaps lanes
+// (0,1)(2,3), CTRL = 0x4E swaps (0,2)(1,3) (DPP quad permutations).
+template <int CTRL>
+__device__ inline float quad_swap(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double quad_swap(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+// Sum over the four lanes of a quad; every lane receives the total.
+template <typename T>
+__device__ inline T quad_sum(T v) {
+  v += quad_swap<0xB1>(v);
+  v += quad_swap<0x4E>(v);
+  return v;
 }
 
 // blockIdx -> logical block: with remap on, each of the 8 XCDs (which receive

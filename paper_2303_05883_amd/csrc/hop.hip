@@ -102,7 +102,7 @@ __device__ inline void link_mul(const cx<T> u[6], const cx<T> h[6], cx<T> w[6]) 
   }
 }
 
-template <int P, int MU, bool FWD>
+template <int P, int MU, bool FWD, bool NT>
 __device__ inline void hop_dir(const void* in, const void* links, size_t vh, size_t nbr, size_t lidx, bool flip,
                                cx<typename IO<P>::T> acc[12]) {
   using T = typename IO<P>::T;
@@ -120,7 +120,7 @@ __device__ inline void hop_dir(const void* in, const void* links, size_t vh, siz
     project<MU, FWD>(s, h);
   }
   cx<T> u[6], w[6];
-  IO<P>::load_link(links, vh, lidx, u);
+  IO<P>::template load_link<NT>(links, vh, lidx, u);
   link_mul<FWD>(u, h, w);
   expand<MU, FWD>(acc, w);
 }
@@ -138,19 +138,92 @@ struct HopArgs {
   double scale;
   Geom g;
   int p;
-  int remap;
+  int remap;  // 0: linear, 1: XCD-contiguous ranges, 2: XCD z-slabs (see map_site)
+  int hz;     // z extent of one XCD slab (remap 2)
 };
 
+// Site of this thread (local = index among the block's sites, spb sites per
+// block). remap 2 gives XCD k (blocks are dealt to the 8 XCDs round-robin) the
+// slab z in [k hz, (k+1) hz) and walks it x, y fastest, then z, then t, so that
+// the z and t neighbours of the sites in flight were read shortly before and
+// are still in that XCD's L2. Returns false for threads past the slab's end.
+__device__ inline bool map_site(const HopArgs& a, int spb, int local, size_t& i) {
+  if (a.remap == 2) {
+    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int xy = a.g.lxh * a.g.ly;
+    const int q = j * spb + local;
+    if (q >= xy * a.hz * a.g.lt) return false;
+    const int xyi = q % xy, rest = q / xy;
+    const int zin = rest % a.hz, t = rest / a.hz;
+    i = (size_t)xyi + (size_t)xy * ((size_t)(k * a.hz + zin) + (size_t)a.g.lz * t);
+    return true;
+  }
+  i = (size_t)logical_block(a.remap) * spb + local;
+  return i < (size_t)a.g.vh;
+}
+
+
+// The epilogue shared by the hop kernels: out from the hop sum acc at site i,
+// plus the fused reductions of this site added into red.
 template <int P, int EPI, bool CLOV, int RED>
+__device__ inline void hop_epilogue(const HopArgs& a, size_t i, cx<typename IO<P>::T> acc[12],
+                                    cx<typename IO<P>::T> out[12], double red[3]) {
+  using T = typename IO<P>::T;
+  const size_t vh = (size_t)a.g.vh;
+  const T sc = (T)a.scale;
+  if (EPI == EPI_SCALE) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[k] = sc * acc[k];
+  } else if (EPI == EPI_SCALE_CLOV) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
+    clover_apply<P>(a.clov, vh, i, acc, out);
+  } else {
+    cx<T> xo[12];
+    IO<P>::load_spinor(a.xown, vh, i, xo);
+    if (CLOV) {
+      cx<T> cxo[12];
+      clover_apply<P>(a.clov, vh, i, xo, cxo);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) out[k] = cxo[k] + sc * acc[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) out[k] = xo[k] + sc * acc[k];
+    }
+    if (RED == RED_TS) {
+      // <out, x> and <out, out>
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const cx<T> d = cmulc(out[k], xo[k]);
+        red[0] += (double)d.r;
+        red[1] += (double)d.i;
+        red[2] += (double)out[k].r * (double)out[k].r + (double)out[k].i * (double)out[k].i;
+      }
+    }
+  }
+  if (RED == RED_DOT) {
+    cx<T> wv[12];
+    IO<P>::load_spinor(a.w, vh, i, wv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const cx<T> d = cmulc(wv[k], out[k]);
+      red[0] += (double)d.r;
+      red[1] += (double)d.i;
+    }
+  }
+}
+
+template <int P, int EPI, bool CLOV, int RED, bool NT>
 __global__ void __launch_bounds__(256) k_hop(HopArgs a) {
   using T = typename IO<P>::T;
   if (a.skip && *a.skip) return;
   const size_t vh = (size_t)a.g.vh;
-  const int blk = logical_block(a.remap);
-  const size_t i = (size_t)blk * blockDim.x + threadIdx.x;
+  const int blk = blockIdx.x;
+  size_t i = 0;
+  const bool active = map_site(a, blockDim.x, threadIdx.x, i);
   constexpr int NR = RED == RED_DOT ? 2 : (RED == RED_TS ? 3 : 0);
   double red[3] = {0.0, 0.0, 0.0};
-  if (i < vh) {
+  if (active) {
     const Geom& g = a.g;
     const int ii = (int)i;
     const int xh = ii % g.lxh;
@@ -181,58 +254,134 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
 
-    hop_dir<P, 0, true>(a.in, gf + 0 * ls, vh, (size_t)(row + (xf >> 1)), i, false, acc);
-    hop_dir<P, 0, false>(a.in, gb + 0 * ls, vh, (size_t)(row + (xb >> 1)), (size_t)(row + (xb >> 1)), false, acc);
-    hop_dir<P, 1, true>(a.in, gf + 1 * ls, vh, (size_t)iyf, i, false, acc);
-    hop_dir<P, 1, false>(a.in, gb + 1 * ls, vh, (size_t)iyb, (size_t)iyb, false, acc);
-    hop_dir<P, 2, true>(a.in, gf + 2 * ls, vh, (size_t)izf, i, false, acc);
-    hop_dir<P, 2, false>(a.in, gb + 2 * ls, vh, (size_t)izb, (size_t)izb, false, acc);
-    hop_dir<P, 3, true>(a.in, gf + 3 * ls, vh, (size_t)itf, i, flipf, acc);
-    hop_dir<P, 3, false>(a.in, gb + 3 * ls, vh, (size_t)itb, (size_t)itb, flipb, acc);
+    hop_dir<P, 0, true, NT>(a.in, gf + 0 * ls, vh, (size_t)(row + (xf >> 1)), i, false, acc);
+    hop_dir<P, 0, false, NT>(a.in, gb + 0 * ls, vh, (size_t)(row + (xb >> 1)), (size_t)(row + (xb >> 1)), false, acc);
+    hop_dir<P, 1, true, NT>(a.in, gf + 1 * ls, vh, (size_t)iyf, i, false, acc);
+    hop_dir<P, 1, false, NT>(a.in, gb + 1 * ls, vh, (size_t)iyb, (size_t)iyb, false, acc);
+    hop_dir<P, 2, true, NT>(a.in, gf + 2 * ls, vh, (size_t)izf, i, false, acc);
+    hop_dir<P, 2, false, NT>(a.in, gb + 2 * ls, vh, (size_t)izb, (size_t)izb, false, acc);
+    hop_dir<P, 3, true, NT>(a.in, gf + 3 * ls, vh, (size_t)itf, i, flipf, acc);
+    hop_dir<P, 3, false, NT>(a.in, gb + 3 * ls, vh, (size_t)itb, (size_t)itb, flipb, acc);
 
-    const T sc = (T)a.scale;
     cx<T> out[12];
-    if (EPI == EPI_SCALE) {
-#pragma unroll
-      for (int k = 0; k < 12; ++k) out[k] = sc * acc[k];
-    } else if (EPI == EPI_SCALE_CLOV) {
-#pragma unroll
-      for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
-      clover_apply<P>(a.clov, vh, i, acc, out);
-    } else {
-      cx<T> xo[12];
-      IO<P>::load_spinor(a.xown, vh, i, xo);
-      if (CLOV) {
-        cx<T> cxo[12];
-        clover_apply<P>(a.clov, vh, i, xo, cxo);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) out[k] = cxo[k] + sc * acc[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) out[k] = xo[k] + sc * acc[k];
-      }
-      if (RED == RED_TS) {
-        // <out, x> and <out, out>
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          const cx<T> d = cmulc(out[k], xo[k]);
-          red[0] += (double)d.r;
-          red[1] += (double)d.i;
-          red[2] += (double)out[k].r * (double)out[k].r + (double)out[k].i * (double)out[k].i;
-        }
-      }
-    }
+    hop_epilogue<P, EPI, CLOV, RED>(a, i, acc, out, red);
     IO<P>::store_spinor(a.out, vh, i, out);
-    if (RED == RED_DOT) {
-      cx<T> wv[12];
-      IO<P>::load_spinor(a.w, vh, i, wv);
+  }
+  if constexpr (NR > 0) block_reduce<NR>(red, a.partials + (size_t)blk * NR);
+}
+
+
+// Direction-split hop: four lanes of a quad share one output site, lane mu
+// taking the forward and backward hops in direction mu. Every lane issues its
+// two neighbour loads and two link loads before any arithmetic, so a site has
+// all of its 16 reads in flight at once with a quarter of the registers per
+// lane; the four partial sums are added with quad DPP exchanges. The lanes run
+// one instruction stream: the direction enters only through the coefficients
+// of the spin projection and reconstruction, (1 -+ gamma_mu) psi = (h, P h)
+// with h = a u + c0 l_{j0}, ... (see below). The epilogue is computed by all
+// four lanes; the stores are split between them.
+template <int P, int EPI, bool CLOV, int RED, bool NT>
+__global__ void __launch_bounds__(256) k_hop4(HopArgs a) {
+  using T = typename IO<P>::T;
+  if (a.skip && *a.skip) return;
+  const size_t vh = (size_t)a.g.vh;
+  const int blk = blockIdx.x;
+  const int mu = threadIdx.x & 3;
+  size_t i = 0;
+  const bool active = map_site(a, blockDim.x >> 2, threadIdx.x >> 2, i);
+  constexpr int NR = RED == RED_DOT ? 2 : (RED == RED_TS ? 3 : 0);
+  double red[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    const Geom& g = a.g;
+    const int ii = (int)i;
+    const int xh = ii % g.lxh;
+    int r = ii / g.lxh;
+    const int y = r % g.ly;
+    r /= g.ly;
+    const int z = r % g.lz;
+    const int t = r / g.lz;
+    const int x = 2 * xh + ((y + z + t + a.p) & 1);
+    // neighbour indices in direction mu, computed without branching: for
+    // mu = 0 the checkerboarded x index moves within the row, otherwise the
+    // index moves by the direction's stride with a periodic wrap
+    const bool tdir = mu == 3;
+    const int c = mu == 1 ? y : (mu == 2 ? z : t);
+    const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
+    const int st = mu == 1 ? g.lxh : (mu == 2 ? g.lxh * g.ly : g.lxh * g.ly * g.lz);
+    const int row = ii - xh;
+    const int xnf = row + (((x + 1 == g.lx) ? 0 : x + 1) >> 1);
+    const int xnb = row + (((x == 0) ? g.lx - 1 : x - 1) >> 1);
+    const int nf = mu == 0 ? xnf : ii + ((c + 1 == L) ? -(L - 1) * st : st);
+    const int nb = mu == 0 ? xnb : ii + ((c == 0) ? (L - 1) * st : -st);
+    const bool flipf = tdir && (g.t_bc < 0) && (t + 1 == g.lt);
+    const bool flipb = tdir && (g.t_bc < 0) && (t == 0);
+    // loads first, the same instructions in every lane: a t lane needs one
+    // half of each neighbour and reads it into both halves (its other half is
+    // multiplied by zero below)
+    cx<T> sf[12], sb[12], uf[6], ub[6];
+    const char* lf = a.gauge + (size_t)(a.p * 4 + mu) * a.link_stride;
+    const char* lb = a.gauge + (size_t)((1 - a.p) * 4 + mu) * a.link_stride;
+    IO<P>::template load_link<NT>(lf, vh, i, uf);
+    IO<P>::template load_link<NT>(lb, vh, (size_t)nb, ub);
+    IO<P>::load_spinor_sel(a.in, vh, (size_t)nf, tdir ? 2 : 0, sf);
+    IO<P>::load_spinor_sel(a.in, vh, (size_t)nb, tdir ? 1 : 0, sb);
+    // projection h0 = A s0 + C0 s_{j0}, h1 = A s1 + C1 s_{j1} (j0, j1 = 3, 2 for
+    // x and y, 2, 3 for z and t); expansion upper += B w, lower0 += D0 w_{m0},
+    // lower1 += D1 w_{m1} (m0, m1 = 1, 0 for x and y, 0, 1 for z and t).
+    // Backward hops negate C and D; in t the forward hop is (0, 2 l), the
+    // backward one (2 u, 0); eta = -1 flips h.
+    const bool sw = mu < 2;
+    const T c0r = mu == 1 ? T(1) : (tdir ? T(2) : T(0));
+    const T c0i = (mu == 0 || mu == 2) ? T(1) : T(0);
+    const T c1r = mu == 1 ? T(-1) : (tdir ? T(2) : T(0));
+    const T c1i = mu == 0 ? T(1) : (mu == 2 ? T(-1) : T(0));
+    const T d0r = mu == 1 ? T(-1) : (tdir ? T(1) : T(0));
+    const T d0i = (mu == 0 || mu == 2) ? T(-1) : T(0);
+    const T d1r = (mu == 1 || tdir) ? T(1) : T(0);
+    const T d1i = mu == 0 ? T(-1) : (mu == 2 ? T(1) : T(0));
+    cx<T> acc[12];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        const cx<T> d = cmulc(wv[k], out[k]);
-        red[0] += (double)d.r;
-        red[1] += (double)d.i;
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool fwd = dir == 0;
+      const cx<T>* s = fwd ? sf : sb;
+      const T e = (fwd ? flipf : flipb) ? T(-1) : T(1);
+      const T A = e * (tdir ? (fwd ? T(0) : T(2)) : T(1));
+      const T sg = fwd ? e : -e;  // sign of C for this hop (backward negates; eta flips)
+      const T C0r = tdir && !fwd ? T(0) : sg * c0r, C0i = sg * c0i;
+      const T C1r = tdir && !fwd ? T(0) : sg * c1r, C1i = sg * c1i;
+      cx<T> h[6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<T> l0 = sw ? s[9 + c] : s[6 + c];
+        const cx<T> l1 = sw ? s[6 + c] : s[9 + c];
+        h[c] = {A * s[c].r + C0r * l0.r - C0i * l0.i, A * s[c].i + C0r * l0.i + C0i * l0.r};
+        h[3 + c] = {A * s[3 + c].r + C1r * l1.r - C1i * l1.i, A * s[3 + c].i + C1r * l1.i + C1i * l1.r};
+      }
+      cx<T> w[6];
+      if (fwd) link_mul<true>(uf, h, w);
+      else link_mul<false>(ub, h, w);
+      const T B = tdir && fwd ? T(0) : T(1);
+      const T ds = fwd ? T(1) : T(-1);
+      const T D0r = tdir ? (fwd ? T(1) : T(0)) : ds * d0r, D0i = ds * d0i;
+      const T D1r = tdir ? (fwd ? T(1) : T(0)) : ds * d1r, D1i = ds * d1i;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<T> w0 = w[c], w1 = w[3 + c];
+        const cx<T> m0 = sw ? w1 : w0, m1 = sw ? w0 : w1;
+        acc[c] = acc[c] + B * w0;
+        acc[3 + c] = acc[3 + c] + B * w1;
+        acc[6 + c] = acc[6 + c] + cx<T>{D0r * m0.r - D0i * m0.i, D0r * m0.i + D0i * m0.r};
+        acc[9 + c] = acc[9 + c] + cx<T>{D1r * m1.r - D1i * m1.i, D1r * m1.i + D1i * m1.r};
       }
     }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {quad_sum(acc[k].r), quad_sum(acc[k].i)};
+    cx<T> out[12];
+    hop_epilogue<P, EPI, CLOV, RED>(a, i, acc, out, red);
+    if (mu != 0) red[0] = red[1] = red[2] = 0.0;
+    IO<P>::store_part(a.out, vh, i, out, mu, 4);
   }
   if constexpr (NR > 0) block_reduce<NR>(red, a.partials + (size_t)blk * NR);
 }
@@ -253,36 +402,48 @@ __global__ void __launch_bounds__(256) k_site(const void* clov, const void* in, 
 }
 
 int hop_blocks(lqcd_ctx* c, int prec) {
-  const int bs = c->hop_block[prec];
-  return (c->g.vh + bs - 1) / bs;
+  const int sites = c->hop_block[prec] / c->hop_split[prec];
+  if (c->hop_remap[prec] == 2) {
+    const int slab = c->g.vh / 8;  // sites of one XCD slab
+    return 8 * ((slab + sites - 1) / sites);
+  }
+  return (c->g.vh + sites - 1) / sites;
 }
 
 template <int P, int EPI, bool CLOV, int RED>
-static void launch_t(const HopArgs& a, int nb, int bs, hipStream_t s) {
-  hipLaunchKernelGGL((k_hop<P, EPI, CLOV, RED>), dim3(nb), dim3(bs), 0, s, a);
+static void launch_t(const HopArgs& a, int nb, int bs, hipStream_t s, bool nt, int split) {
+  if (split == 4) {
+    if (nt) hipLaunchKernelGGL((k_hop4<P, EPI, CLOV, RED, true>), dim3(nb), dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL((k_hop4<P, EPI, CLOV, RED, false>), dim3(nb), dim3(bs), 0, s, a);
+  } else {
+    if (nt) hipLaunchKernelGGL((k_hop<P, EPI, CLOV, RED, true>), dim3(nb), dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL((k_hop<P, EPI, CLOV, RED, false>), dim3(nb), dim3(bs), 0, s, a);
+  }
 }
 
 template <int P>
 static int dispatch(lqcd_ctx* c, const HopCall& h, HopArgs& a, int nb, int bs) {
   const bool cl = h.clov != nullptr;
+  const bool nt = c->hop_nt[h.prec] != 0;
+  const int split = c->hop_split[h.prec];
   hipStream_t s = c->stream;
   if (h.epi == EPI_SCALE && h.red == RED_NONE) {
-    launch_t<P, EPI_SCALE, false, RED_NONE>(a, nb, bs, s);
+    launch_t<P, EPI_SCALE, false, RED_NONE>(a, nb, bs, s, nt, split);
   } else if (h.epi == EPI_SCALE && h.red == RED_DOT) {
-    launch_t<P, EPI_SCALE, false, RED_DOT>(a, nb, bs, s);
+    launch_t<P, EPI_SCALE, false, RED_DOT>(a, nb, bs, s, nt, split);
   } else if (h.epi == EPI_SCALE_CLOV && h.red == RED_NONE) {
-    if (cl) launch_t<P, EPI_SCALE_CLOV, true, RED_NONE>(a, nb, bs, s);
-    else launch_t<P, EPI_SCALE, false, RED_NONE>(a, nb, bs, s);
+    if (cl) launch_t<P, EPI_SCALE_CLOV, true, RED_NONE>(a, nb, bs, s, nt, split);
+    else launch_t<P, EPI_SCALE, false, RED_NONE>(a, nb, bs, s, nt, split);
   } else if (h.epi == EPI_XPAY) {
     if (h.red == RED_NONE) {
-      if (cl) launch_t<P, EPI_XPAY, true, RED_NONE>(a, nb, bs, s);
-      else launch_t<P, EPI_XPAY, false, RED_NONE>(a, nb, bs, s);
+      if (cl) launch_t<P, EPI_XPAY, true, RED_NONE>(a, nb, bs, s, nt, split);
+      else launch_t<P, EPI_XPAY, false, RED_NONE>(a, nb, bs, s, nt, split);
     } else if (h.red == RED_DOT) {
-      if (cl) launch_t<P, EPI_XPAY, true, RED_DOT>(a, nb, bs, s);
-      else launch_t<P, EPI_XPAY, false, RED_DOT>(a, nb, bs, s);
+      if (cl) launch_t<P, EPI_XPAY, true, RED_DOT>(a, nb, bs, s, nt, split);
+      else launch_t<P, EPI_XPAY, false, RED_DOT>(a, nb, bs, s, nt, split);
     } else {
-      if (cl) launch_t<P, EPI_XPAY, true, RED_TS>(a, nb, bs, s);
-      else launch_t<P, EPI_XPAY, false, RED_TS>(a, nb, bs, s);
+      if (cl) launch_t<P, EPI_XPAY, true, RED_TS>(a, nb, bs, s, nt, split);
+      else launch_t<P, EPI_XPAY, false, RED_TS>(a, nb, bs, s, nt, split);
     }
   } else {
     return set_error(LQCD_EINVAL, "unsupported hop epilogue/reduction combination");
@@ -295,6 +456,7 @@ int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out) {
   if (!c->gauge[h.prec]) return set_error(LQCD_ESTATE, "gauge field not set");
   const int bs = c->hop_block[h.prec];
   if (bs % 64 != 0 || bs < 64 || bs > 256) return set_error(LQCD_EINVAL, "hop block size must be 64..256, multiple of 64");
+  if (c->hop_split[h.prec] != 1 && c->hop_split[h.prec] != 4) return set_error(LQCD_EINVAL, "bad hop split");
   const int nb = hop_blocks(c, h.prec);
   if (nblocks_out) *nblocks_out = nb;
   if (h.red != RED_NONE && !h.partials) return set_error(LQCD_EINVAL, "reduction without a partials buffer");
@@ -312,6 +474,8 @@ int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out) {
   a.g = c->g;
   a.p = h.out_parity;
   a.remap = c->hop_remap[h.prec];
+  a.hz = c->g.lz / 8;
+  if (a.remap == 2 && (c->g.lz % 8 != 0)) return set_error(LQCD_EINVAL, "XCD z-slabs need Lz divisible by 8");
   switch (h.prec) {
     case 0: return dispatch<0>(c, h, a, nb, bs);
     case 1: return dispatch<1>(c, h, a, nb, bs);

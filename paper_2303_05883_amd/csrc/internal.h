@@ -124,6 +124,8 @@ struct lqcd_ctx {
   // launch shape of the hop per precision (autotuned)
   int hop_block[3] = {256, 256, 256};
   int hop_remap[3] = {1, 1, 1};
+  int hop_nt[3] = {0, 0, 0};     // non-temporal link loads
+  int hop_split[3] = {1, 1, 1};  // lanes per output site: 1, or 4 (one direction per lane)
 
   lq::Workspace* ws = nullptr;
 };
@@ -175,6 +177,8 @@ struct HopCall {
 };
 int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out);
 int hop_blocks(lqcd_ctx* c, int prec);
+// most blocks any hop launch shape uses (partials buffers are sized for it)
+inline size_t max_hop_blocks(size_t vh) { return (vh + 15) / 16 + 8; }
 // out = C x (C = clover slot, or identity -> copy)
 int launch_site(lqcd_ctx* c, int prec, const void* clov, const void* in, void* out);
 

@@ -16,7 +16,7 @@ struct InnerVecs {
   double* partials = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int graph_k = 0, graph_block = 0, graph_remap = -1;
+  int graph_k = 0, graph_block = 0, graph_remap = -1, graph_nt = -1, graph_split = -1;
   int init(lqcd_ctx* c, int prec, int xprec);
   void release();
 };

@@ -43,7 +43,7 @@ int InnerVecs::init(lqcd_ctx* c, int p, int xp) {
   for (void** q : v) LQ_TRY(alloc(q, spinor_bytes(prec, vh)));
   LQ_TRY(alloc(&x, spinor_bytes(xprec, vh)));
   LQ_TRY(alloc(reinterpret_cast<void**>(&sc), sizeof(Scal)));
-  const size_t np = (size_t)std::max(blas_blocks(vh), (int)((vh + 63) / 64)) * 3;
+  const size_t np = std::max((size_t)blas_blocks(vh), max_hop_blocks(vh)) * 3;
   LQ_TRY(alloc(reinterpret_cast<void**>(&partials), np * sizeof(double)));
   return LQCD_OK;
 }
@@ -141,7 +141,8 @@ static int run_chunk(lqcd_ctx* c, InnerVecs& v, int k, bool use_graph) {
     for (int j = 0; j < k; ++j) LQ_TRY(bicg_iteration(c, v));
     return LQCD_OK;
   }
-  if (!v.exec || v.graph_k != k || v.graph_block != c->hop_block[v.prec] || v.graph_remap != c->hop_remap[v.prec]) {
+  if (!v.exec || v.graph_k != k || v.graph_block != c->hop_block[v.prec] || v.graph_remap != c->hop_remap[v.prec] ||
+      v.graph_nt != c->hop_nt[v.prec] || v.graph_split != c->hop_split[v.prec]) {
     if (v.exec) (void)hipGraphExecDestroy(v.exec);
     if (v.graph) (void)hipGraphDestroy(v.graph);
     v.exec = nullptr;
@@ -165,6 +166,8 @@ static int run_chunk(lqcd_ctx* c, InnerVecs& v, int k, bool use_graph) {
     v.graph_k = k;
     v.graph_block = c->hop_block[v.prec];
     v.graph_remap = c->hop_remap[v.prec];
+    v.graph_nt = c->hop_nt[v.prec];
+    v.graph_split = c->hop_split[v.prec];
   }
   LQ_HIP(hipGraphLaunch(v.exec, c->stream));
   return LQCD_OK;

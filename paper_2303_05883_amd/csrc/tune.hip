@@ -2,12 +2,14 @@
 //
 // The paper measures the operator over several SIMD tile shapes and finds
 // little difference (Sec. 3); on gfx950 the equivalent knobs are the workgroup
-// size and whether blocks are mapped so that each XCD works on one contiguous
-// slab of the lattice (its own L2). The tuner times each candidate with HIP
+// size, whether blocks are mapped so that each XCD works on one contiguous
+// slab of the lattice (its own L2), and whether the links (read once) are
+// loaded non-temporally, and whether one lane or a quad of lanes (one lattice
+// direction each) computes an output site. The tuner times each candidate with HIP
 // events on scratch fields and keeps the fastest per (lattice, precision).
 //
 // Cache format: one JSON object, keys "Lx.Ly.Lz.Lt:prec", values
-// {"block": B, "remap": R, "us": T}. The path comes from lqcd_autotune's
+// {"block": B, "remap": R, "nt": N, "split": S, "us": T}. The path comes from lqcd_autotune's
 // argument or from the LQCD_TUNE_CACHE environment variable.
 #include <cstdio>
 #include <cstdlib>
@@ -31,7 +33,7 @@ std::string key_of(const lqcd_ctx* c, int prec) {
 }
 
 struct Entry {
-  int block = 256, remap = 1;
+  int block = 256, remap = 1, nt = 0, split = 1;
   double us = 0;
 };
 
@@ -61,12 +63,16 @@ std::map<std::string, Entry> read_cache(const std::string& path) {
       const size_t colon = body.find(':', k);
       if (colon != std::string::npos) out = std::atof(body.c_str() + colon + 1);
     };
-    double b = 256, r = 1, us = 0;
+    double b = 256, r = 1, nt = 0, sp = 1, us = 0;
     num("block", b);
     num("remap", r);
+    num("nt", nt);
+    num("split", sp);
+    e.split = (int)sp;
     num("us", us);
     e.block = (int)b;
     e.remap = (int)r;
+    e.nt = (int)nt;
     e.us = us;
     m[key] = e;
     pos = cb + 1;
@@ -81,13 +87,16 @@ bool write_cache(const std::string& path, const std::map<std::string, Entry>& m)
   size_t n = 0;
   for (const auto& kv : m) {
     f << "  \"" << kv.first << "\": {\"block\": " << kv.second.block << ", \"remap\": " << kv.second.remap
-      << ", \"us\": " << kv.second.us << "}" << (++n < m.size() ? "," : "") << "\n";
+      << ", \"nt\": " << kv.second.nt << ", \"split\": " << kv.second.split << ", \"us\": " << kv.second.us << "}" << (++n < m.size() ? "," : "") << "\n";
   }
   f << "}\n";
   return true;
 }
 
-bool valid(const Entry& e) { return (e.block == 64 || e.block == 128 || e.block == 192 || e.block == 256) && (e.remap == 0 || e.remap == 1); }
+bool valid(const Entry& e) {
+  return (e.block == 64 || e.block == 128 || e.block == 192 || e.block == 256) && e.remap >= 0 && e.remap <= 2 &&
+         (e.nt == 0 || e.nt == 1) && (e.split == 1 || e.split == 4);
+}
 
 }  // namespace
 
@@ -100,6 +109,8 @@ int tune_load_defaults(lqcd_ctx* c) {
     if (it != m.end() && valid(it->second)) {
       c->hop_block[p] = it->second.block;
       c->hop_remap[p] = it->second.remap;
+      c->hop_nt[p] = it->second.nt;
+      c->hop_split[p] = it->second.split;
     }
   }
   return LQCD_OK;
@@ -113,52 +124,73 @@ extern "C" int lqcd_autotune(lqcd_ctx* c, int prec, const char* path) {
   if (!c) return set_error(LQCD_EINVAL, "null argument");
   if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
   if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  // three input/output pairs in rotation, so that the timed launches stream
+  // from HBM instead of hitting in the Infinity Cache as a solver's would not
   const size_t bytes = spinor_bytes(prec, c->g.vh);
-  void *in = nullptr, *out = nullptr;
-  if (hipMalloc(&in, bytes) != hipSuccess || hipMalloc(&out, bytes) != hipSuccess) {
-    if (in) (void)hipFree(in);
-    return set_error(LQCD_ENOMEM, "autotune scratch allocation failed");
+  constexpr int NB = 3;
+  void* buf[2 * NB] = {};
+  for (int k = 0; k < 2 * NB; ++k) {
+    if (hipMalloc(&buf[k], bytes) != hipSuccess) {
+      for (int j = 0; j < k; ++j) (void)hipFree(buf[j]);
+      (void)hipGetLastError();
+      return set_error(LQCD_ENOMEM, "autotune scratch allocation failed");
+    }
+    (void)hipMemsetAsync(buf[k], 0, bytes, c->stream);
   }
-  (void)hipMemsetAsync(in, 0, bytes, c->stream);
+  const bool verbose = std::getenv("LQCD_TUNE_VERBOSE") != nullptr;
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   const int blocks[] = {64, 128, 192, 256};
   Entry best;
   best.us = 1e30;
-  const int save_b = c->hop_block[prec], save_r = c->hop_remap[prec];
+  const int save_b = c->hop_block[prec], save_r = c->hop_remap[prec], save_nt = c->hop_nt[prec],
+            save_s = c->hop_split[prec];
   int status = LQCD_OK;
-  for (int remap = 0; remap < 2 && status == LQCD_OK; ++remap)
+  for (int split : {1, 4})
+  for (int nt = 0; nt < 2 && status == LQCD_OK; ++nt)
+  for (int remap = 0; remap < 3 && status == LQCD_OK; ++remap)
     for (int b : blocks) {
+      if (remap == 2 && c->g.lz % 8 != 0) continue;
       c->hop_block[prec] = b;
       c->hop_remap[prec] = remap;
-      for (int w = 0; w < 3 && status == LQCD_OK; ++w) status = op_hop(c, prec, 0, in, out, 1.0);
+      c->hop_nt[prec] = nt;
+      c->hop_split[prec] = split;
+      for (int w = 0; w < 3 && status == LQCD_OK; ++w) status = op_hop(c, prec, 0, buf[w], buf[NB + w], 1.0);
       (void)hipEventRecord(e0, c->stream);
-      const int reps = 20;
-      for (int r = 0; r < reps && status == LQCD_OK; ++r) status = op_hop(c, prec, r & 1, r & 1 ? out : in, r & 1 ? in : out, 1.0);
+      const int reps = 24;
+      for (int r = 0; r < reps && status == LQCD_OK; ++r) status = op_hop(c, prec, 0, buf[r % NB], buf[NB + r % NB], 1.0);
       (void)hipEventRecord(e1, c->stream);
       (void)hipEventSynchronize(e1);
       if (status != LQCD_OK) break;
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
       const double us = 1000.0 * ms / reps;
+      if (verbose)
+        std::fprintf(stderr, "[lqcd tune] %s split %d block %d remap %d nt %d: %.2f us\n", key_of(c, prec).c_str(),
+                     split, b, remap, nt, us);
       if (us < best.us) {
         best.us = us;
         best.block = b;
         best.remap = remap;
+        best.nt = nt;
+        best.split = split;
       }
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(in);
-  (void)hipFree(out);
+  for (void* p : buf) (void)hipFree(p);
   if (status != LQCD_OK) {
     c->hop_block[prec] = save_b;
     c->hop_remap[prec] = save_r;
+    c->hop_nt[prec] = save_nt;
+    c->hop_split[prec] = save_s;
     return status;
   }
   c->hop_block[prec] = best.block;
   c->hop_remap[prec] = best.remap;
+  c->hop_nt[prec] = best.nt;
+  c->hop_split[prec] = best.split;
   std::string p = path ? path : "";
   if (p.empty()) {
     const char* env = std::getenv("LQCD_TUNE_CACHE");
@@ -169,5 +201,22 @@ extern "C" int lqcd_autotune(lqcd_ctx* c, int prec, const char* path) {
     m[key_of(c, prec)] = best;
     if (!write_cache(p, m)) return set_error(LQCD_EINVAL, "cannot write tune cache " + p);
   }
+  return LQCD_OK;
+}
+
+extern "C" int lqcd_set_hop_shape(lqcd_ctx* c, int prec, int block, int split, int xcd_map, int nt) {
+  if (!c) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  Entry e;
+  e.block = block;
+  e.split = split;
+  e.remap = xcd_map;
+  e.nt = nt;
+  if (!valid(e)) return set_error(LQCD_EINVAL, "bad hop launch shape");
+  if (xcd_map == 2 && c->g.lz % 8 != 0) return set_error(LQCD_EINVAL, "XCD z-slabs need Lz divisible by 8");
+  c->hop_block[prec] = block;
+  c->hop_split[prec] = split;
+  c->hop_remap[prec] = xcd_map;
+  c->hop_nt[prec] = nt;
   return LQCD_OK;
 }

@@ -30,7 +30,8 @@ OPS = {"D": D, "DEE": DEE, "DOO": DOO, "DEO": DEO, "DOE": DOE, "DPREC_PAPER": DP
 
 EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply",
             "lqcd_default_params", "lqcd_solve", "lqcd_solve_batch", "lqcd_field_bytes", "lqcd_import",
-            "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_strerror", "lqcd_last_error"]
+            "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_strerror",
+            "lqcd_last_error"]
 
 
 class SolveParams(C.Structure):
@@ -88,12 +89,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_export.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_apply_native.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_autotune.argtypes = [vp, ip, C.c_char_p]
+    lib.lqcd_set_hop_shape.argtypes = [vp, ip, ip, ip, ip, ip]
     lib.lqcd_strerror.argtypes = [ip]
     lib.lqcd_strerror.restype = C.c_char_p
     lib.lqcd_last_error.argtypes = []
     lib.lqcd_last_error.restype = C.c_char_p
     for name in ("lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply", "lqcd_solve",
-                 "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune"):
+                 "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune",
+                 "lqcd_set_hop_shape"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -237,6 +240,24 @@ class Lattice:
         op = OPS[op] if isinstance(op, str) else int(op)
         _check(self._call(self.lib.lqcd_apply_native, self.handle, op, int(prec), _ptr(native_in)[0],
                           _ptr(native_out)[0]), "lqcd_apply_native")
+
+    def apply_native_repeat(self, op, prec, ins, outs, reps: int):
+        """reps launches of one native operator, cycling over the (in, out)
+        pairs, enqueued back to back (one stream ordering for the whole loop)."""
+        op = OPS[op] if isinstance(op, str) else int(op)
+        pi = [_ptr(t)[0] for t in ins]
+        po = [_ptr(t)[0] for t in outs]
+        self._enter()
+        try:
+            for r in range(int(reps)):
+                k = r % len(pi)
+                _check(self.lib.lqcd_apply_native(self.handle, op, int(prec), pi[k], po[k]), "lqcd_apply_native")
+        finally:
+            self._exit()
+
+    def set_hop_shape(self, prec: int, block: int = 256, split: int = 1, xcd_map: int = 1, nt: int = 0):
+        _check(self.lib.lqcd_set_hop_shape(self.handle, int(prec), int(block), int(split), int(xcd_map), int(nt)),
+               "lqcd_set_hop_shape")
 
     def autotune(self, prec: int, path: str | None = None):
         _check(self._call(self.lib.lqcd_autotune, self.handle, int(prec), path.encode() if path else None),

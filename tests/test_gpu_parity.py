@@ -54,6 +54,22 @@ def case(dims, csw, t_bc):
 OPNAMES = ["D", "DEE", "DOO", "DEO", "DOE", "HOP_EO", "HOP_OE", "DPREC_SCHUR", "DPREC_PAPER", "DEE_INV", "DOO_INV"]
 
 
+# hop launch shapes: (block, lanes per site, block-to-XCD mapping, non-temporal links)
+SHAPES = [(256, 1, 1, 0), (64, 4, 1, 1), (192, 4, 0, 0), (128, 1, 0, 1), (128, 1, 2, 1), (256, 4, 2, 0)]
+
+
+def shapes_for(dims):
+    return [s for s in SHAPES if s[2] != 2 or dims[2] % 8 == 0]
+REFS = {}
+
+
+def oracle_ref(key, op, name, psi):
+    k = key + (name,)
+    if k not in REFS:
+        REFS[k] = oracle_op(op, name, psi)
+    return REFS[k]
+
+
 @pytest.mark.parametrize("dims", DIMS)
 @pytest.mark.parametrize("csw", [0.0, 1.0])
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -61,14 +77,32 @@ def test_apply_matches_oracle(dims, csw, prec):
     U, psi, op, lat = case(dims, csw, -1)
     x = to_dev(psi)
     out = to_dev(np.zeros_like(psi))
-    worst = {}
-    for name in OPNAMES:
-        lat.apply(name, prec, x, out)
-        got = from_dev(out)
-        ref = oracle_op(op, name, psi)
-        worst[name] = dirac.rel_l2(got, ref)
-    bad = {k: v for k, v in worst.items() if not v <= TOL[prec]}
+    bad = {}
+    for shape in shapes_for(dims):
+        lat.set_hop_shape(prec, *shape)
+        for name in OPNAMES:
+            lat.apply(name, prec, x, out)
+            err = dirac.rel_l2(from_dev(out), oracle_ref((dims, csw), op, name, psi))
+            if not err <= TOL[prec]:
+                bad[(shape, name)] = err
+    lat.set_hop_shape(prec)
     assert not bad, f"{dims} csw={csw} prec={prec}: {bad}"
+
+
+def test_launch_shapes_agree_in_fp64():
+    """The FP64 operator does not depend on the launch shape beyond the order in
+    which the eight hops of a site are added."""
+    U, psi, op, lat = case((4, 6, 8, 10), 1.0, -1)
+    x = to_dev(psi)
+    outs = []
+    for shape in shapes_for((4, 6, 8, 10)):
+        lat.set_hop_shape(0, *shape)
+        out = to_dev(np.zeros_like(psi))
+        lat.apply("DPREC_SCHUR", 0, x, out)
+        outs.append(from_dev(out))
+    lat.set_hop_shape(0)
+    for o in outs[1:]:
+        assert np.abs(o - outs[0]).max() <= 1e-14 * np.abs(outs[0]).max()
 
 
 def test_periodic_time_boundary():

@@ -34,11 +34,14 @@ def test_wilson_haar_8(prec, graph):
 
 
 @pytest.mark.parametrize("prec", [lqcd.F64, lqcd.F32, lqcd.F16])
-def test_clover_smooth(prec):
+@pytest.mark.parametrize("split", [1, 4])
+def test_clover_smooth(prec, split):
     dims = (8, 8, 8, 8)
     U = fg.gauge_field(dims, 1003, "smooth", 0.3)
     b = fg.gaussian_spinor(dims, 1003)
     lat = lattice(dims, U, 0.137, 1.0)
+    for p in (lqcd.F64, lqcd.F32, lqcd.F16):
+        lat.set_hop_shape(p, 128 if split == 4 else 256, split, 1, 1)
     x = to_dev(np.zeros_like(b))
     st = lat.solve(to_dev(b), x, inner_prec=prec)
     r = true_residual(dirac.Operator(U, 0.137, 1.0), from_dev(x), b)
