@@ -37,9 +37,13 @@ static void dfree(void*& p) {
 
 static size_t full_sites(const lqcd_ctx* c) { return (size_t)c->g.vh * 2; }
 
-static int ensure_apply_buffers(lqcd_ctx* c, int prec) {
+int ensure_canon(lqcd_ctx* c) {
   LQ_TRY(dalloc(&c->canon_a, full_sites(c) * 192));
-  LQ_TRY(dalloc(&c->canon_b, full_sites(c) * 192));
+  return dalloc(&c->canon_b, full_sites(c) * 192);
+}
+
+static int ensure_apply_buffers(lqcd_ctx* c, int prec) {
+  LQ_TRY(ensure_canon(c));
   const size_t b = spinor_bytes(prec, c->g.vh);
   LQ_TRY(dalloc(&c->half_a[prec], b));
   LQ_TRY(dalloc(&c->half_b[prec], b));

@@ -9,8 +9,7 @@
 // kernels also compute the next scalars (the solver's global reductions, of up
 // to three values at once, the pattern the paper credits for solver
 // efficiency in Sec. 3).
-#include "blas.h"
-#include "fieldio.h"
+#include "blascore.h"
 
 namespace lq {
 
@@ -21,103 +20,39 @@ constexpr int FBS = 1024;  // threads of the one-block finalize kernels
 
 __device__ inline bool is_done(const Scal* s) { return s && s->done; }
 
-template <typename T>
-__device__ inline cx<T> ld(const double* re_im) {
-  return {(T)re_im[0], (T)re_im[1]};
-}
-
 // p = r + beta (p - omega v)
 template <int P>
 __global__ void __launch_bounds__(BS) k_p_update(const void* r, void* p, const void* v, const Scal* sc, size_t vh) {
-  using T = typename IO<P>::T;
   if (is_done(sc)) return;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= vh) return;
-  const cx<T> beta = ld<T>(&sc->beta_r), omega = ld<T>(&sc->omega_r);
-  cx<T> a[12], b[12], c[12];
-  IO<P>::load_spinor(r, vh, i, a);
-  IO<P>::load_spinor(p, vh, i, b);
-  IO<P>::load_spinor(v, vh, i, c);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) b[k] = a[k] + beta * (b[k] - omega * c[k]);
-  IO<P>::store_spinor(p, vh, i, b);
+  if (i < vh) p_update_site<P>(r, p, v, sc, vh, i);
 }
 
 // s = r - alpha v
 template <int P>
 __global__ void __launch_bounds__(BS) k_s_update(const void* r, const void* v, void* s, const Scal* sc, size_t vh) {
-  using T = typename IO<P>::T;
   if (is_done(sc)) return;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= vh) return;
-  const cx<T> alpha = ld<T>(&sc->alpha_r);
-  cx<T> a[12], c[12];
-  IO<P>::load_spinor(r, vh, i, a);
-  IO<P>::load_spinor(v, vh, i, c);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) a[k] = a[k] - alpha * c[k];
-  IO<P>::store_spinor(s, vh, i, a);
+  if (i < vh) s_update_site<P>(r, v, s, sc, vh, i);
 }
 
 // x += alpha p + omega s (x in precision PX); r = s - omega t; partials <rhat, r>, <r, r>
 template <int P, int PX>
 __global__ void __launch_bounds__(BS) k_xr_update(void* x, const void* p, const void* s, const void* t, void* r,
                                                   const void* rhat, const Scal* sc, double* partials, size_t vh) {
-  using T = typename IO<P>::T;
-  using TX = typename IO<PX>::T;
   if (is_done(sc)) return;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
   double red[3] = {0.0, 0.0, 0.0};
-  if (i < vh) {
-    const cx<T> alpha = ld<T>(&sc->alpha_r), omega = ld<T>(&sc->omega_r);
-    const cx<TX> alx = ld<TX>(&sc->alpha_r), omx = ld<TX>(&sc->omega_r);
-    cx<T> pv[12], sv[12], tv[12];
-    cx<TX> xv[12];
-    IO<P>::load_spinor(p, vh, i, pv);
-    IO<P>::load_spinor(s, vh, i, sv);
-    IO<PX>::load_spinor(x, vh, i, xv);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const cx<TX> pk = {(TX)pv[k].r, (TX)pv[k].i}, sk = {(TX)sv[k].r, (TX)sv[k].i};
-      xv[k] = xv[k] + alx * pk + omx * sk;
-    }
-    IO<PX>::store_spinor(x, vh, i, xv);
-    IO<P>::load_spinor(t, vh, i, tv);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) sv[k] = sv[k] - omega * tv[k];
-    IO<P>::store_spinor(r, vh, i, sv);
-    // FP16 codes round the stored value: reduce what was stored
-    if (P == 2) IO<P>::load_spinor(r, vh, i, sv);
-    IO<P>::load_spinor(rhat, vh, i, tv);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const cx<T> d = cmulc(tv[k], sv[k]);
-      red[0] += (double)d.r;
-      red[1] += (double)d.i;
-      red[2] += (double)sv[k].r * (double)sv[k].r + (double)sv[k].i * (double)sv[k].i;
-    }
-  }
+  if (i < vh) xr_update_site<P, PX>(x, p, s, t, r, rhat, sc, vh, i, red);
   block_reduce<3>(red, partials + (size_t)blockIdx.x * 3);
 }
 
 // partials <a, b> (re, im) and <b, b>
 template <int P>
 __global__ void __launch_bounds__(BS) k_dot_norm(const void* a, const void* b, double* partials, size_t vh) {
-  using T = typename IO<P>::T;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
   double red[3] = {0.0, 0.0, 0.0};
-  if (i < vh) {
-    cx<T> av[12], bv[12];
-    IO<P>::load_spinor(a, vh, i, av);
-    IO<P>::load_spinor(b, vh, i, bv);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const cx<T> d = cmulc(av[k], bv[k]);
-      red[0] += (double)d.r;
-      red[1] += (double)d.i;
-      red[2] += (double)bv[k].r * (double)bv[k].r + (double)bv[k].i * (double)bv[k].i;
-    }
-  }
+  if (i < vh) dot_norm_site<P>(a, b, vh, i, red);
   block_reduce<3>(red, partials + (size_t)blockIdx.x * 3);
 }
 
@@ -173,61 +108,14 @@ __global__ void __launch_bounds__(BS) k_accum_up(void* x, const void* e, const d
 
 template <int P>
 __global__ void __launch_bounds__(BS) k_copy(const void* src, void* dst, size_t vh) {
-  using T = typename IO<P>::T;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= vh) return;
-  cx<T> a[12];
-  IO<P>::load_spinor(src, vh, i, a);
-  IO<P>::store_spinor(dst, vh, i, a);
+  if (i < vh) copy_site<P>(src, dst, vh, i);
 }
 
 template <int P>
 __global__ void __launch_bounds__(BS) k_zero(void* dst, size_t vh) {
-  using T = typename IO<P>::T;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= vh) return;
-  cx<T> a[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) a[k] = {T(0), T(0)};
-  IO<P>::store_spinor(dst, vh, i, a);
-}
-
-// Sum n partial records of `width` doubles in a fixed order into out[0..width).
-template <int W>
-__device__ inline void sum_partials(const double* partials, int n, double out[W]) {
-  // four independent partial sums per thread keep four loads in flight; the
-  // order of additions is fixed by (n, blockDim), so the result is reproducible
-  double v[4][W];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int k = 0; k < W; ++k) v[u][k] = 0.0;
-  const int step = blockDim.x;
-  int j = threadIdx.x;
-  for (; j + 3 * step < n; j += 4 * step)
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int k = 0; k < W; ++k) v[u][k] += partials[(size_t)(j + u * step) * W + k];
-  for (; j < n; j += step)
-#pragma unroll
-    for (int k = 0; k < W; ++k) v[0][k] += partials[(size_t)j * W + k];
-#pragma unroll
-  for (int k = 0; k < W; ++k) v[0][k] = (v[0][k] + v[1][k]) + (v[2][k] + v[3][k]);
-  __shared__ double res[W];
-  double tmp[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) tmp[k] = v[0][k];
-  block_reduce<W>(tmp, res);
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < W; ++k) out[k] = res[k];
-}
-
-__device__ inline void cdiv(double ar, double ai, double br, double bi, double& cr, double& ci) {
-  const double d = br * br + bi * bi;
-  cr = (ar * br + ai * bi) / d;
-  ci = (ai * br - ar * bi) / d;
+  if (i < vh) zero_site<P>(dst, vh, i);
 }
 
 // alpha = rho / <rhat, v>
@@ -235,14 +123,7 @@ __global__ void __launch_bounds__(FBS) k_fin_alpha(Scal* sc, const double* parti
   if (sc->done) return;
   double v[2];
   sum_partials<2>(partials, n, v);
-  if (threadIdx.x == 0) {
-    if (v[0] == 0.0 && v[1] == 0.0) {
-      sc->breakdown = 1;
-      sc->done = 1;
-      return;
-    }
-    cdiv(sc->rho_r, sc->rho_i, v[0], v[1], sc->alpha_r, sc->alpha_i);
-  }
+  if (threadIdx.x == 0) scal_alpha(sc, v);
 }
 
 // omega = <t, s> / <t, t>
@@ -250,15 +131,7 @@ __global__ void __launch_bounds__(FBS) k_fin_omega(Scal* sc, const double* parti
   if (sc->done) return;
   double v[3];
   sum_partials<3>(partials, n, v);
-  if (threadIdx.x == 0) {
-    if (v[2] == 0.0) {
-      sc->omega_r = 0.0;
-      sc->omega_i = 0.0;
-    } else {
-      sc->omega_r = v[0] / v[2];
-      sc->omega_i = v[1] / v[2];
-    }
-  }
+  if (threadIdx.x == 0) scal_omega(sc, v);
 }
 
 // rho_new = <rhat, r>, rr = <r, r>; beta = (rho_new / rho)(alpha / omega); convergence test
@@ -266,51 +139,15 @@ __global__ void __launch_bounds__(FBS) k_fin_rho(Scal* sc, const double* partial
   if (sc->done) return;
   double v[3];
   sum_partials<3>(partials, n, v);
-  if (threadIdx.x == 0) {
-    sc->iters += 1;
-    sc->rr = v[2];
-    if (v[2] <= sc->target2 || !(v[2] == v[2])) {
-      sc->done = 1;
-      if (!(v[2] == v[2])) sc->breakdown = 1;
-      return;
-    }
-    if ((v[0] == 0.0 && v[1] == 0.0) || (sc->omega_r == 0.0 && sc->omega_i == 0.0)) {
-      sc->breakdown = 1;
-      sc->done = 1;
-      return;
-    }
-    double qr, qi, ar, ai;
-    cdiv(v[0], v[1], sc->rho_r, sc->rho_i, qr, qi);
-    cdiv(sc->alpha_r, sc->alpha_i, sc->omega_r, sc->omega_i, ar, ai);
-    sc->beta_r = qr * ar - qi * ai;
-    sc->beta_i = qr * ai + qi * ar;
-    sc->rho_r = v[0];
-    sc->rho_i = v[1];
-    if (sc->iters >= sc->max_iters) sc->done = 1;
-  }
+  if (threadIdx.x == 0) scal_rho(sc, v);
 }
 
 // Start of a (re)start: rho = <rhat, r>, rr = <r, r>, alpha = omega = 1.
 __global__ void __launch_bounds__(FBS) k_fin_init(Scal* sc, const double* partials, int n, double target2,
-                                                 int max_iters) {
+                                                  int max_iters) {
   double v[3];
   sum_partials<3>(partials, n, v);
-  if (threadIdx.x == 0) {
-    sc->rho_r = v[0];
-    sc->rho_i = v[1];
-    sc->rr = v[2];
-    sc->alpha_r = 1.0;
-    sc->alpha_i = 0.0;
-    sc->omega_r = 1.0;
-    sc->omega_i = 0.0;
-    sc->beta_r = 0.0;
-    sc->beta_i = 0.0;
-    sc->target2 = target2;
-    sc->done = (v[2] <= target2) ? 1 : 0;
-    sc->breakdown = 0;
-    sc->max_iters = max_iters;
-    sc->iters = 0;
-  }
+  if (threadIdx.x == 0) scal_init(sc, v, target2, max_iters);
 }
 
 // out[0] = sum of n partials (width 1 or 3, component `comp`); out[1] = 1/sqrt(out[0]) (0 if out[0] == 0)

@@ -146,6 +146,9 @@ int set_error(int status, const std::string& msg);
     if (s_ != LQCD_OK) return s_; \
   } while (0)
 
+// api.hip: the two canonical full-lattice staging vectors of a context
+int ensure_canon(lqcd_ctx* c);
+
 // ---------------------------------------------------------------- kernels (host launchers)
 // layout.hip
 int launch_import_spinor(lqcd_ctx* c, int prec, int parity, const double* canon, void* half);

@@ -159,15 +159,23 @@ class Lattice:
     """
 
     def __init__(self, dims, t_bc: int = -1, stream=None):
+        """stream: None (a torch stream of its own when torch sees a GPU), a
+        torch.cuda.Stream (share it, e.g. across the lattices of one batched
+        solve), or a raw hipStream_t handle."""
         lib = load()
         self.dims = tuple(int(d) for d in dims)
         arr = (C.c_int * 4)(*self.dims)
         h = C.c_void_p()
         self.stream = None
-        torch = _torch_cuda() if stream is None else None
-        if torch is not None:
-            self.stream = torch.cuda.Stream()
-            stream = self.stream.cuda_stream
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            # a torch stream, possibly shared with other lattices (batched solves)
+            self.stream = stream
+            stream = stream.cuda_stream
+        elif stream is None:
+            torch = _torch_cuda()
+            if torch is not None:
+                self.stream = torch.cuda.Stream()
+                stream = self.stream.cuda_stream
         s = C.c_void_p(int(stream)) if stream is not None else None
         _check(lib.lqcd_create(arr, int(t_bc), s, C.byref(h)), "lqcd_create")
         self.handle = h
