@@ -1,9 +1,9 @@
-"""Benchmark of the even-odd Wilson Dslash and BiCGStab on one MI355X.
+"""Benchmark of the even-odd Wilson/clover Dslash and BiCGStab on one MI355X.
 
-Workload (default): 32^3 x 64 lattice, Wilson operator, links
-U = exp(0.3 i H) (H random traceless Hermitian), kappa = 0.1350, Gaussian
-source, antiperiodic in time; even-odd preconditioned BiCGStab to a true FP64
-residual of 1e-10.
+Default workload (the configuration the metric is quoted on): 32^3 x 64
+lattice, Wilson operator, links U = exp(0.3 i H) (H random traceless
+Hermitian), kappa = 0.1350, Gaussian source, antiperiodic in time, even-odd
+preconditioned BiCGStab to a true FP64 residual of 1e-10.
 
 One timed step = one whole solve through the hot path: source preparation,
 FP32 inner BiCGStab (Dslash, fused BLAS-1 and reductions, device scalars,
@@ -17,7 +17,14 @@ timed wall clock. The JSON line also carries the Dslash kernel's roofline
 (HIP events on the library's stream), the FP64-vs-mixed solve comparison and
 the CPU oracle baseline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Other workloads (not the headline line; same JSON shape):
+  --workload clover  32^3x64 clover, c_SW = 1.0, kappa = 0.1370, eps = 0.3
+  --workload batch   12 point sources on each of 32^3x64, 24^3x48, 16^3x32
+                     clover lattices (own fields), one batched solve per step,
+                     against 36 sequential single-RHS FP64 solves
+  --workload large   64^3x128 clover, eps = 0.25, kappa = 0.1372
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 
 from __future__ import annotations
@@ -37,13 +44,22 @@ sys.path.insert(0, ROOT)
 import fieldgen as fg  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-DIMS = (32, 32, 32, 64)
-KAPPA = 0.1350
-EPS = 0.3
-SEED = 1002
 HOP_FLOPS = 1320
 # algorithmic bytes per output site of one hop: 8 links x 12 reals + 24 in + 24 out
 HOP_BYTES = {0: (8 * 12 + 48) * 8, 1: (8 * 12 + 48) * 4, 2: 8 * 12 * 2 + 48 * 2 + 2 * 4}
+DIMS = (32, 32, 32, 64)
+KAPPA = 0.1350
+SEED = 1002
+
+WORKLOADS = {
+    "wilson": dict(dims=(32, 32, 32, 64), eps=0.3, kappa=0.1350, csw=0.0, seed=1002,
+                   text="32^3x64 Wilson even-odd BiCGStab, kappa=0.1350, eps=0.3, antiperiodic t"),
+    "clover": dict(dims=(32, 32, 32, 64), eps=0.3, kappa=0.1370, csw=1.0, seed=1003,
+                   text="32^3x64 clover (c_SW=1.0) even-odd BiCGStab, kappa=0.1370, eps=0.3, antiperiodic t"),
+    "large": dict(dims=(64, 64, 64, 128), eps=0.25, kappa=0.1372, csw=1.0, seed=1005,
+                  text="64^3x128 clover (c_SW=1.0) even-odd BiCGStab, kappa=0.1372, eps=0.25, antiperiodic t"),
+}
+BATCH = [((32, 32, 32, 64), 1004), ((24, 24, 24, 48), 1005), ((16, 16, 16, 32), 1006)]
 
 
 def log(msg):
@@ -51,17 +67,17 @@ def log(msg):
 
 
 def _slice(args):
-    kind, dims, seed, t = args
+    kind, dims, seed, eps, t = args
     if kind == "gauge":
-        return fg.gauge_field(dims, seed, "smooth", EPS, t_slices=[t])
+        return fg.gauge_field(dims, seed, "smooth", eps, t_slices=[t])
     return fg.gaussian_spinor(dims, seed, t_slices=[t])
 
 
-def generate(dims, seed, workers=8):
+def generate(dims, seed, eps=0.3, workers=8, source=True):
     lt = dims[3]
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        U = np.concatenate(list(ex.map(_slice, [("gauge", dims, seed, t) for t in range(lt)])))
-        b = np.concatenate(list(ex.map(_slice, [("src", dims, seed, t) for t in range(lt)])))
+        U = np.concatenate(list(ex.map(_slice, [("gauge", dims, seed, eps, t) for t in range(lt)])))
+        b = np.concatenate(list(ex.map(_slice, [("src", dims, seed, eps, t) for t in range(lt)]))) if source else None
     return U, b
 
 
@@ -75,6 +91,7 @@ def time_hop(torch, lat, prec, reps=40, nbuf=3):
     src = torch.from_numpy(fg.gaussian_spinor(lat.dims, 5)).cuda()
     for t in ins:
         lat.import_field(prec, 1, src, t)
+    del src
     lat.apply_native_repeat("HOP_EO", prec, ins, outs, 3)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -103,12 +120,13 @@ def copy_probe(torch, mib=1024):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x64.txt")
+KERNEL_SOURCES = ("hop.hip", "hopcore.h", "fieldio.h")
 
 
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("hop.hip", "fieldio.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2303_05883_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -135,27 +153,184 @@ def measured_traffic(prec_name):
     return None
 
 
-def hop_applications(st, inner_prec):
+def hop_applications(st):
     """Hop launches of one solve: 4 per BiCGStab iteration (two Schur applies of
     two hops), 2 per FP64 residual (one per outer pass plus the initial one), 1
     for the source, 1 for the reconstruction and 2 for the final full-D residual."""
     return 4 * st.inner_iters + 2 * (st.outer_iters + 1) + 1 + 1 + 2
 
 
-def cpu_baseline(U, b, budget_s=30.0):
-    """The CPU oracle's hopping term on the same 32^3 x 64 field (one full-lattice
+def cpu_baseline(U, b, dims):
+    """The CPU oracle's hopping term on the same field (one full-lattice
     application = 1320 flop x V), timed on the host."""
     from oracle import dirac
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     reps = 2
     t0 = time.perf_counter()
     for _ in range(reps):
         dirac.hop(U, b, -1)
     dt = (time.perf_counter() - t0) / reps
-    v = int(np.prod(DIMS))
+    v = int(np.prod(dims))
     return {"value": round(HOP_FLOPS * v / dt / 1e9, 4), "unit": "GFlop/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} oracle hopping-term applications H psi on the full 32^3x64 lattice "
+            "sample": f"{reps} oracle hopping-term applications H psi on the full {dims[0]}^3x{dims[3]} lattice "
                       f"(1320 flop/site x {v} sites each, NumPy float64, one thread), {dt:.1f} s each"}
+
+
+def make_lattice(torch, lqcd, dims, seed, eps, kappa, csw, stream=None, source=True):
+    t0 = time.perf_counter()
+    U, b = generate(dims, seed, eps, source=source)
+    log(f"{dims} fields generated in {time.perf_counter() - t0:.1f} s")
+    lat = lqcd.Lattice(dims, -1, stream=stream)
+    Ud = torch.from_numpy(U).cuda()
+    lat.set_gauge(Ud)
+    del Ud
+    lat.set_clover(kappa, csw)
+    return lat, U, b
+
+
+def tune(lat, lqcd, cached, label):
+    if cached:
+        log(f"launch shapes of {label} from the tune cache")
+        return
+    for p in (lqcd.F64, lqcd.F32, lqcd.F16):
+        lat.autotune(p)
+    log(f"autotuned {label}")
+
+
+def roofline_of(torch, lat, lqcd, dom, vh):
+    hop = {}
+    for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.F16, "f16")):
+        ms = time_hop(torch, lat, p)
+        gbs = HOP_BYTES[p] * vh / (ms * 1e-3) / 1e9
+        hop[name] = {"us": round(1000 * ms, 2), "gflops": round(HOP_FLOPS * vh / (ms * 1e-3) / 1e9, 1),
+                     "gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"hop kernel: {hop}")
+    pd = 1 if dom == "f32" else 2
+    roof = {"bound": "hbm", "achieved": hop[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": hop[dom]["frac_hbm"],
+            "traffic": measured_traffic(dom) if tuple(lat.dims) == DIMS else None,
+            "kernel": f"k_hop<{pd},EPI_SCALE> (Dslash, {dom} storage)",
+            "bytes_per_launch": HOP_BYTES[pd] * vh}
+    return roof, hop
+
+
+def compare_solves(torch, lat, lqcd, bd):
+    out = {}
+    for name, prec in (("f64", lqcd.F64), ("mixed_f32", lqcd.F32), ("mixed_f16", lqcd.F16)):
+        xs = torch.zeros_like(bd)
+        lat.solve(bd, xs, inner_prec=prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s = lat.solve(bd, xs, inner_prec=prec)
+        torch.cuda.synchronize()
+        out[name] = {"ms": round(1000 * (time.perf_counter() - t1), 2), "outer": s.outer_iters,
+                     "inner": s.inner_iters, "true_rel_resid": s.true_rel_resid}
+    for name in ("mixed_f32", "mixed_f16"):
+        out[name]["speedup_vs_f64"] = round(out["f64"]["ms"] / out[name]["ms"], 3)
+    log(f"solve comparison: {out}")
+    return out
+
+
+def run_single(a, torch, lqcd):
+    w = WORKLOADS[a.workload]
+    dims = w["dims"]
+    vh = int(np.prod(dims)) // 2
+    lat, U, b = make_lattice(torch, lqcd, dims, w["seed"], w["eps"], w["kappa"], w["csw"])
+    bd = torch.from_numpy(b).cuda()
+    tune(lat, lqcd, a.cached, str(dims))
+    inner = lqcd.F32 if a.inner == "f32" else lqcd.F16
+    if a.kernels_only:
+        for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.F16, "f16")):
+            ms = time_hop(torch, lat, p, reps=10)
+            log(f"hop {name}: {1000 * ms:.2f} us, {HOP_BYTES[p] * vh / (ms * 1e-3) / 1e9:.1f} GB/s")
+        log(f"copy probe: {copy_probe(torch, mib=512):.1f} GB/s (512 MiB read + 512 MiB written per launch)")
+        return None
+    x = torch.zeros_like(bd)
+    st = None
+    for _ in range(a.warmup):
+        st = lat.solve(bd, x, inner_prec=inner)
+    log(f"warmup solve: {st}")
+
+    # ---- timed region: K whole solves
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = [lat.solve(bd, x, inner_prec=inner) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    worst = max(s.true_rel_resid for s in stats)
+    if not worst <= 1e-10:
+        log(f"true residual {worst} above 1e-10")
+        sys.exit(1)
+    value = HOP_FLOPS * vh * sum(hop_applications(s) for s in stats) / elapsed / 1e9
+    ms_step = 1000 * elapsed / a.steps
+    log(f"timed {a.steps} solves: {ms_step:.1f} ms each, {stats[-1]}")
+
+    dom = "f32" if inner == lqcd.F32 else "f16"
+    roof, hop = roofline_of(torch, lat, lqcd, dom, vh)
+    roof["copy_gbs"] = round(copy_probe(torch), 1)
+    compare = None if a.no_compare else compare_solves(torch, lat, lqcd, bd)
+    cpu = None if (a.no_cpu or a.workload != "wilson") else cpu_baseline(U, b, dims)
+    if cpu:
+        log(f"cpu baseline: {cpu}")
+    config = {"workload": w["text"] + f", {a.inner} inner / f64 outer to true residual 1e-10",
+              "lattice": list(dims), "kappa": w["kappa"], "csw": w["csw"], "step": "one whole solve",
+              "inner_iters_per_solve": stats[-1].inner_iters, "outer_iters_per_solve": stats[-1].outer_iters,
+              "parallelism": "single GPU"}
+    return value, ms_step, config, roof, hop, compare, cpu, inner
+
+
+def run_batch(a, torch, lqcd):
+    stream = torch.cuda.Stream()
+    lats, bs, xs = [], [], []
+    vhs = []
+    for dims, seed in BATCH:
+        lat, U, _ = make_lattice(torch, lqcd, dims, seed, 0.3, 0.1370, 1.0, stream=stream, source=False)
+        del U
+        tune(lat, lqcd, a.cached, str(dims))
+        src = np.stack([fg.point_source(dims, k // 3, k % 3) for k in range(12)])
+        lats.append(lat)
+        bs.append(torch.from_numpy(src).cuda())
+        xs.append(torch.zeros_like(bs[-1]))
+        vhs.append(int(np.prod(dims)) // 2)
+    inner = lqcd.F32 if a.inner == "f32" else lqcd.F16
+    for _ in range(a.warmup):
+        lqcd.solve_batch(lats, bs, xs, inner_prec=inner)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = None
+    for _ in range(a.steps):
+        stats = lqcd.solve_batch(lats, bs, xs, inner_prec=inner)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    worst = max(s.true_rel_resid for s in stats)
+    if not worst <= 1e-10:
+        log(f"true residual {worst} above 1e-10")
+        sys.exit(1)
+    seg_vh = [vh for vh in vhs for _ in range(12)]
+    flops = sum(HOP_FLOPS * vh * hop_applications(s) for vh, s in zip(seg_vh, stats)) * a.steps
+    value = flops / elapsed / 1e9
+    ms_step = 1000 * elapsed / a.steps
+    props = 3 * a.steps / elapsed
+    log(f"timed {a.steps} batched solves of 36 RHS: {ms_step:.1f} ms each, {props:.2f} propagators/s")
+    compare = None
+    if not a.no_compare:
+        # the same 36 right-hand sides one after another, plain FP64 BiCGStab
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for lat, b, x in zip(lats, bs, xs):
+            for r in range(12):
+                lat.solve(b[r], x[r], inner_prec=lqcd.F64)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t1
+        compare = {"batched_ms": round(ms_step, 2), "sequential_f64_ms": round(1000 * seq, 2),
+                   "propagators_per_s_batched": round(props, 3),
+                   "propagators_per_s_sequential_f64": round(3 / seq, 3),
+                   "speedup": round(seq / (ms_step / 1000), 3)}
+        log(f"batch vs sequential FP64: {compare}")
+    roof, hop = roofline_of(torch, lats[0], lqcd, "f32" if inner == lqcd.F32 else "f16", vhs[0])
+    config = {"workload": "12 point sources on each of 32^3x64, 24^3x48, 16^3x32 clover lattices (c_SW=1.0, "
+                          f"kappa=0.1370, eps=0.3), one batched solve of 36 RHS, {a.inner} inner / f64 outer to 1e-10",
+              "step": "one batched solve", "propagators_per_s": round(props, 3), "parallelism": "single GPU"}
+    return value, ms_step, config, roof, hop, compare, None, inner
 
 
 def main():
@@ -163,6 +338,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large"], default="wilson")
     ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-vs-mixed solve comparison")
@@ -183,92 +359,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    t0 = time.perf_counter()
-    U, b = generate(DIMS, SEED)
-    log(f"fields generated in {time.perf_counter() - t0:.1f} s")
-    vh = int(np.prod(DIMS)) // 2
-    cached = bool(a.tune_cache) and os.path.exists(a.tune_cache)
+    a.cached = bool(a.tune_cache) and os.path.exists(a.tune_cache)
     if a.tune_cache:
         os.environ["LQCD_TUNE_CACHE"] = os.path.abspath(a.tune_cache)
-    lat = lqcd.Lattice(DIMS, -1)
-    Ud = torch.from_numpy(U).cuda()
-    bd = torch.from_numpy(b).cuda()
-    lat.set_gauge(Ud)
-    del Ud
-    lat.set_clover(KAPPA, 0.0)
-    if not cached:
-        for p in (lqcd.F64, lqcd.F32, lqcd.F16):
-            lat.autotune(p)
-        log("autotuned" + (f" (cache {a.tune_cache})" if a.tune_cache else ""))
-    else:
-        log(f"launch shapes from {a.tune_cache}")
-    inner = lqcd.F32 if a.inner == "f32" else lqcd.F16
-    if a.kernels_only:
-        for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.F16, "f16")):
-            ms = time_hop(torch, lat, p, reps=10)
-            log(f"hop {name}: {1000 * ms:.2f} us, {HOP_BYTES[p] * vh / (ms * 1e-3) / 1e9:.1f} GB/s")
-        log(f"copy probe: {copy_probe(torch, mib=512):.1f} GB/s (512 MiB read + 512 MiB written per launch)")
+    res = run_batch(a, torch, lqcd) if a.workload == "batch" else run_single(a, torch, lqcd)
+    if res is None:
         return
-    x = torch.zeros_like(bd)
-    for _ in range(a.warmup):
-        st = lat.solve(bd, x, inner_prec=inner)
-    log(f"warmup solve: {st}")
-
-    # ---- timed region: K whole solves
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    stats = []
-    for _ in range(a.steps):
-        stats.append(lat.solve(bd, x, inner_prec=inner))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    worst = max(s.true_rel_resid for s in stats)
-    if not worst <= 1e-10:
-        log(f"true residual {worst} above 1e-10")
-        sys.exit(1)
-    hops = sum(hop_applications(s, inner) for s in stats)
-    value = HOP_FLOPS * vh * hops / elapsed / 1e9
-    ms_step = 1000 * elapsed / a.steps
-    log(f"timed {a.steps} solves: {ms_step:.1f} ms each, {stats[-1]}")
-
-    # ---- roofline of the Dslash kernel, on the library's stream
-    hop = {}
-    for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.F16, "f16")):
-        ms = time_hop(torch, lat, p)
-        gbs = HOP_BYTES[p] * vh / (ms * 1e-3) / 1e9
-        hop[name] = {"us": round(1000 * ms, 2), "gflops": round(HOP_FLOPS * vh / (ms * 1e-3) / 1e9, 1),
-                     "gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
-    log(f"hop kernel: {hop}")
-    dom = "f32" if inner == lqcd.F32 else "f16"
-    copy_gbs = copy_probe(torch)
-    roofline = {"bound": "hbm", "achieved": hop[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hop[dom]["frac_hbm"], "traffic": measured_traffic(dom),
-                "kernel": f"k_hop<{1 if dom == 'f32' else 2},EPI_SCALE> (Dslash, {dom} storage)",
-                "bytes_per_launch": HOP_BYTES[1 if dom == "f32" else 2] * vh,
-                "copy_gbs": round(copy_gbs, 1)}
-
-    # ---- FP64 vs mixed time to solution
-    compare = None
-    if not a.no_compare:
-        compare = {}
-        for name, prec in (("f64", lqcd.F64), ("mixed_f32", lqcd.F32), ("mixed_f16", lqcd.F16)):
-            xs = torch.zeros_like(bd)
-            lat.solve(bd, xs, inner_prec=prec)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            s = lat.solve(bd, xs, inner_prec=prec)
-            torch.cuda.synchronize()
-            compare[name] = {"ms": round(1000 * (time.perf_counter() - t1), 2), "outer": s.outer_iters,
-                             "inner": s.inner_iters, "true_rel_resid": s.true_rel_resid}
-        for name in ("mixed_f32", "mixed_f16"):
-            compare[name]["speedup_vs_f64"] = round(compare["f64"]["ms"] / compare[name]["ms"], 3)
-        log(f"solve comparison: {compare}")
-
-    cpu = None
-    if not a.no_cpu:
-        cpu = cpu_baseline(U, b)
-        log(f"cpu baseline: {cpu}")
-
+    value, ms_step, config, roof, hop, compare, cpu, inner = res
     out = {
         "metric": "Dslash GFlop/s & %HBM peak; mixed vs FP64 solve time to residual 1e-10",
         "value": round(value, 2),
@@ -281,13 +378,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if inner == lqcd.F32 else "f16+f32+f64",
-        "data": "synthetic (seeded SU(3) links exp(0.3 i H), Gaussian source)",
-        "config": {"workload": "32^3x64 Wilson even-odd BiCGStab, kappa=0.1350, eps=0.3, antiperiodic t, "
-                               f"{a.inner} inner / f64 outer to true residual 1e-10",
-                   "lattice": list(DIMS), "kappa": KAPPA, "step": "one whole solve",
-                   "inner_iters_per_solve": stats[-1].inner_iters, "outer_iters_per_solve": stats[-1].outer_iters,
-                   "parallelism": "single GPU"},
-        "roofline": roofline,
+        "data": "synthetic (seeded SU(3) links exp(i eps H), Gaussian or point sources)",
+        "config": config,
+        "roofline": roof,
         "dslash_kernel": hop,
         "solve_compare": compare,
         "cpu_baseline": cpu,

@@ -171,6 +171,7 @@ int lqcd_create(const int dims[4], int t_bc, void* hip_stream, lqcd_ctx** out) {
 int lqcd_destroy(lqcd_ctx* c) {
   if (!c) return LQCD_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->batch && c->batch_free) c->batch_free(c->batch);
   if (c->ws) {
     c->ws->release();
     delete c->ws;

@@ -212,6 +212,10 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_k = 0;
+  // shape key: (sites per parity, nrhs) per lattice, inner precision, clover
+  std::vector<std::pair<int, int>> key;
+  Scal* dscal_all = nullptr;
+  bool ready = false;  // every buffer allocated
 
   ~Batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -348,6 +352,8 @@ int seg_norm(lqcd_ctx* c, const void* a, double* dst) {
   return fin_norm(c, dst, part, blas_blocks(c->g.vh), 3, 2);
 }
 
+void free_batch(void* p) { delete reinterpret_cast<Batch*>(p); }
+
 }  // namespace
 
 }  // namespace lq
@@ -379,7 +385,23 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
       if (ctxs[m] == c) return set_error(LQCD_EINVAL, "a context appears twice in the batch");
   }
   const int IP = prm.inner_prec;
-  Batch B;
+  std::vector<std::pair<int, int>> key;
+  for (int l = 0; l < nlattices; ++l) key.push_back({ctxs[l]->g.vh, nrhs[l]});
+  key.push_back({IP, clover ? 1 : 0});
+  lqcd_ctx* lead = ctxs[0];
+  Batch* cached = reinterpret_cast<Batch*>(lead->batch);
+  const bool reuse = cached && cached->ready && cached->key == key;
+  if (!reuse && cached) {
+    (void)hipStreamSynchronize(stream);
+    lead->batch_free(cached);
+    lead->batch = nullptr;
+    lead->batch_free = nullptr;
+  }
+  if (!reuse) {
+    lead->batch = new Batch();
+    lead->batch_free = free_batch;
+  }
+  Batch& B = *reinterpret_cast<Batch*>(lead->batch);
   B.stream = stream;
   B.prec = IP;
   B.xprec = IP == 2 ? 1 : IP;
@@ -387,11 +409,17 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   const int check = prm.check_every > 0 ? prm.check_every : 8;
   const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : (IP == 2 ? 1e-3 : 1e-10));
 
-  // descriptors and buffers
+  // descriptors (rebuilt every call from the current contexts) and buffers
+  // (allocated when the batch shape is new)
   int total_seg = 0;
   for (int l = 0; l < nlattices; ++l) total_seg += nrhs[l];
-  Scal* dscal_all = nullptr;
-  LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&dscal_all), (size_t)total_seg * sizeof(Scal)));
+  if (!reuse) {
+    B.key = key;
+    LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dscal_all), (size_t)total_seg * sizeof(Scal)));
+  }
+  Scal* dscal_all = B.dscal_all;
+  B.hlat.clear();
+  B.ctx.clear();
   int tile = 0, btile = 0, seg = 0;
   for (int l = 0; l < nlattices; ++l) {
     lqcd_ctx* c = ctxs[l];
@@ -415,6 +443,7 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
     B.hlat.push_back(L);
     B.ctx.push_back(c);
     for (int r = 0; r < nrhs[l]; ++r, ++seg) {
+      if (reuse) continue;
       BSeg S{};
       const size_t vh = c->g.vh;
       for (int f = 0; f < F_COUNT; ++f)
@@ -433,13 +462,16 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   B.hop_tiles = tile;
   B.blas_tiles = btile;
   for (int k = 0; k <= 8; ++k) B.bound[k] = (int)((long long)tile * k / 8);
-  LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dlat), B.hlat.size() * sizeof(BLat)));
-  LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dseg), B.hseg.size() * sizeof(BSeg)));
-  LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.snorm), (size_t)nseg * 16 * sizeof(double)));
-  LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dtarget), (size_t)nseg * sizeof(double)));
-  if (hipHostMalloc(reinterpret_cast<void**>(&B.htmp), (size_t)nseg * 16 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&B.hscal), (size_t)nseg * sizeof(Scal)) != hipSuccess)
-    return set_error(LQCD_ENOMEM, "pinned host allocation failed");
+  if (!reuse) {
+    LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dlat), B.hlat.size() * sizeof(BLat)));
+    LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dseg), B.hseg.size() * sizeof(BSeg)));
+    LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.snorm), (size_t)nseg * 16 * sizeof(double)));
+    LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dtarget), (size_t)nseg * sizeof(double)));
+    if (hipHostMalloc(reinterpret_cast<void**>(&B.htmp), (size_t)nseg * 16 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&B.hscal), (size_t)nseg * sizeof(Scal)) != hipSuccess)
+      return set_error(LQCD_ENOMEM, "pinned host allocation failed");
+    B.ready = true;
+  }
   LQ_HIP(hipMemcpyAsync(B.dlat, B.hlat.data(), B.hlat.size() * sizeof(BLat), hipMemcpyHostToDevice, stream));
   LQ_HIP(hipMemcpyAsync(B.dseg, B.hseg.data(), B.hseg.size() * sizeof(BSeg), hipMemcpyHostToDevice, stream));
 

@@ -128,6 +128,10 @@ struct lqcd_ctx {
   int hop_split[3] = {1, 1, 1};  // lanes per output site: 1, or 4 (one direction per lane)
 
   lq::Workspace* ws = nullptr;
+  // workspace of the last batched solve led by this context (reused when the
+  // next batch has the same shape)
+  void* batch = nullptr;
+  void (*batch_free)(void*) = nullptr;
 };
 
 namespace lq {
