@@ -56,8 +56,11 @@ WORKLOADS = {
                    text="32^3x64 Wilson even-odd BiCGStab, kappa=0.1350, eps=0.3, antiperiodic t"),
     "clover": dict(dims=(32, 32, 32, 64), eps=0.3, kappa=0.1370, csw=1.0, seed=1003,
                    text="32^3x64 clover (c_SW=1.0) even-odd BiCGStab, kappa=0.1370, eps=0.3, antiperiodic t"),
-    "large": dict(dims=(64, 64, 64, 128), eps=0.25, kappa=0.1372, csw=1.0, seed=1005,
-                  text="64^3x128 clover (c_SW=1.0) even-odd BiCGStab, kappa=0.1372, eps=0.25, antiperiodic t"),
+    # H scale sqrt(2): at scale 1 this kappa is past the critical one of the
+    # eps = 0.25 ensemble on lattices from 16^4 up (BiCGStab stalls)
+    "large": dict(dims=(64, 64, 64, 128), eps=0.25, kappa=0.1372, csw=1.0, seed=1005, scale=2 ** 0.5,
+                  text="64^3x128 clover (c_SW=1.0) even-odd BiCGStab, kappa=0.1372, eps=0.25 with H scale sqrt(2), "
+                       "antiperiodic t"),
 }
 BATCH = [((32, 32, 32, 64), 1004), ((24, 24, 24, 48), 1005), ((16, 16, 16, 32), 1006)]
 
@@ -67,17 +70,18 @@ def log(msg):
 
 
 def _slice(args):
-    kind, dims, seed, eps, t = args
+    kind, dims, seed, eps, scale, t = args
     if kind == "gauge":
-        return fg.gauge_field(dims, seed, "smooth", eps, t_slices=[t])
+        return fg.gauge_field(dims, seed, "smooth", eps, scale, t_slices=[t])
     return fg.gaussian_spinor(dims, seed, t_slices=[t])
 
 
-def generate(dims, seed, eps=0.3, workers=8, source=True):
+def generate(dims, seed, eps=0.3, workers=8, source=True, scale=1.0):
     lt = dims[3]
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        U = np.concatenate(list(ex.map(_slice, [("gauge", dims, seed, eps, t) for t in range(lt)])))
-        b = np.concatenate(list(ex.map(_slice, [("src", dims, seed, eps, t) for t in range(lt)]))) if source else None
+        U = np.concatenate(list(ex.map(_slice, [("gauge", dims, seed, eps, scale, t) for t in range(lt)])))
+        b = (np.concatenate(list(ex.map(_slice, [("src", dims, seed, eps, scale, t) for t in range(lt)])))
+             if source else None)
     return U, b
 
 
@@ -175,9 +179,9 @@ def cpu_baseline(U, b, dims):
                       f"(1320 flop/site x {v} sites each, NumPy float64, one thread), {dt:.1f} s each"}
 
 
-def make_lattice(torch, lqcd, dims, seed, eps, kappa, csw, stream=None, source=True):
+def make_lattice(torch, lqcd, dims, seed, eps, kappa, csw, stream=None, source=True, scale=1.0):
     t0 = time.perf_counter()
-    U, b = generate(dims, seed, eps, source=source)
+    U, b = generate(dims, seed, eps, source=source, scale=scale)
     log(f"{dims} fields generated in {time.perf_counter() - t0:.1f} s")
     lat = lqcd.Lattice(dims, -1, stream=stream)
     Ud = torch.from_numpy(U).cuda()
@@ -234,7 +238,7 @@ def run_single(a, torch, lqcd):
     w = WORKLOADS[a.workload]
     dims = w["dims"]
     vh = int(np.prod(dims)) // 2
-    lat, U, b = make_lattice(torch, lqcd, dims, w["seed"], w["eps"], w["kappa"], w["csw"])
+    lat, U, b = make_lattice(torch, lqcd, dims, w["seed"], w["eps"], w["kappa"], w["csw"], scale=w.get("scale", 1.0))
     bd = torch.from_numpy(b).cuda()
     tune(lat, lqcd, a.cached, str(dims))
     inner = lqcd.F32 if a.inner == "f32" else lqcd.F16

@@ -21,6 +21,8 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -578,6 +580,13 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
       const double prev = rnorm[s];
       rnorm[s] = B.htmp[16 * s + 8];
       if (!(rnorm[s] < prev)) ++fails[s];
+    }
+    if (std::getenv("LQCD_LOG")) {
+      double worst = 0.0;
+      for (int s = 0; s < nseg; ++s)
+        if (bnorm2[s] > 0) worst = std::max(worst, rnorm[s] / std::sqrt(bnorm2[s]));
+      std::fprintf(stderr, "[lqcd] batch outer pass: %zu active, %d inner iterations so far, worst |r|/|b| %.3e\n",
+                   active.size(), total_inner, worst);
     }
   }
   for (int s = 0; s < nseg; ++s)

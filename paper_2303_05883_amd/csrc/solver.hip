@@ -17,6 +17,8 @@
 //     then the true residual |b - D x| / |b| with the full FP64 operator.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "blas.h"
@@ -25,6 +27,13 @@
 #include "solver.h"
 
 namespace lq {
+
+// Progress lines on stderr when LQCD_LOG is set (each outer pass, and every
+// inner convergence check when LQCD_LOG=2).
+static int log_level() {
+  const char* e = std::getenv("LQCD_LOG");
+  return e ? std::atoi(e) : 0;
+}
 
 static int alloc(void** p, size_t bytes) {
   if (hipMalloc(p, bytes) != hipSuccess) {
@@ -184,9 +193,16 @@ static int bicg_run(lqcd_ctx* c, InnerVecs& v, double target2, int max_iters, in
   LQ_TRY(blas_dot_norm(c, P, v.rhat, v.r, v.partials));
   LQ_TRY(fin_init(c, v.sc, v.partials, blas_blocks(c->g.vh), target2, max_iters));
   Scal* hs = reinterpret_cast<Scal*>(c->ws->hnorms + 32);
+  const bool verbose = log_level() >= 2;
+  int last_logged = 0;
   for (;;) {
     LQ_HIP(hipMemcpyAsync(hs, v.sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
     LQ_HIP(hipStreamSynchronize(c->stream));
+    if (verbose && (hs->done || hs->iters / 256 != last_logged / 256)) {
+      std::fprintf(stderr, "[lqcd] inner prec %d iter %d |r|^2 %.3e (target %.3e)\n", P, hs->iters, hs->rr,
+                   target2);
+      last_logged = hs->iters;
+    }
     if (hs->done) break;
     LQ_TRY(run_chunk(c, v, check, use_graph));
   }
@@ -264,6 +280,9 @@ int solve_native(lqcd_ctx* c, const lqcd_solve_params& prm, lqcd_solve_stats& st
       LQ_HIP(hipStreamSynchronize(c->stream));
       const double prev = rnorm;
       rnorm = hn[8];
+      if (log_level() >= 1)
+        std::fprintf(stderr, "[lqcd] FP64 pass %d: %d iterations, |r|/|b| %.3e\n", outer, total_iters,
+                     rnorm / std::sqrt(bnorm2));
       if (rnorm > target) ++restarts;
       if (bd) ++fails;
       if (!(rnorm < prev) && ++fails > 5) {
@@ -298,6 +317,9 @@ int solve_native(lqcd_ctx* c, const lqcd_solve_params& prm, lqcd_solve_stats& st
       LQ_HIP(hipStreamSynchronize(c->stream));
       const double prev = rnorm;
       rnorm = hn[8];
+      if (log_level() >= 1)
+        std::fprintf(stderr, "[lqcd] outer %d (inner prec %d): %d inner iterations, |r|/|b| %.3e\n", outer, IP,
+                     total_iters, rnorm / std::sqrt(bnorm2));
       if (bd) ++restarts;
       if (!(rnorm < prev) && ++fails > 5) {
         status = set_error(LQCD_EBREAKDOWN, "defect correction stopped reducing the residual");
