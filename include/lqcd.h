@@ -126,6 +126,10 @@ typedef struct {
   int use_graph;        /* 1: replay check_every iterations from a captured hipGraph */
   const double* x0;     /* optional initial guess (canonical, same residency as b) */
   int on_device;        /* 1: b, x and x0 are device pointers; 0: host pointers */
+  int reliable_update;  /* mixed only: 1 = reliable updates (one low-precision Krylov
+                           space, the FP64 true residual re-injected each time the
+                           iterated one drops 10x); 0 = defect correction (restart
+                           the inner solve from each FP64 residual) */
 } lqcd_solve_params;
 
 typedef struct {
@@ -139,12 +143,12 @@ typedef struct {
 
 /* Fill *p with the defaults (tol 1e-10, max_iter 100000, max_outer 100,
  * inner_prec LQCD_F64, inner_tol 1e-6 for F32 / 1e-3 for F16 when 0,
- * check_every 8, use_graph 1, x0 NULL, on_device 0). */
+ * check_every 8, use_graph 1, x0 NULL, on_device 0, reliable_update 0). */
 void lqcd_default_params(lqcd_solve_params* p);
 
 /* Solve D x = b (canonical full-lattice vectors) by even-odd preconditioning:
  * b_e' = b_e - D_eo D_oo^-1 b_o, S x_e = b_e' by BiCGStab (FP64, or FP32/FP16
- * inner iterations inside an FP64 defect-correction loop), then
+ * iterations with FP64 reliable updates or an FP64 defect-correction loop), then
  * x_o = D_oo^-1 (b_o - D_oe x_e). Returns after the stream is synchronised.
  * ENOCONV if the caps are hit (x holds the last iterate, stats are filled). */
 int lqcd_solve(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_params* prm,

@@ -120,6 +120,7 @@ void lqcd_default_params(lqcd_solve_params* p) {
   p->use_graph = 1;
   p->x0 = nullptr;
   p->on_device = 0;
+  p->reliable_update = 0;
 }
 
 int lqcd_create(const int dims[4], int t_bc, void* hip_stream, lqcd_ctx** out) {

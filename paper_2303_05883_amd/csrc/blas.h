@@ -33,6 +33,8 @@ int blas_accum_up(lqcd_ctx* c, int sprec, void* x, const void* e, const double* 
 int blas_copy(lqcd_ctx* c, int prec, const void* src, void* dst);
 int blas_zero(lqcd_ctx* c, int prec, void* dst);
 
+int blas_scale2(lqcd_ctx* c, int prec, void* p, void* v, double f);
+int fin_reliable(lqcd_ctx* c, Scal* sc, const double* partials, int n, double target2);
 int fin_alpha(lqcd_ctx* c, Scal* sc, const double* partials, int n);
 int fin_omega(lqcd_ctx* c, Scal* sc, const double* partials, int n);
 int fin_rho(lqcd_ctx* c, Scal* sc, const double* partials, int n);

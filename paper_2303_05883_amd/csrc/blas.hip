@@ -118,6 +118,30 @@ __global__ void __launch_bounds__(BS) k_zero(void* dst, size_t vh) {
   if (i < vh) zero_site<P>(dst, vh, i);
 }
 
+// p *= f, v *= f (a reliable update changes the residual's normalisation)
+template <int P>
+__global__ void __launch_bounds__(BS) k_scale2(void* p, void* v, double f, size_t vh) {
+  using T = typename IO<P>::T;
+  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= vh) return;
+  const T s = (T)f;
+  cx<T> a[12];
+  IO<P>::load_spinor(p, vh, i, a);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a[k] = s * a[k];
+  IO<P>::store_spinor(p, vh, i, a);
+  IO<P>::load_spinor(v, vh, i, a);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a[k] = s * a[k];
+  IO<P>::store_spinor(v, vh, i, a);
+}
+
+__global__ void __launch_bounds__(FBS) k_fin_reliable(Scal* sc, const double* partials, int n, double target2) {
+  double v[3];
+  sum_partials<3>(partials, n, v);
+  if (threadIdx.x == 0) scal_reliable(sc, v, target2);
+}
+
 // alpha = rho / <rhat, v>
 __global__ void __launch_bounds__(FBS) k_fin_alpha(Scal* sc, const double* partials, int n) {
   if (sc->done) return;
@@ -250,6 +274,19 @@ int blas_copy(lqcd_ctx* c, int prec, const void* src, void* dst) {
 int blas_zero(lqcd_ctx* c, int prec, void* dst) {
   const size_t vh = c->g.vh;
   LQ_PREC_SWITCH(prec, hipLaunchKernelGGL(k_zero<P>, dim3(nblk(vh)), dim3(BS), 0, c->stream, dst, vh));
+  LQ_HIP(hipGetLastError());
+  return LQCD_OK;
+}
+
+int blas_scale2(lqcd_ctx* c, int prec, void* p, void* v, double f) {
+  const size_t vh = c->g.vh;
+  LQ_PREC_SWITCH(prec, hipLaunchKernelGGL(k_scale2<P>, dim3(nblk(vh)), dim3(BS), 0, c->stream, p, v, f, vh));
+  LQ_HIP(hipGetLastError());
+  return LQCD_OK;
+}
+
+int fin_reliable(lqcd_ctx* c, Scal* sc, const double* partials, int n, double target2) {
+  hipLaunchKernelGGL(k_fin_reliable, dim3(1), dim3(FBS), 0, c->stream, sc, partials, n, target2);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }

@@ -208,4 +208,15 @@ __device__ inline void scal_init(Scal* sc, const double v[3], double target2, in
   sc->iters = 0;
 }
 
+// After a reliable update replaced r: rho = <rhat, r>, rr = <r, r>, new
+// target; alpha, omega and the iteration count carry on.
+__device__ inline void scal_reliable(Scal* sc, const double v[3], double target2) {
+  sc->rho_r = v[0];
+  sc->rho_i = v[1];
+  sc->rr = v[2];
+  sc->target2 = target2;
+  sc->breakdown = 0;
+  sc->done = (v[2] <= target2 || sc->iters >= sc->max_iters) ? 1 : 0;
+}
+
 }  // namespace lq

@@ -212,6 +212,90 @@ static int bicg_run(lqcd_ctx* c, InnerVecs& v, double target2, int max_iters, in
   return LQCD_OK;
 }
 
+// Mixed precision with reliable updates (Sleijpen and van der Vorst, 1996):
+// one low-precision BiCGStab runs on the residual equation normalised by the
+// last true residual; whenever its iterated residual has dropped by DELTA_R
+// since then (or it reports convergence), the low-precision solution is added
+// to x in FP64, the true residual b' - S x is recomputed in FP64 and put back
+// into the iteration (p and v rescaled to the new normalisation, rho
+// recomputed), so that the Krylov space is kept instead of restarted. On a
+// breakdown the iteration restarts from the true residual.
+static int reliable_mixed(lqcd_ctx* c, const lqcd_solve_params& prm, InnerVecs& iv, double target, double bnorm2,
+                          double& rnorm, int& total_iters, int& restarts, int& updates, int& status) {
+  constexpr double DELTA_R = 0.1;
+  Workspace* w = c->ws;
+  const int IP = iv.prec;
+  double* hn = w->hnorms;
+  Scal* hs = reinterpret_cast<Scal*>(hn + 32);
+  const int check = prm.check_every > 0 ? prm.check_every : 8;
+  const bool graph = prm.use_graph != 0;
+  const int nb = blas_blocks(c->g.vh);
+  bool restart = true;
+  int base_iters = 0;  // iterations of earlier restarts
+  double prev = rnorm;
+  int fails = 0;
+  while (rnorm > target) {
+    if (restart) {
+      if (total_iters >= prm.max_iter) break;
+      LQ_TRY(blas_scale_down(c, IP, w->r64, iv.r, w->norms + 7, 0.0));
+      LQ_TRY(blas_zero(c, iv.xprec, iv.x));
+      LQ_TRY(blas_copy(c, IP, iv.r, iv.rhat));
+      LQ_TRY(blas_copy(c, IP, iv.r, iv.pv));
+      LQ_TRY(blas_dot_norm(c, IP, iv.rhat, iv.r, iv.partials));
+      const double t = target / rnorm;
+      LQ_TRY(fin_init(c, iv.sc, iv.partials, nb, t * t, prm.max_iter - total_iters));
+      base_iters = total_iters;
+      restart = false;
+    }
+    // iterate until the iterated residual has dropped by DELTA_R (it starts at 1)
+    for (;;) {
+      LQ_HIP(hipMemcpyAsync(hs, iv.sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+      LQ_HIP(hipStreamSynchronize(c->stream));
+      if (hs->done || hs->rr <= DELTA_R * DELTA_R) break;
+      LQ_TRY(run_chunk(c, iv, check, graph));
+    }
+    total_iters = base_iters + hs->iters;
+    const bool breakdown = hs->breakdown != 0;
+    const bool exhausted = hs->iters >= hs->max_iters;
+    // reliable update: x += |r| e (FP64), e = 0, r = b' - S x (FP64)
+    LQ_TRY(blas_accum_up(c, iv.xprec, w->x_e, iv.x, w->norms + 8));
+    LQ_TRY(blas_zero(c, iv.xprec, iv.x));
+    LQ_TRY(residual64(c, w->x_e, w->r64, w->norms + 6));
+    LQ_HIP(hipMemcpyAsync(hn + 6, w->norms + 6, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LQ_HIP(hipStreamSynchronize(c->stream));
+    const double rold = rnorm;
+    rnorm = hn[8];
+    ++updates;
+    if (log_level() >= 1)
+      std::fprintf(stderr, "[lqcd] reliable update %d (inner prec %d): %d iterations, |r|/|b| %.3e\n", updates, IP,
+                   total_iters, rnorm / std::sqrt(bnorm2));
+    if (rnorm <= target) break;
+    if (exhausted || total_iters >= prm.max_iter) break;
+    if (!(rnorm < prev)) {
+      if (++fails > 5) {
+        status = set_error(LQCD_EBREAKDOWN, "reliable updates stopped reducing the residual");
+        return LQCD_OK;
+      }
+    } else {
+      prev = rnorm;
+    }
+    if (breakdown || !(rnorm < rold)) {
+      ++restarts;
+      restart = true;
+      continue;
+    }
+    // put the true residual back: r = r64 / |r64|, p and v to the new normalisation
+    LQ_TRY(blas_scale_down(c, IP, w->r64, iv.r, w->norms + 7, 0.0));
+    LQ_TRY(blas_scale2(c, IP, iv.pv, iv.v_, rold / rnorm));
+    LQ_TRY(blas_dot_norm(c, IP, iv.rhat, iv.r, iv.partials));
+    const double t = target / rnorm;
+    LQ_TRY(fin_reliable(c, iv.sc, iv.partials, nb, t * t));
+  }
+  if (rnorm > target && status == LQCD_OK)
+    status = set_error(LQCD_ENOCONV, "mixed-precision solve did not reach the tolerance");
+  return LQCD_OK;
+}
+
 int solve_native(lqcd_ctx* c, const lqcd_solve_params& prm, lqcd_solve_stats& st) {
   using clk = std::chrono::steady_clock;
   const auto t0 = clk::now();
@@ -291,6 +375,9 @@ int solve_native(lqcd_ctx* c, const lqcd_solve_params& prm, lqcd_solve_stats& st
       }
     }
   } else {
+    if (prm.reliable_update) {
+      LQ_TRY(reliable_mixed(c, prm, iv, target, bnorm2, rnorm, total_iters, restarts, outer, status));
+    } else {
     // mixed precision: FP64 defect correction around FP32 / FP16 BiCGStab
     const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : 1e-3);
     while (rnorm > target) {
@@ -325,6 +412,7 @@ int solve_native(lqcd_ctx* c, const lqcd_solve_params& prm, lqcd_solve_stats& st
         status = set_error(LQCD_EBREAKDOWN, "defect correction stopped reducing the residual");
         break;
       }
+    }
     }
   }
   const auto t_solved = clk::now();

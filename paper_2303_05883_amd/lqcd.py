@@ -37,7 +37,7 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("max_outer", C.c_int), ("inner_prec", C.c_int),
                 ("inner_tol", C.c_double), ("check_every", C.c_int), ("use_graph", C.c_int),
-                ("x0", C.c_void_p), ("on_device", C.c_int)]
+                ("x0", C.c_void_p), ("on_device", C.c_int), ("reliable_update", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -273,7 +273,7 @@ class Lattice:
 
     # solver ----------------------------------------------------------------
     def solve(self, b, x, tol=1e-10, inner_prec=F64, inner_tol=0.0, max_iter=100000, max_outer=100,
-              check_every=8, use_graph=True, x0=None, raise_on_fail=True) -> Stats:
+              check_every=8, use_graph=True, x0=None, raise_on_fail=True, reliable_update=False) -> Stats:
         prm = default_params()
         pb, db = _ptr(b)
         px, dx = _ptr(x)
@@ -282,6 +282,7 @@ class Lattice:
         prm.tol, prm.inner_prec, prm.inner_tol = float(tol), int(inner_prec), float(inner_tol)
         prm.max_iter, prm.max_outer, prm.check_every = int(max_iter), int(max_outer), int(check_every)
         prm.use_graph, prm.on_device = int(bool(use_graph)), db
+        prm.reliable_update = int(bool(reliable_update))
         if x0 is not None:
             prm.x0 = _ptr(x0)[0]
         st = SolveStats()

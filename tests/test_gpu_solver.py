@@ -35,7 +35,8 @@ def test_wilson_haar_8(prec, graph):
 
 @pytest.mark.parametrize("prec", [lqcd.F64, lqcd.F32, lqcd.F16])
 @pytest.mark.parametrize("split", [1, 4])
-def test_clover_smooth(prec, split):
+@pytest.mark.parametrize("reliable", [True, False])
+def test_clover_smooth(prec, split, reliable):
     dims = (8, 8, 8, 8)
     U = fg.gauge_field(dims, 1003, "smooth", 0.3)
     b = fg.gaussian_spinor(dims, 1003)
@@ -43,7 +44,7 @@ def test_clover_smooth(prec, split):
     for p in (lqcd.F64, lqcd.F32, lqcd.F16):
         lat.set_hop_shape(p, 128 if split == 4 else 256, split, 1, 1)
     x = to_dev(np.zeros_like(b))
-    st = lat.solve(to_dev(b), x, inner_prec=prec)
+    st = lat.solve(to_dev(b), x, inner_prec=prec, reliable_update=reliable)
     r = true_residual(dirac.Operator(U, 0.137, 1.0), from_dev(x), b)
     assert st.true_rel_resid <= 1e-10 and r <= 1e-10, (st, r)
     if prec != lqcd.F64:
