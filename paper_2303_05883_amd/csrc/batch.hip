@@ -4,12 +4,13 @@
 // rho, alpha, omega; not block Krylov), but every operator step of every
 // unconverged segment of every lattice is ONE persistent kernel launch:
 //
-//  * the hop walks a tile list of (lattice, site block, rhs) in which the
-//    right-hand sides of one site block are consecutive and the list is cut
-//    into 8 contiguous chunks, one per XCD (blocks reach the XCDs
-//    round-robin), so each link is read from HBM once and reused from that
-//    XCD's L2 by the other right-hand sides (the paper's motivation: many
-//    equations on one gauge field, Sec. 3);
+//  * the hop walks a tile list of (lattice, site block, group of right-hand
+//    sides); a thread computes its site for every right-hand side of its
+//    group, loading each link and clover block once for all of them, and the
+//    groups of one site block are consecutive tiles in one of 8 contiguous
+//    chunks, one per XCD (blocks reach the XCDs round-robin), so links are
+//    reused from that XCD's L2 across groups too (the paper's motivation:
+//    many equations on one gauge field, Sec. 3);
 //  * vector updates and the fused reductions are batched the same way, with
 //    per-segment partial sums and per-segment finalize blocks;
 //  * converged segments are masked: their tiles return at once;
@@ -46,7 +47,7 @@ struct BLat {
   const void* clov_oinv;  // A_oo^-1 (slot 3) or null
   double kappa;
   int tile0;   // first hop tile of this lattice
-  int ntile;   // hop tiles: nsb * nrhs
+  int ntile;   // hop tiles: nsb * ceil(nrhs / NB)
   int nsb;     // hop site blocks
   int btile0;  // first blas tile
   int nbb;     // blas blocks
@@ -63,6 +64,11 @@ struct BSeg {
 
 constexpr int MAXLAT = 16;
 constexpr int BS = 256;
+// right-hand sides per thread in the batched hop (links shared between them)
+template <int P>
+struct RhsBlock {
+  static constexpr int NB = P == 0 ? 2 : 4;
+};
 
 struct BHopArgs {
   const BLat* lat;
@@ -82,26 +88,50 @@ __device__ inline int find_lat(const BLat* lat, int nlat, int tile, bool blas) {
   return l;
 }
 
-template <int P, int EPI, bool CLOV, int RED, bool NT>
+// Tiles are (lattice, site block, group of NB right-hand sides), groups
+// fastest; each thread computes one site for the NB right-hand sides of its
+// group (link and clover loads shared).
+template <int P, int EPI, bool CLOV, int RED, bool NT, int NB>
 __global__ void __launch_bounds__(BS) k_bhop(BHopArgs b) {
   constexpr int NR = RED == RED_DOT ? 2 : (RED == RED_TS ? 3 : 0);
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, nslot = gridDim.x >> 3;
   for (int t = b.bound[xcd] + slot; t < b.bound[xcd + 1]; t += nslot) {
     const int l = find_lat(b.lat, b.nlat, t, false);
     const BLat& L = b.lat[l];
+    const int ngroup = (L.nrhs + NB - 1) / NB;
     const int local = t - L.tile0;
-    const int sb = local / L.nrhs, r = local % L.nrhs;
-    const BSeg& S = b.seg[L.seg0 + r];
-    if (S.sc->done) continue;  // uniform over the block
+    const int sb = local / ngroup, grp = local % ngroup;
+    MultiPtrs<NB> m;
+    m.act = 0u;
+    int segs[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int r = grp * NB + q;
+      segs[q] = -1;
+      m.in[q] = nullptr;
+      m.out[q] = nullptr;
+      m.own[q] = nullptr;
+      m.w[q] = nullptr;
+      if (r < L.nrhs) {
+        const BSeg& S = b.seg[L.seg0 + r];
+        segs[q] = L.seg0 + r;
+        if (!S.sc->done) m.act |= 1u << q;  // uniform over the block
+        m.in[q] = S.f[b.in_sel];
+        m.out[q] = S.f[b.out_sel];
+        m.own[q] = b.own_sel >= 0 ? S.f[b.own_sel] : nullptr;
+        m.w[q] = b.w_sel >= 0 ? S.f[b.w_sel] : nullptr;
+      }
+    }
+    if (m.act == 0u) continue;
     HopArgs a;
-    a.in = S.f[b.in_sel];
-    a.out = S.f[b.out_sel];
+    a.in = nullptr;
+    a.out = nullptr;
     a.gauge = L.gauge;
     a.link_stride = L.link_stride;
     a.clov = b.clov_slot == 0 ? L.clov_e : L.clov_oinv;
-    a.xown = b.own_sel >= 0 ? S.f[b.own_sel] : nullptr;
-    a.w = b.w_sel >= 0 ? S.f[b.w_sel] : nullptr;
-    a.partials = S.partials;
+    a.xown = nullptr;
+    a.w = nullptr;
+    a.partials = nullptr;
     a.skip = nullptr;
     a.scale = b.scale_mode == 0 ? 1.0 : -L.kappa * L.kappa;
     a.g = L.g;
@@ -109,11 +139,17 @@ __global__ void __launch_bounds__(BS) k_bhop(BHopArgs b) {
     a.remap = 0;
     a.hz = 0;
     const size_t i = (size_t)sb * BS + threadIdx.x;
-    double red[3] = {0.0, 0.0, 0.0};
-    if (i < (size_t)L.g.vh) hop_site<P, EPI, CLOV, RED, NT>(a, i, red);
+    double red[NB][3];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) red[q][0] = red[q][1] = red[q][2] = 0.0;
+    if (i < (size_t)L.g.vh) hop_site_multi<P, EPI, CLOV, RED, NT, NB>(a, m, i, red);
     if constexpr (NR > 0) {
-      block_reduce<NR>(red, S.partials + (size_t)sb * NR);
-      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (!((m.act >> q) & 1u)) continue;
+        block_reduce<NR>(red[q], b.seg[segs[q]].partials + (size_t)sb * NR);
+        __syncthreads();
+      }
     }
   }
 }
@@ -255,14 +291,14 @@ int batch_hop(Batch& B, hipStream_t s, int in_sel, int out_sel, int own_sel, int
   const bool cl = B.clover;
 #define LQ_BHOP(P)                                                                                       \
   if (epi == EPI_SCALE_CLOV) {                                                                           \
-    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_SCALE_CLOV, true, RED_NONE, true>), dim3(grid), dim3(BS), 0, s, a); \
-    else hipLaunchKernelGGL((k_bhop<P, EPI_SCALE, false, RED_NONE, true>), dim3(grid), dim3(BS), 0, s, a);      \
+    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_SCALE_CLOV, true, RED_NONE, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a); \
+    else hipLaunchKernelGGL((k_bhop<P, EPI_SCALE, false, RED_NONE, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);      \
   } else if (red == RED_DOT) {                                                                           \
-    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, true, RED_DOT, true>), dim3(grid), dim3(BS), 0, s, a);        \
-    else hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, false, RED_DOT, true>), dim3(grid), dim3(BS), 0, s, a);          \
+    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, true, RED_DOT, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);        \
+    else hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, false, RED_DOT, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);          \
   } else {                                                                                               \
-    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, true, RED_TS, true>), dim3(grid), dim3(BS), 0, s, a);         \
-    else hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, false, RED_TS, true>), dim3(grid), dim3(BS), 0, s, a);           \
+    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, true, RED_TS, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);         \
+    else hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, false, RED_TS, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);           \
   }
   if (B.prec == 1) {
     LQ_BHOP(1)
@@ -437,7 +473,10 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
     L.nbb = L.nsb;
     L.nrhs = nrhs[l];
     L.tile0 = tile;
-    L.ntile = L.nsb * L.nrhs;
+    {
+      const int nbk = IP == 0 ? RhsBlock<0>::NB : RhsBlock<1>::NB;
+      L.ntile = L.nsb * ((L.nrhs + nbk - 1) / nbk);
+    }
     L.btile0 = btile;
     L.seg0 = seg;
     tile += L.ntile;

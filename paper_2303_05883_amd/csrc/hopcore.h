@@ -246,4 +246,119 @@ __device__ inline void hop_site(const HopArgs& a, size_t i, double red[3]) {
   IO<P>::store_spinor(a.out, vh, i, out);
 }
 
+// ------------------------------------------------------------------ several right-hand sides
+// NB right-hand sides of one lattice at one site: each link (and its rebuilt
+// third row) is loaded once per direction and applied to every right-hand
+// side, so the link traffic per site-RHS falls by NB. act has bit r set for
+// the right-hand sides to compute (uniform over a block).
+template <int NB>
+struct MultiPtrs {
+  const void* in[NB];
+  void* out[NB];
+  const void* own[NB];
+  const void* w[NB];
+  unsigned act;
+};
+
+template <int P, int MU, bool FWD, bool NT, int NB>
+__device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, size_t vh, size_t nbr, size_t lidx,
+                                     bool flip, cx<typename IO<P>::T> acc[NB][12]) {
+  using T = typename IO<P>::T;
+  cx<T> u[6], r2[3];
+  IO<P>::template load_link<NT>(links, vh, lidx, u);
+  reconstruct(u, r2);
+  const cx<T> M[9] = {u[0], u[1], u[2], u[3], u[4], u[5], r2[0], r2[1], r2[2]};
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    if (!((m.act >> r) & 1u)) continue;
+    cx<T> h[6];
+    if (MU == 3) {
+      cx<T> half[6];
+      IO<P>::load_half(m.in[r], vh, nbr, !FWD, half);
+      const T two = flip ? T(-2) : T(2);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k] = two * half[k];
+    } else {
+      cx<T> s[12];
+      IO<P>::load_spinor(m.in[r], vh, nbr, s);
+      project<MU, FWD>(s, h);
+    }
+    cx<T> w[6];
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cx<T> q;
+        if (FWD) {
+          q = M[3 * a] * h[3 * v];
+          q = q + M[3 * a + 1] * h[3 * v + 1];
+          q = q + M[3 * a + 2] * h[3 * v + 2];
+        } else {
+          q = cmulc(M[a], h[3 * v]);
+          q = q + cmulc(M[3 + a], h[3 * v + 1]);
+          q = q + cmulc(M[6 + a], h[3 * v + 2]);
+        }
+        w[3 * v + a] = q;
+      }
+    expand<MU, FWD>(acc[r], w);
+  }
+}
+
+template <int P, int EPI, bool CLOV, int RED, bool NT, int NB>
+__device__ inline void hop_site_multi(const HopArgs& a, const MultiPtrs<NB>& m, size_t i, double red[NB][3]) {
+  using T = typename IO<P>::T;
+  const size_t vh = (size_t)a.g.vh;
+  const Geom& g = a.g;
+  const int ii = (int)i;
+  const int xh = ii % g.lxh;
+  int r = ii / g.lxh;
+  const int y = r % g.ly;
+  r /= g.ly;
+  const int z = r % g.lz;
+  const int t = r / g.lz;
+  const int x = 2 * xh + ((y + z + t + a.p) & 1);
+  const int row = ii - xh;
+  const int xf = (x + 1 == g.lx) ? 0 : x + 1;
+  const int xb = (x == 0) ? g.lx - 1 : x - 1;
+  const int yl = g.lxh, zl = g.lxh * g.ly, tl = g.lxh * g.ly * g.lz;
+  const int iyf = ii + ((y + 1 == g.ly) ? -(g.ly - 1) * yl : yl);
+  const int iyb = ii + ((y == 0) ? (g.ly - 1) * yl : -yl);
+  const int izf = ii + ((z + 1 == g.lz) ? -(g.lz - 1) * zl : zl);
+  const int izb = ii + ((z == 0) ? (g.lz - 1) * zl : -zl);
+  const int itf = ii + ((t + 1 == g.lt) ? -(g.lt - 1) * tl : tl);
+  const int itb = ii + ((t == 0) ? (g.lt - 1) * tl : -tl);
+  const bool flipf = (g.t_bc < 0) && (t + 1 == g.lt);
+  const bool flipb = (g.t_bc < 0) && (t == 0);
+  const char* gf = a.gauge + (size_t)(a.p * 4) * a.link_stride;
+  const char* gb = a.gauge + (size_t)((1 - a.p) * 4) * a.link_stride;
+  const size_t ls = a.link_stride;
+
+  cx<T> acc[NB][12];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
+
+  hop_dir_multi<P, 0, true, NT, NB>(m, gf + 0 * ls, vh, (size_t)(row + (xf >> 1)), i, false, acc);
+  hop_dir_multi<P, 0, false, NT, NB>(m, gb + 0 * ls, vh, (size_t)(row + (xb >> 1)), (size_t)(row + (xb >> 1)), false,
+                                     acc);
+  hop_dir_multi<P, 1, true, NT, NB>(m, gf + 1 * ls, vh, (size_t)iyf, i, false, acc);
+  hop_dir_multi<P, 1, false, NT, NB>(m, gb + 1 * ls, vh, (size_t)iyb, (size_t)iyb, false, acc);
+  hop_dir_multi<P, 2, true, NT, NB>(m, gf + 2 * ls, vh, (size_t)izf, i, false, acc);
+  hop_dir_multi<P, 2, false, NT, NB>(m, gb + 2 * ls, vh, (size_t)izb, (size_t)izb, false, acc);
+  hop_dir_multi<P, 3, true, NT, NB>(m, gf + 3 * ls, vh, (size_t)itf, i, flipf, acc);
+  hop_dir_multi<P, 3, false, NT, NB>(m, gb + 3 * ls, vh, (size_t)itb, (size_t)itb, flipb, acc);
+
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (!((m.act >> q) & 1u)) continue;
+    HopArgs aq = a;
+    aq.xown = m.own[q];
+    aq.w = m.w[q];
+    cx<T> out[12];
+    hop_epilogue<P, EPI, CLOV, RED>(aq, i, acc[q], out, red[q]);
+    IO<P>::store_spinor(m.out[q], vh, i, out);
+  }
+}
+
 }  // namespace lq
