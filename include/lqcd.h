@@ -187,7 +187,8 @@ int lqcd_autotune(lqcd_ctx* ctx, int prec, const char* path);
 
 /* Fix the launch shape of the hop kernels for one precision (the knobs the
  * autotuner searches): block = workgroup size (64, 128, 192 or 256 threads),
- * split = lanes per output site (1, or 4 with one lattice direction per lane),
+ * split = lanes per output site (1; 2 with the forward hops in one lane and the
+ * backward hops in the other; 4 with one lattice direction per lane),
  * xcd_map = 0 for blocks in site order, 1 to give each of the chip's 8 XCDs
  * one contiguous range of sites, 2 to give each XCD one slab of Lz/8 z-planes
  * walked z before t (needs Lz divisible by 8),

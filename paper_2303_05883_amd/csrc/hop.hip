@@ -155,6 +155,166 @@ __global__ void __launch_bounds__(256) k_hop4(HopArgs a) {
   if constexpr (NR > 0) block_reduce<NR>(red, a.partials + (size_t)blk * NR);
 }
 
+
+// Pair-split hop: two lanes share one output site, lane 0 taking the four
+// forward hops and lane 1 the four backward ones, in one instruction stream
+// (the two differ only in signs, the neighbour and link they read, and U
+// against U^dag). A CU then holds half as many sites in flight as with one
+// lane per site for the same bytes in flight, so the z and t neighbours of
+// those sites stay in the XCD's L2; the two partial sums are added with one
+// DPP exchange. The loads of HOP2_PF directions are issued ahead of the
+// arithmetic of the current one.
+#ifndef HOP2_PF
+#define HOP2_PF 2
+#endif
+
+template <int P>
+struct PairIn {
+  cx<typename IO<P>::T> u[6], s[12];
+};
+
+template <int P, int MU, bool NT>
+__device__ inline void pair_load(const void* in, const char* links, size_t vh, size_t nbr, size_t lidx, bool fwd,
+                                 PairIn<P>& d) {
+  IO<P>::template load_link<NT>(links, vh, lidx, d.u);
+  if (MU == 3) IO<P>::load_spinor_sel(in, vh, nbr, fwd ? 2 : 1, d.s);  // the needed half, in both halves
+  else IO<P>::load_spinor(in, vh, nbr, d.s);
+}
+
+template <int P, int MU>
+__device__ inline void pair_compute(const PairIn<P>& d, bool fwd, bool flip, cx<typename IO<P>::T> acc[12]) {
+  using T = typename IO<P>::T;
+  const cx<T>* s = d.s;
+  const T sg = fwd ? T(1) : T(-1);
+  cx<T> h[6];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (MU == 3) {  // the FP16 load brings the whole spinor, the others the selected half twice
+      const T two = flip ? T(-2) : T(2);
+      h[c] = two * ((P == 2 && fwd) ? s[6 + c] : s[c]);
+      h[3 + c] = two * ((P == 2 && fwd) ? s[9 + c] : s[3 + c]);
+    } else if (MU == 0) {  // h = u + sg i sigma_x l = (s0 + sg i s3, s1 + sg i s2)
+      h[c] = s[c] + sg * mul_i(s[9 + c]);
+      h[3 + c] = s[3 + c] + sg * mul_i(s[6 + c]);
+    } else if (MU == 1) {  // i sigma_y l = (s3, -s2)
+      h[c] = s[c] + sg * s[9 + c];
+      h[3 + c] = s[3 + c] - sg * s[6 + c];
+    } else {  // i sigma_z l = (i s2, -i s3)
+      h[c] = s[c] + sg * mul_i(s[6 + c]);
+      h[3 + c] = s[3 + c] - sg * mul_i(s[9 + c]);
+    }
+  }
+  cx<T> r2[3];
+  reconstruct(d.u, r2);
+  const cx<T> U9[9] = {d.u[0], d.u[1], d.u[2], d.u[3], d.u[4], d.u[5], r2[0], r2[1], r2[2]};
+  cx<T> M[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = fwd ? U9[3 * a + b] : conj(U9[3 * b + a]);
+  cx<T> w[6];
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<T> q = M[3 * a] * h[3 * v];
+      q = q + M[3 * a + 1] * h[3 * v + 1];
+      q = q + M[3 * a + 2] * h[3 * v + 2];
+      w[3 * v + a] = q;
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<T> w0 = w[c], w1 = w[3 + c];
+    if (MU == 3) {  // forward: lower spins; backward: upper spins
+      const T fw = fwd ? T(1) : T(0), bw = fwd ? T(0) : T(1);
+      acc[c] = acc[c] + bw * w0;
+      acc[3 + c] = acc[3 + c] + bw * w1;
+      acc[6 + c] = acc[6 + c] + fw * w0;
+      acc[9 + c] = acc[9 + c] + fw * w1;
+    } else {
+      acc[c] = acc[c] + w0;
+      acc[3 + c] = acc[3 + c] + w1;
+      if (MU == 0) {  // lower += -sg i sigma_x w = -sg (i w1, i w0)
+        acc[6 + c] = acc[6 + c] - sg * mul_i(w1);
+        acc[9 + c] = acc[9 + c] - sg * mul_i(w0);
+      } else if (MU == 1) {  // -sg (w1, -w0)
+        acc[6 + c] = acc[6 + c] - sg * w1;
+        acc[9 + c] = acc[9 + c] + sg * w0;
+      } else {  // -sg (i w0, -i w1)
+        acc[6 + c] = acc[6 + c] - sg * mul_i(w0);
+        acc[9 + c] = acc[9 + c] + sg * mul_i(w1);
+      }
+    }
+  }
+}
+
+template <int P, int EPI, bool CLOV, int RED, bool NT>
+__global__ void __launch_bounds__(256) k_hop2(HopArgs a) {
+  using T = typename IO<P>::T;
+  if (a.skip && *a.skip) return;
+  const size_t vh = (size_t)a.g.vh;
+  const int blk = blockIdx.x;
+  const int lane = threadIdx.x & 1;
+  const bool fwd = lane == 0;
+  size_t i = 0;
+  const bool active = map_site(a, blockDim.x >> 1, threadIdx.x >> 1, i);
+  constexpr int NR = RED == RED_DOT ? 2 : (RED == RED_TS ? 3 : 0);
+  double red[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    const Geom& g = a.g;
+    const int ii = (int)i;
+    const int xh = ii % g.lxh;
+    int r = ii / g.lxh;
+    const int y = r % g.ly;
+    r /= g.ly;
+    const int z = r % g.lz;
+    const int t = r / g.lz;
+    const int x = 2 * xh + ((y + z + t + a.p) & 1);
+    const int row = ii - xh;
+    const int yl = g.lxh, zl = g.lxh * g.ly, tl = g.lxh * g.ly * g.lz;
+    // this lane's neighbour in each direction: forward or backward
+    size_t nb[4];
+    nb[0] = (size_t)(row + ((fwd ? ((x + 1 == g.lx) ? 0 : x + 1) : ((x == 0) ? g.lx - 1 : x - 1)) >> 1));
+    nb[1] = (size_t)(fwd ? ii + ((y + 1 == g.ly) ? -(g.ly - 1) * yl : yl) : ii + ((y == 0) ? (g.ly - 1) * yl : -yl));
+    nb[2] = (size_t)(fwd ? ii + ((z + 1 == g.lz) ? -(g.lz - 1) * zl : zl) : ii + ((z == 0) ? (g.lz - 1) * zl : -zl));
+    nb[3] = (size_t)(fwd ? ii + ((t + 1 == g.lt) ? -(g.lt - 1) * tl : tl) : ii + ((t == 0) ? (g.lt - 1) * tl : -tl));
+    const bool flip = (g.t_bc < 0) && (fwd ? (t + 1 == g.lt) : (t == 0));
+    // forward hops read U_mu(x) (parity p, index i); backward hops U_mu(x - mu) (parity 1-p)
+    const char* gl = a.gauge + (size_t)((fwd ? a.p : 1 - a.p) * 4) * a.link_stride;
+    const size_t ls = a.link_stride;
+    cx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+#define LD(MU, B) pair_load<P, MU, NT>(a.in, gl + MU * ls, vh, nb[MU], fwd ? i : nb[MU], fwd, d[B])
+#define CP(MU, B) pair_compute<P, MU>(d[B], fwd, MU == 3 && flip, acc)
+#if HOP2_PF >= 4
+    PairIn<P> d[4];
+    LD(0, 0); LD(1, 1); LD(2, 2); LD(3, 3);
+    CP(0, 0); CP(1, 1); CP(2, 2); CP(3, 3);
+#elif HOP2_PF == 3
+    PairIn<P> d[3];
+    LD(0, 0); LD(1, 1); LD(2, 2);
+    CP(0, 0); LD(3, 0); CP(1, 1); CP(2, 2); CP(3, 0);
+#elif HOP2_PF == 2
+    PairIn<P> d[2];
+    LD(0, 0); LD(1, 1);
+    CP(0, 0); LD(2, 0); CP(1, 1); LD(3, 1); CP(2, 0); CP(3, 1);
+#else
+    PairIn<P> d[1];
+    LD(0, 0); CP(0, 0); LD(1, 0); CP(1, 0); LD(2, 0); CP(2, 0); LD(3, 0); CP(3, 0);
+#endif
+#undef LD
+#undef CP
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {acc[k].r + quad_swap<0xB1>(acc[k].r), acc[k].i + quad_swap<0xB1>(acc[k].i)};
+    cx<T> out[12];
+    hop_epilogue<P, EPI, CLOV, RED>(a, i, acc, out, red);
+    if (lane != 0) red[0] = red[1] = red[2] = 0.0;
+    IO<P>::store_part(a.out, vh, i, out, lane, 2);
+  }
+  if constexpr (NR > 0) block_reduce<NR>(red, a.partials + (size_t)blk * NR);
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) k_site(const void* clov, const void* in, void* out, size_t vh) {
   using T = typename IO<P>::T;
@@ -184,6 +344,9 @@ static void launch_t(const HopArgs& a, int nb, int bs, hipStream_t s, bool nt, i
   if (split == 4) {
     if (nt) hipLaunchKernelGGL((k_hop4<P, EPI, CLOV, RED, true>), dim3(nb), dim3(bs), 0, s, a);
     else hipLaunchKernelGGL((k_hop4<P, EPI, CLOV, RED, false>), dim3(nb), dim3(bs), 0, s, a);
+  } else if (split == 2) {
+    if (nt) hipLaunchKernelGGL((k_hop2<P, EPI, CLOV, RED, true>), dim3(nb), dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL((k_hop2<P, EPI, CLOV, RED, false>), dim3(nb), dim3(bs), 0, s, a);
   } else {
     if (nt) hipLaunchKernelGGL((k_hop<P, EPI, CLOV, RED, true>), dim3(nb), dim3(bs), 0, s, a);
     else hipLaunchKernelGGL((k_hop<P, EPI, CLOV, RED, false>), dim3(nb), dim3(bs), 0, s, a);
@@ -225,7 +388,8 @@ int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out) {
   if (!c->gauge[h.prec]) return set_error(LQCD_ESTATE, "gauge field not set");
   const int bs = c->hop_block[h.prec];
   if (bs % 64 != 0 || bs < 64 || bs > 256) return set_error(LQCD_EINVAL, "hop block size must be 64..256, multiple of 64");
-  if (c->hop_split[h.prec] != 1 && c->hop_split[h.prec] != 4) return set_error(LQCD_EINVAL, "bad hop split");
+  if (c->hop_split[h.prec] != 1 && c->hop_split[h.prec] != 2 && c->hop_split[h.prec] != 4)
+    return set_error(LQCD_EINVAL, "bad hop split");
   const int nb = hop_blocks(c, h.prec);
   if (nblocks_out) *nblocks_out = nb;
   if (h.red != RED_NONE && !h.partials) return set_error(LQCD_EINVAL, "reduction without a partials buffer");

@@ -125,7 +125,7 @@ struct lqcd_ctx {
   int hop_block[3] = {256, 256, 256};
   int hop_remap[3] = {1, 1, 1};
   int hop_nt[3] = {0, 0, 0};     // non-temporal link loads
-  int hop_split[3] = {1, 1, 1};  // lanes per output site: 1, or 4 (one direction per lane)
+  int hop_split[3] = {1, 1, 1};  // lanes per output site: 1, 2 (forward / backward) or 4 (one direction each)
 
   lq::Workspace* ws = nullptr;
   // workspace of the last batched solve led by this context (reused when the

@@ -95,7 +95,7 @@ bool write_cache(const std::string& path, const std::map<std::string, Entry>& m)
 
 bool valid(const Entry& e) {
   return (e.block == 64 || e.block == 128 || e.block == 192 || e.block == 256) && e.remap >= 0 && e.remap <= 2 &&
-         (e.nt == 0 || e.nt == 1) && (e.split == 1 || e.split == 4);
+         (e.nt == 0 || e.nt == 1) && (e.split == 1 || e.split == 2 || e.split == 4);
 }
 
 }  // namespace
@@ -147,7 +147,7 @@ extern "C" int lqcd_autotune(lqcd_ctx* c, int prec, const char* path) {
   const int save_b = c->hop_block[prec], save_r = c->hop_remap[prec], save_nt = c->hop_nt[prec],
             save_s = c->hop_split[prec];
   int status = LQCD_OK;
-  for (int split : {1, 4})
+  for (int split : {1, 2, 4})
   for (int nt = 0; nt < 2 && status == LQCD_OK; ++nt)
   for (int remap = 0; remap < 3 && status == LQCD_OK; ++remap)
     for (int b : blocks) {

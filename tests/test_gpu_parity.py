@@ -55,7 +55,8 @@ OPNAMES = ["D", "DEE", "DOO", "DEO", "DOE", "HOP_EO", "HOP_OE", "DPREC_SCHUR", "
 
 
 # hop launch shapes: (block, lanes per site, block-to-XCD mapping, non-temporal links)
-SHAPES = [(256, 1, 1, 0), (64, 4, 1, 1), (192, 4, 0, 0), (128, 1, 0, 1), (128, 1, 2, 1), (256, 4, 2, 0)]
+SHAPES = [(256, 1, 1, 0), (64, 4, 1, 1), (192, 4, 0, 0), (128, 1, 0, 1), (128, 1, 2, 1), (256, 4, 2, 0),
+          (128, 2, 1, 1), (256, 2, 0, 0), (64, 2, 2, 1)]
 
 
 def shapes_for(dims):
