@@ -166,7 +166,8 @@ int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const
                      lqcd_solve_stats* stats);
 
 /* Native fast path (benchmarks, solvers in the caller): half-lattice fields of
- * one parity in the library's internal layout on the device. */
+ * one parity in the library's internal layout on the device (site-blocked:
+ * sites in blocks of 64, the count per parity rounded up to whole blocks). */
 size_t lqcd_field_bytes(lqcd_ctx* ctx, int prec);
 /* canonical full-lattice device vector -> native half field of the given parity */
 int lqcd_import(lqcd_ctx* ctx, int prec, int parity, const double* canon, void* native);

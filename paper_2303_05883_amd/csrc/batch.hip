@@ -177,19 +177,19 @@ __global__ void __launch_bounds__(BS) k_bblas(BBlasArgs b) {
     const size_t i = (size_t)blk * BS + threadIdx.x;
     const bool act = i < vh;
     if (OP == B_P_UPDATE) {
-      if (act) p_update_site<P>(S.f[F_R], S.f[F_P], S.f[F_V], S.sc, vh, i);
+      if (act) p_update_site<P>(S.f[F_R], S.f[F_P], S.f[F_V], S.sc, i);
     } else if (OP == B_S_UPDATE) {
-      if (act) s_update_site<P>(S.f[F_R], S.f[F_V], S.f[F_S], S.sc, vh, i);
+      if (act) s_update_site<P>(S.f[F_R], S.f[F_V], S.f[F_S], S.sc, i);
     } else {
       double red[3] = {0.0, 0.0, 0.0};
       if (OP == B_XR_UPDATE) {
         if (act)
-          xr_update_site<P, PX>(S.f[F_X], S.f[F_P], S.f[F_S], S.f[F_T], S.f[F_R], S.f[F_RHAT], S.sc, vh, i, red);
+          xr_update_site<P, PX>(S.f[F_X], S.f[F_P], S.f[F_S], S.f[F_T], S.f[F_R], S.f[F_RHAT], S.sc, i, red);
       } else {  // start: rhat = p = r, <rhat, r>, <r, r>
         if (act) {
-          copy_site<P>(S.f[F_R], S.f[F_RHAT], vh, i);
-          copy_site<P>(S.f[F_R], S.f[F_P], vh, i);
-          dot_norm_site<P>(S.f[F_R], S.f[F_R], vh, i, red);
+          copy_site<P>(S.f[F_R], S.f[F_RHAT], i);
+          copy_site<P>(S.f[F_R], S.f[F_P], i);
+          dot_norm_site<P>(S.f[F_R], S.f[F_R], i, red);
         }
       }
       block_reduce<3>(red, S.partials + (size_t)blk * 3);

@@ -25,7 +25,7 @@ template <int P>
 __global__ void __launch_bounds__(BS) k_p_update(const void* r, void* p, const void* v, const Scal* sc, size_t vh) {
   if (is_done(sc)) return;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i < vh) p_update_site<P>(r, p, v, sc, vh, i);
+  if (i < vh) p_update_site<P>(r, p, v, sc, i);
 }
 
 // s = r - alpha v
@@ -33,7 +33,7 @@ template <int P>
 __global__ void __launch_bounds__(BS) k_s_update(const void* r, const void* v, void* s, const Scal* sc, size_t vh) {
   if (is_done(sc)) return;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i < vh) s_update_site<P>(r, v, s, sc, vh, i);
+  if (i < vh) s_update_site<P>(r, v, s, sc, i);
 }
 
 // x += alpha p + omega s (x in precision PX); r = s - omega t; partials <rhat, r>, <r, r>
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(BS) k_xr_update(void* x, const void* p, const 
   if (is_done(sc)) return;
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
   double red[3] = {0.0, 0.0, 0.0};
-  if (i < vh) xr_update_site<P, PX>(x, p, s, t, r, rhat, sc, vh, i, red);
+  if (i < vh) xr_update_site<P, PX>(x, p, s, t, r, rhat, sc, i, red);
   block_reduce<3>(red, partials + (size_t)blockIdx.x * 3);
 }
 
@@ -52,7 +52,7 @@ template <int P>
 __global__ void __launch_bounds__(BS) k_dot_norm(const void* a, const void* b, double* partials, size_t vh) {
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
   double red[3] = {0.0, 0.0, 0.0};
-  if (i < vh) dot_norm_site<P>(a, b, vh, i, red);
+  if (i < vh) dot_norm_site<P>(a, b, i, red);
   block_reduce<3>(red, partials + (size_t)blockIdx.x * 3);
 }
 
@@ -62,14 +62,14 @@ __global__ void __launch_bounds__(BS) k_sub_norm(const void* a, const void* b, v
   double red[1] = {0.0};
   if (i < vh) {
     cx<double> av[12], bv[12];
-    IO<0>::load_spinor(a, vh, i, av);
-    IO<0>::load_spinor(b, vh, i, bv);
+    IO<0>::load_spinor(a, i, av);
+    IO<0>::load_spinor(b, i, bv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       av[k] = av[k] - bv[k];
       red[0] += av[k].r * av[k].r + av[k].i * av[k].i;
     }
-    IO<0>::store_spinor(out, vh, i, av);
+    IO<0>::store_spinor(out, i, av);
   }
   block_reduce<1>(red, partials + blockIdx.x);
 }
@@ -84,10 +84,10 @@ __global__ void __launch_bounds__(BS) k_scale_down(const void* src, void* dst, c
   const double s = dscale ? *dscale : hscale;
   cx<double> a[12];
   cx<TD> d[12];
-  IO<0>::load_spinor(src, vh, i, a);
+  IO<0>::load_spinor(src, i, a);
 #pragma unroll
   for (int k = 0; k < 12; ++k) d[k] = {(TD)(s * a[k].r), (TD)(s * a[k].i)};
-  IO<PD>::store_spinor(dst, vh, i, d);
+  IO<PD>::store_spinor(dst, i, d);
 }
 
 // x64 += scale * e (e in precision PS)
@@ -99,23 +99,23 @@ __global__ void __launch_bounds__(BS) k_accum_up(void* x, const void* e, const d
   const double s = *dscale;
   cx<double> a[12];
   cx<TS> b[12];
-  IO<0>::load_spinor(x, vh, i, a);
-  IO<PS>::load_spinor(e, vh, i, b);
+  IO<0>::load_spinor(x, i, a);
+  IO<PS>::load_spinor(e, i, b);
 #pragma unroll
   for (int k = 0; k < 12; ++k) a[k] = a[k] + s * cx<double>{(double)b[k].r, (double)b[k].i};
-  IO<0>::store_spinor(x, vh, i, a);
+  IO<0>::store_spinor(x, i, a);
 }
 
 template <int P>
 __global__ void __launch_bounds__(BS) k_copy(const void* src, void* dst, size_t vh) {
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i < vh) copy_site<P>(src, dst, vh, i);
+  if (i < vh) copy_site<P>(src, dst, i);
 }
 
 template <int P>
 __global__ void __launch_bounds__(BS) k_zero(void* dst, size_t vh) {
   const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (i < vh) zero_site<P>(dst, vh, i);
+  if (i < vh) zero_site<P>(dst, i);
 }
 
 // p *= f, v *= f (a reliable update changes the residual's normalisation)
@@ -126,14 +126,14 @@ __global__ void __launch_bounds__(BS) k_scale2(void* p, void* v, double f, size_
   if (i >= vh) return;
   const T s = (T)f;
   cx<T> a[12];
-  IO<P>::load_spinor(p, vh, i, a);
+  IO<P>::load_spinor(p, i, a);
 #pragma unroll
   for (int k = 0; k < 12; ++k) a[k] = s * a[k];
-  IO<P>::store_spinor(p, vh, i, a);
-  IO<P>::load_spinor(v, vh, i, a);
+  IO<P>::store_spinor(p, i, a);
+  IO<P>::load_spinor(v, i, a);
 #pragma unroll
   for (int k = 0; k < 12; ++k) a[k] = s * a[k];
-  IO<P>::store_spinor(v, vh, i, a);
+  IO<P>::store_spinor(v, i, a);
 }
 
 __global__ void __launch_bounds__(FBS) k_fin_reliable(Scal* sc, const double* partials, int n, double target2) {

@@ -15,57 +15,57 @@ __device__ inline cx<T> ld_scalar(const double* re_im) {
 
 // p = r + beta (p - omega v)
 template <int P>
-__device__ inline void p_update_site(const void* r, void* p, const void* v, const Scal* sc, size_t vh, size_t i) {
+__device__ inline void p_update_site(const void* r, void* p, const void* v, const Scal* sc, size_t i) {
   using T = typename IO<P>::T;
   const cx<T> beta = ld_scalar<T>(&sc->beta_r), omega = ld_scalar<T>(&sc->omega_r);
   cx<T> a[12], b[12], c[12];
-  IO<P>::load_spinor(r, vh, i, a);
-  IO<P>::load_spinor(p, vh, i, b);
-  IO<P>::load_spinor(v, vh, i, c);
+  IO<P>::load_spinor(r, i, a);
+  IO<P>::load_spinor(p, i, b);
+  IO<P>::load_spinor(v, i, c);
 #pragma unroll
   for (int k = 0; k < 12; ++k) b[k] = a[k] + beta * (b[k] - omega * c[k]);
-  IO<P>::store_spinor(p, vh, i, b);
+  IO<P>::store_spinor(p, i, b);
 }
 
 // s = r - alpha v
 template <int P>
-__device__ inline void s_update_site(const void* r, const void* v, void* s, const Scal* sc, size_t vh, size_t i) {
+__device__ inline void s_update_site(const void* r, const void* v, void* s, const Scal* sc, size_t i) {
   using T = typename IO<P>::T;
   const cx<T> alpha = ld_scalar<T>(&sc->alpha_r);
   cx<T> a[12], c[12];
-  IO<P>::load_spinor(r, vh, i, a);
-  IO<P>::load_spinor(v, vh, i, c);
+  IO<P>::load_spinor(r, i, a);
+  IO<P>::load_spinor(v, i, c);
 #pragma unroll
   for (int k = 0; k < 12; ++k) a[k] = a[k] - alpha * c[k];
-  IO<P>::store_spinor(s, vh, i, a);
+  IO<P>::store_spinor(s, i, a);
 }
 
 // x += alpha p + omega s (x in precision PX); r = s - omega t; red += <rhat, r>, <r, r>
 template <int P, int PX>
 __device__ inline void xr_update_site(void* x, const void* p, const void* s, const void* t, void* r, const void* rhat,
-                                      const Scal* sc, size_t vh, size_t i, double red[3]) {
+                                      const Scal* sc, size_t i, double red[3]) {
   using T = typename IO<P>::T;
   using TX = typename IO<PX>::T;
   const cx<T> omega = ld_scalar<T>(&sc->omega_r);
   const cx<TX> alx = ld_scalar<TX>(&sc->alpha_r), omx = ld_scalar<TX>(&sc->omega_r);
   cx<T> pv[12], sv[12], tv[12];
   cx<TX> xv[12];
-  IO<P>::load_spinor(p, vh, i, pv);
-  IO<P>::load_spinor(s, vh, i, sv);
-  IO<PX>::load_spinor(x, vh, i, xv);
+  IO<P>::load_spinor(p, i, pv);
+  IO<P>::load_spinor(s, i, sv);
+  IO<PX>::load_spinor(x, i, xv);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const cx<TX> pk = {(TX)pv[k].r, (TX)pv[k].i}, sk = {(TX)sv[k].r, (TX)sv[k].i};
     xv[k] = xv[k] + alx * pk + omx * sk;
   }
-  IO<PX>::store_spinor(x, vh, i, xv);
-  IO<P>::load_spinor(t, vh, i, tv);
+  IO<PX>::store_spinor(x, i, xv);
+  IO<P>::load_spinor(t, i, tv);
 #pragma unroll
   for (int k = 0; k < 12; ++k) sv[k] = sv[k] - omega * tv[k];
-  IO<P>::store_spinor(r, vh, i, sv);
+  IO<P>::store_spinor(r, i, sv);
   // FP16 codes round the stored value: reduce what was stored
-  if (P == 2) IO<P>::load_spinor(r, vh, i, sv);
-  IO<P>::load_spinor(rhat, vh, i, tv);
+  if (P == 2) IO<P>::load_spinor(r, i, sv);
+  IO<P>::load_spinor(rhat, i, tv);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const cx<T> d = cmulc(tv[k], sv[k]);
@@ -77,11 +77,11 @@ __device__ inline void xr_update_site(void* x, const void* p, const void* s, con
 
 // red += <a, b>, <b, b>
 template <int P>
-__device__ inline void dot_norm_site(const void* a, const void* b, size_t vh, size_t i, double red[3]) {
+__device__ inline void dot_norm_site(const void* a, const void* b, size_t i, double red[3]) {
   using T = typename IO<P>::T;
   cx<T> av[12], bv[12];
-  IO<P>::load_spinor(a, vh, i, av);
-  IO<P>::load_spinor(b, vh, i, bv);
+  IO<P>::load_spinor(a, i, av);
+  IO<P>::load_spinor(b, i, bv);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const cx<T> d = cmulc(av[k], bv[k]);
@@ -92,20 +92,20 @@ __device__ inline void dot_norm_site(const void* a, const void* b, size_t vh, si
 }
 
 template <int P>
-__device__ inline void copy_site(const void* src, void* dst, size_t vh, size_t i) {
+__device__ inline void copy_site(const void* src, void* dst, size_t i) {
   using T = typename IO<P>::T;
   cx<T> a[12];
-  IO<P>::load_spinor(src, vh, i, a);
-  IO<P>::store_spinor(dst, vh, i, a);
+  IO<P>::load_spinor(src, i, a);
+  IO<P>::store_spinor(dst, i, a);
 }
 
 template <int P>
-__device__ inline void zero_site(void* dst, size_t vh, size_t i) {
+__device__ inline void zero_site(void* dst, size_t i) {
   using T = typename IO<P>::T;
   cx<T> a[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) a[k] = {T(0), T(0)};
-  IO<P>::store_spinor(dst, vh, i, a);
+  IO<P>::store_spinor(dst, i, a);
 }
 
 __device__ inline void cdiv(double ar, double ai, double br, double bi, double& cr, double& ci) {

@@ -64,7 +64,7 @@ __device__ inline M3 link(const Geom& g, const char* g64, Site s, int mu) {
   const size_t i = (size_t)(s.c[0] >> 1) + (size_t)g.lxh * (s.c[1] + (size_t)g.ly * (s.c[2] + (size_t)g.lz * s.c[3]));
   const void* blk = g64 + (size_t)(p * 4 + mu) * link_bytes(0, g.vh);
   cx<double> u[6], r2[3];
-  IO<0>::load_link(blk, g.vh, i, u);
+  IO<0>::load_link(blk, i, u);
   reconstruct(u, r2);
   M3 m;
 #pragma unroll
@@ -168,19 +168,20 @@ __device__ bool invert6(const M6& in, M6& out) {
 }
 
 // Store a Hermitian 6x6 block (times `half`) into 18 slots of the FP64 layout.
-__device__ inline void store_block(void* dst, size_t vh, size_t i, int blk, const M6& m, double half) {
-  double2* b = reinterpret_cast<double2*>(dst) + (size_t)blk * 18 * vh;
+__device__ inline void store_block(void* dst, size_t i, int blk, const M6& m, double half) {
+  double2* b = reinterpret_cast<double2*>(dst);
+  const int o = blk * 18;
   // diagonal (real part; the imaginary part of a Hermitian diagonal is zero)
-  b[0 * vh + i] = make_double2(half * m.a[0].r, half * m.a[7].r);
-  b[1 * vh + i] = make_double2(half * m.a[14].r, half * m.a[21].r);
-  b[2 * vh + i] = make_double2(half * m.a[28].r, half * m.a[35].r);
+  b[widx(i, o + 0, 36)] = make_double2(half * m.a[0].r, half * m.a[7].r);
+  b[widx(i, o + 1, 36)] = make_double2(half * m.a[14].r, half * m.a[21].r);
+  b[widx(i, o + 2, 36)] = make_double2(half * m.a[28].r, half * m.a[35].r);
   int k = 3;
   for (int r = 0; r < 6; ++r)
     for (int c = r + 1; c < 6; ++c) {
       // average with the conjugate of the mirrored entry: exact for Hermitian input,
       // removes the rounding asymmetry of the inverse
       const cx<double> u = m.a[6 * r + c], l = conj(m.a[6 * c + r]);
-      b[(size_t)k * vh + i] = make_double2(half * 0.5 * (u.r + l.r), half * 0.5 * (u.i + l.i));
+      b[widx(i, o + k, 36)] = make_double2(half * 0.5 * (u.r + l.r), half * 0.5 * (u.i + l.i));
       ++k;
     }
 }
@@ -220,13 +221,13 @@ __global__ void __launch_bounds__(128) k_build_clover(Geom g, int p, const char*
     add_kron(m, sy, fyt, sg * kc);
     add_kron(m, sz, fxy, kc);
     add_kron(m, sz, fzt, sg * kc);
-    store_block(a_out, g.vh, i, blk, m, 0.5);
+    store_block(a_out, i, blk, m, 0.5);
     M6 inv;
     if (!invert6(m, inv)) {
       ok = false;
       for (int k = 0; k < 36; ++k) inv.a[k] = {0.0, 0.0};
     }
-    store_block(ainv_out, g.vh, i, blk, inv, 0.5);
+    store_block(ainv_out, i, blk, inv, 0.5);
   }
   if (!ok) atomicOr(flag, 1ull);
 }
@@ -238,16 +239,16 @@ __global__ void __launch_bounds__(256) k_clover_down(const double2* src, size_t 
   for (int k = 0; k < 9; ++k) {
     double2 v[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = src[(size_t)(4 * k + j) * vh + i];
-    d32[(size_t)(2 * k) * vh + i] = make_float4((float)v[0].x, (float)v[0].y, (float)v[1].x, (float)v[1].y);
-    d32[(size_t)(2 * k + 1) * vh + i] = make_float4((float)v[2].x, (float)v[2].y, (float)v[3].x, (float)v[3].y);
+    for (int j = 0; j < 4; ++j) v[j] = src[widx(i, 4 * k + j, 36)];
+    d32[widx(i, 2 * k, 18)] = make_float4((float)v[0].x, (float)v[0].y, (float)v[1].x, (float)v[1].y);
+    d32[widx(i, 2 * k + 1, 18)] = make_float4((float)v[2].x, (float)v[2].y, (float)v[3].x, (float)v[3].y);
     half8 h;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       h[2 * j] = (_Float16)v[j].x;
       h[2 * j + 1] = (_Float16)v[j].y;
     }
-    d16[(size_t)k * vh + i] = h;
+    d16[widx(i, k, 9)] = h;
   }
 }
 

@@ -36,132 +36,146 @@ __device__ inline half4 ld8(const half4* p) {
   return *p;
 }
 
+// Site-blocked layout: a field is a sequence of blocks of SB consecutive
+// sites; inside a block, word k of every site is stored together (SB words of
+// 16 bytes, 8 for FP16 links), so one wavefront reads each word of its 64
+// sites from one contiguous 1 KiB run and every block of a field is one
+// contiguous region. Word index of word k (of nw) of site i:
+__device__ inline size_t widx(size_t i, int k, int nw) {
+  return ((i / SB) * (size_t)nw + (size_t)k) * SB + (i % SB);
+}
+
 template <int P>
 struct IO;
 
 // ------------------------------------------------------------------ FP64
+// spinor: 12 words (spin-major complex), link: 6 words (rows 0, 1), clover:
+// 36 words (18 per chiral block)
 template <>
 struct IO<0> {
   using T = double;
-  __device__ static inline void load_spinor(const void* f, size_t vh, size_t i, cx<T> s[12]) {
+  __device__ static inline void load_spinor(const void* f, size_t i, cx<T> s[12]) {
     const double2* b = reinterpret_cast<const double2*>(f);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      double2 v = b[k * vh + i];
+      double2 v = b[widx(i, k, 12)];
       s[k] = {v.x, v.y};
     }
   }
   // sel 0: the whole spinor; sel 1: spins 0,1 into both halves; sel 2: spins
   // 2,3 into both halves (one instruction stream whatever the lane's sel)
-  __device__ static inline void load_spinor_sel(const void* f, size_t vh, size_t i, int sel, cx<T> s[12]) {
+  __device__ static inline void load_spinor_sel(const void* f, size_t i, int sel, cx<T> s[12]) {
     const double2* b = reinterpret_cast<const double2*>(f);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const int h = sel == 0 ? k / 6 : sel - 1;
-      double2 v = b[(size_t)(k % 6 + 6 * h) * vh + i];
+      double2 v = b[widx(i, k % 6 + 6 * h, 12)];
       s[k] = {v.x, v.y};
     }
   }
   // spins 0,1 (upper = true) or spins 2,3 into s[0..5]
-  __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
-    const double2* b = reinterpret_cast<const double2*>(f) + (upper ? 0 : 6 * vh);
+  __device__ static inline void load_half(const void* f, size_t i, bool upper, cx<T> s[6]) {
+    const double2* b = reinterpret_cast<const double2*>(f);
+    const int o = upper ? 0 : 6;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double2 v = b[k * vh + i];
+      double2 v = b[widx(i, o + k, 12)];
       s[k] = {v.x, v.y};
     }
   }
-  __device__ static inline void store_spinor(void* f, size_t vh, size_t i, const cx<T> s[12]) {
+  __device__ static inline void store_spinor(void* f, size_t i, const cx<T> s[12]) {
     double2* b = reinterpret_cast<double2*>(f);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) b[k * vh + i] = make_double2(s[k].r, s[k].i);
+    for (int k = 0; k < 12; ++k) b[widx(i, k, 12)] = make_double2(s[k].r, s[k].i);
   }
-  // planes k with k % nl == lane (the lanes of one site share the stores)
-  __device__ static inline void store_part(void* f, size_t vh, size_t i, const cx<T> s[12], int lane, int nl) {
+  // words k with k % nl == lane (the lanes of one site share the stores)
+  __device__ static inline void store_part(void* f, size_t i, const cx<T> s[12], int lane, int nl) {
     double2* b = reinterpret_cast<double2*>(f);
 #pragma unroll
     for (int k = 0; k < 12; ++k)
-      if (k % nl == lane) b[k * vh + i] = make_double2(s[k].r, s[k].i);
+      if (k % nl == lane) b[widx(i, k, 12)] = make_double2(s[k].r, s[k].i);
   }
   template <bool NT = false>
-  __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
+  __device__ static inline void load_link(const void* g, size_t i, cx<T> u[6]) {
     const double2* b = reinterpret_cast<const double2*>(g);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double2 v = ld16<NT>(b + k * vh + i);
+      double2 v = ld16<NT>(b + widx(i, k, 6));
       u[k] = {v.x, v.y};
     }
   }
   // 18 complex slots of one chiral block (blk = 0: +, 1: -)
-  __device__ static inline void load_clover_block(const void* c, size_t vh, size_t i, int blk, cx<T> m[18]) {
-    const double2* b = reinterpret_cast<const double2*>(c) + (size_t)blk * 18 * vh;
+  __device__ static inline void load_clover_block(const void* c, size_t i, int blk, cx<T> m[18]) {
+    const double2* b = reinterpret_cast<const double2*>(c);
 #pragma unroll
     for (int k = 0; k < 18; ++k) {
-      double2 v = b[k * vh + i];
+      double2 v = b[widx(i, blk * 18 + k, 36)];
       m[k] = {v.x, v.y};
     }
   }
 };
 
 // ------------------------------------------------------------------ FP32
+// spinor: 6 words of 2 complex, link: 3 words, clover: 18 words (9 per block)
 template <>
 struct IO<1> {
   using T = float;
-  __device__ static inline void load_spinor(const void* f, size_t vh, size_t i, cx<T> s[12]) {
+  __device__ static inline void load_spinor(const void* f, size_t i, cx<T> s[12]) {
     const float4* b = reinterpret_cast<const float4*>(f);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float4 v = b[k * vh + i];
+      float4 v = b[widx(i, k, 6)];
       s[2 * k] = {v.x, v.y};
       s[2 * k + 1] = {v.z, v.w};
     }
   }
-  __device__ static inline void load_spinor_sel(const void* f, size_t vh, size_t i, int sel, cx<T> s[12]) {
+  __device__ static inline void load_spinor_sel(const void* f, size_t i, int sel, cx<T> s[12]) {
     const float4* b = reinterpret_cast<const float4*>(f);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int h = sel == 0 ? k / 3 : sel - 1;
-      float4 v = b[(size_t)(k % 3 + 3 * h) * vh + i];
+      float4 v = b[widx(i, k % 3 + 3 * h, 6)];
       s[2 * k] = {v.x, v.y};
       s[2 * k + 1] = {v.z, v.w};
     }
   }
-  __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
-    const float4* b = reinterpret_cast<const float4*>(f) + (upper ? 0 : 3 * vh);
+  __device__ static inline void load_half(const void* f, size_t i, bool upper, cx<T> s[6]) {
+    const float4* b = reinterpret_cast<const float4*>(f);
+    const int o = upper ? 0 : 3;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float4 v = b[k * vh + i];
+      float4 v = b[widx(i, o + k, 6)];
       s[2 * k] = {v.x, v.y};
       s[2 * k + 1] = {v.z, v.w};
     }
   }
-  __device__ static inline void store_spinor(void* f, size_t vh, size_t i, const cx<T> s[12]) {
+  __device__ static inline void store_spinor(void* f, size_t i, const cx<T> s[12]) {
     float4* b = reinterpret_cast<float4*>(f);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      b[k * vh + i] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
+      b[widx(i, k, 6)] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
   }
-  __device__ static inline void store_part(void* f, size_t vh, size_t i, const cx<T> s[12], int lane, int nl) {
+  __device__ static inline void store_part(void* f, size_t i, const cx<T> s[12], int lane, int nl) {
     float4* b = reinterpret_cast<float4*>(f);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      if (k % nl == lane) b[k * vh + i] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
+      if (k % nl == lane) b[widx(i, k, 6)] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
   }
   template <bool NT = false>
-  __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
+  __device__ static inline void load_link(const void* g, size_t i, cx<T> u[6]) {
     const float4* b = reinterpret_cast<const float4*>(g);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float4 v = ld16<NT>(b + k * vh + i);
+      float4 v = ld16<NT>(b + widx(i, k, 3));
       u[2 * k] = {v.x, v.y};
       u[2 * k + 1] = {v.z, v.w};
     }
   }
-  __device__ static inline void load_clover_block(const void* c, size_t vh, size_t i, int blk, cx<T> m[18]) {
-    const float4* b = reinterpret_cast<const float4*>(c) + (size_t)blk * 9 * vh;
+  __device__ static inline void load_clover_block(const void* c, size_t i, int blk, cx<T> m[18]) {
+    const float4* b = reinterpret_cast<const float4*>(c);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      float4 v = b[k * vh + i];
+      float4 v = b[widx(i, blk * 9 + k, 18)];
       m[2 * k] = {v.x, v.y};
       m[2 * k + 1] = {v.z, v.w};
     }
@@ -169,57 +183,50 @@ struct IO<1> {
 };
 
 // ------------------------------------------------------------------ FP16
+// spinor block: 3 words of 4 complex (half8, in units of the site's scale)
+// for each of the SB sites, then the SB float scales (max |component|);
+// link: 3 words of 8 bytes (half4); clover: 9 half8 words (36 complex)
 template <>
 struct IO<2> {
   using T = float;
-  __device__ static inline const float* norms(const void* f, size_t vh) {
-    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(f) + 48 * vh);
+  static constexpr size_t BLOCK_BYTES = SB * (3 * 16 + 4);
+  __device__ static inline const half8* words(const void* f, size_t i) {
+    return reinterpret_cast<const half8*>(reinterpret_cast<const char*>(f) + (i / SB) * BLOCK_BYTES) + (i % SB);
   }
-  __device__ static inline void load_spinor(const void* f, size_t vh, size_t i, cx<T> s[12]) {
-    const half8* b = reinterpret_cast<const half8*>(f);
-    const float n = norms(f, vh)[i];
+  __device__ static inline half8* words(void* f, size_t i) {
+    return reinterpret_cast<half8*>(reinterpret_cast<char*>(f) + (i / SB) * BLOCK_BYTES) + (i % SB);
+  }
+  __device__ static inline float* scale(const void* f, size_t i) {
+    return reinterpret_cast<float*>(const_cast<char*>(reinterpret_cast<const char*>(f)) + (i / SB) * BLOCK_BYTES +
+                                    3 * 16 * SB) + (i % SB);
+  }
+  __device__ static inline void load_spinor(const void* f, size_t i, cx<T> s[12]) {
+    const half8* b = words(f, i);
+    const float n = *scale(f, i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      half8 v = b[k * vh + i];
+      half8 v = b[k * SB];
 #pragma unroll
       for (int j = 0; j < 4; ++j) s[4 * k + j] = {n * (float)v[2 * j], n * (float)v[2 * j + 1]};
     }
   }
-  // the FP16 planes mix spins 1 and 2, so every selection loads the whole spinor
-  __device__ static inline void load_spinor_sel(const void* f, size_t vh, size_t i, int, cx<T> s[12]) {
-    load_spinor(f, vh, i, s);
+  // the FP16 words mix spins 1 and 2, so every selection loads the whole spinor
+  __device__ static inline void load_spinor_sel(const void* f, size_t i, int, cx<T> s[12]) {
+    load_spinor(f, i, s);
   }
-  __device__ static inline void load_half(const void* f, size_t vh, size_t i, bool upper, cx<T> s[6]) {
+  __device__ static inline void load_half(const void* f, size_t i, bool upper, cx<T> s[6]) {
     cx<T> all[12];
-    load_spinor(f, vh, i, all);
+    load_spinor(f, i, all);
 #pragma unroll
     for (int k = 0; k < 6; ++k) s[k] = all[(upper ? 0 : 6) + k];
   }
-  __device__ static inline void store_spinor(void* f, size_t vh, size_t i, const cx<T> s[12]) {
+  // words 0..2 and the scale (as word 3), those with k % nl == lane
+  __device__ static inline void store_part(void* f, size_t i, const cx<T> s[12], int lane, int nl) {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].r), fabsf(s[k].i)));
     const float inv = m > 0.f ? 1.0f / m : 0.f;
-    half8* b = reinterpret_cast<half8*>(f);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      half8 v;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        v[2 * j] = (_Float16)(s[4 * k + j].r * inv);
-        v[2 * j + 1] = (_Float16)(s[4 * k + j].i * inv);
-      }
-      b[k * vh + i] = v;
-    }
-    reinterpret_cast<float*>(reinterpret_cast<char*>(f) + 48 * vh)[i] = m;
-  }
-  // planes 0..2 and the scale (as plane 3), k % nl == lane
-  __device__ static inline void store_part(void* f, size_t vh, size_t i, const cx<T> s[12], int lane, int nl) {
-    float m = 0.f;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].r), fabsf(s[k].i)));
-    const float inv = m > 0.f ? 1.0f / m : 0.f;
-    half8* b = reinterpret_cast<half8*>(f);
+    half8* b = words(f, i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (k % nl != lane) continue;
@@ -229,31 +236,32 @@ struct IO<2> {
         v[2 * j] = (_Float16)(s[4 * k + j].r * inv);
         v[2 * j + 1] = (_Float16)(s[4 * k + j].i * inv);
       }
-      b[k * vh + i] = v;
+      b[k * SB] = v;
     }
-    if (3 % nl == lane) reinterpret_cast<float*>(reinterpret_cast<char*>(f) + 48 * vh)[i] = m;
+    if (3 % nl == lane) *scale(f, i) = m;
   }
+  __device__ static inline void store_spinor(void* f, size_t i, const cx<T> s[12]) { store_part(f, i, s, 0, 1); }
   template <bool NT = false>
-  __device__ static inline void load_link(const void* g, size_t vh, size_t i, cx<T> u[6]) {
+  __device__ static inline void load_link(const void* g, size_t i, cx<T> u[6]) {
     const half4* b = reinterpret_cast<const half4*>(g);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      half4 v = ld8<NT>(b + k * vh + i);
+      half4 v = ld8<NT>(b + widx(i, k, 3));
       u[2 * k] = {(float)v[0], (float)v[1]};
       u[2 * k + 1] = {(float)v[2], (float)v[3]};
     }
   }
-  // block + is complex 0..17 (planes 0..4), block - is complex 18..35 (planes 4..8)
-  __device__ static inline void load_clover_block(const void* c, size_t vh, size_t i, int blk, cx<T> m[18]) {
-    const half8* b = reinterpret_cast<const half8*>(c) + (size_t)(blk * 4) * vh;
+  // block + is complex 0..17 (words 0..4), block - is complex 18..35 (words 4..8)
+  __device__ static inline void load_clover_block(const void* c, size_t i, int blk, cx<T> m[18]) {
+    const half8* b = reinterpret_cast<const half8*>(c);
     cx<T> part[20];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      half8 v = b[k * vh + i];
+      half8 v = b[widx(i, blk * 4 + k, 9)];
 #pragma unroll
       for (int j = 0; j < 4; ++j) part[4 * k + j] = {(float)v[2 * j], (float)v[2 * j + 1]};
     }
-    const int off = blk * 2;  // complex 18 is element 2 of plane 4
+    const int off = blk * 2;  // complex 18 is element 2 of word 4
 #pragma unroll
     for (int k = 0; k < 18; ++k) m[k] = part[k + off];
   }
@@ -287,7 +295,7 @@ __device__ inline void herm6_mul(const cx<T> m[18], const cx<T> x[6], cx<T> y[6]
 
 // out = A psi with A given by its two chiral blocks (1/2 of the basis change folded in).
 template <int P>
-__device__ inline void clover_apply(const void* clov, size_t vh, size_t i, const cx<typename IO<P>::T> in[12],
+__device__ inline void clover_apply(const void* clov, size_t i, const cx<typename IO<P>::T> in[12],
                                     cx<typename IO<P>::T> out[12]) {
   using T = typename IO<P>::T;
   cx<T> chp[6], chm[6], yp[6], ym[6], m[18];
@@ -296,9 +304,9 @@ __device__ inline void clover_apply(const void* clov, size_t vh, size_t i, const
     chp[k] = in[k] - in[k + 6];
     chm[k] = in[k] + in[k + 6];
   }
-  IO<P>::load_clover_block(clov, vh, i, 0, m);
+  IO<P>::load_clover_block(clov, i, 0, m);
   herm6_mul(m, chp, yp);
-  IO<P>::load_clover_block(clov, vh, i, 1, m);
+  IO<P>::load_clover_block(clov, i, 1, m);
   herm6_mul(m, chm, ym);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -319,6 +327,23 @@ __device__ inline double quad_swap(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+// v(lane) + v(lane xor 32): the two halves of the wavefront swap values
+// (v_permlane32_swap exchanges lanes 32..63 of its first operand with lanes
+// 0..31 of its second, so the two results hold own + partner in every lane).
+__device__ inline float half_sum(float v) {
+  const int b = __builtin_bit_cast(int, v);
+  const auto r = __builtin_amdgcn_permlane32_swap(b, b, false, false);
+  return __builtin_bit_cast(float, (int)r[0]) + __builtin_bit_cast(float, (int)r[1]);
+}
+__device__ inline double half_sum(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = (int)(unsigned)(b & 0xffffffffull), hi = (int)(unsigned)(b >> 32);
+  const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double a0 = __builtin_bit_cast(double, ((unsigned long long)(unsigned)rh[0] << 32) | (unsigned)rl[0]);
+  const double a1 = __builtin_bit_cast(double, ((unsigned long long)(unsigned)rh[1] << 32) | (unsigned)rl[1]);
+  return a0 + a1;
 }
 // Sum over the four lanes of a quad; every lane receives the total.
 template <typename T>

@@ -53,7 +53,6 @@ template <int P, int EPI, bool CLOV, int RED, bool NT>
 __global__ void __launch_bounds__(256) k_hop4(HopArgs a) {
   using T = typename IO<P>::T;
   if (a.skip && *a.skip) return;
-  const size_t vh = (size_t)a.g.vh;
   const int blk = blockIdx.x;
   const int mu = threadIdx.x & 3;
   size_t i = 0;
@@ -90,10 +89,10 @@ __global__ void __launch_bounds__(256) k_hop4(HopArgs a) {
     cx<T> sf[12], sb[12], uf[6], ub[6];
     const char* lf = a.gauge + (size_t)(a.p * 4 + mu) * a.link_stride;
     const char* lb = a.gauge + (size_t)((1 - a.p) * 4 + mu) * a.link_stride;
-    IO<P>::template load_link<NT>(lf, vh, i, uf);
-    IO<P>::template load_link<NT>(lb, vh, (size_t)nb, ub);
-    IO<P>::load_spinor_sel(a.in, vh, (size_t)nf, tdir ? 2 : 0, sf);
-    IO<P>::load_spinor_sel(a.in, vh, (size_t)nb, tdir ? 1 : 0, sb);
+    IO<P>::template load_link<NT>(lf, i, uf);
+    IO<P>::template load_link<NT>(lb, (size_t)nb, ub);
+    IO<P>::load_spinor_sel(a.in, (size_t)nf, tdir ? 2 : 0, sf);
+    IO<P>::load_spinor_sel(a.in, (size_t)nb, tdir ? 1 : 0, sb);
     // projection h0 = A s0 + C0 s_{j0}, h1 = A s1 + C1 s_{j1} (j0, j1 = 3, 2 for
     // x and y, 2, 3 for z and t); expansion upper += B w, lower0 += D0 w_{m0},
     // lower1 += D1 w_{m1} (m0, m1 = 1, 0 for x and y, 0, 1 for z and t).
@@ -150,20 +149,23 @@ __global__ void __launch_bounds__(256) k_hop4(HopArgs a) {
     cx<T> out[12];
     hop_epilogue<P, EPI, CLOV, RED>(a, i, acc, out, red);
     if (mu != 0) red[0] = red[1] = red[2] = 0.0;
-    IO<P>::store_part(a.out, vh, i, out, mu, 4);
+    IO<P>::store_part(a.out, i, out, mu, 4);
   }
   if constexpr (NR > 0) block_reduce<NR>(red, a.partials + (size_t)blk * NR);
 }
 
 
-// Pair-split hop: two lanes share one output site, lane 0 taking the four
-// forward hops and lane 1 the four backward ones, in one instruction stream
-// (the two differ only in signs, the neighbour and link they read, and U
-// against U^dag). A CU then holds half as many sites in flight as with one
-// lane per site for the same bytes in flight, so the z and t neighbours of
-// those sites stay in the XCD's L2; the two partial sums are added with one
-// DPP exchange. The loads of HOP2_PF directions are issued ahead of the
-// arithmetic of the current one.
+// Pair-split hop: two lanes share one output site, one taking the four
+// forward hops and the other the four backward ones, in one instruction
+// stream (the two differ only in signs, the neighbour and link they read, and
+// U against U^dag). Lanes 0..31 of a wavefront take the forward hops of 32
+// consecutive sites and lanes 32..63 the backward hops of the same sites, so
+// every load instruction still reads whole contiguous runs (two 512-byte runs)
+// and the partial sums meet with one cross-half lane swap. A CU then holds
+// half as many sites in flight as with one lane per site for the same bytes in
+// flight, so more of the z and t neighbours of those sites are still in the
+// XCD's L2. The loads of HOP2_PF directions are issued ahead of the arithmetic
+// of the current one.
 #ifndef HOP2_PF
 #define HOP2_PF 2
 #endif
@@ -176,9 +178,9 @@ struct PairIn {
 template <int P, int MU, bool NT>
 __device__ inline void pair_load(const void* in, const char* links, size_t vh, size_t nbr, size_t lidx, bool fwd,
                                  PairIn<P>& d) {
-  IO<P>::template load_link<NT>(links, vh, lidx, d.u);
-  if (MU == 3) IO<P>::load_spinor_sel(in, vh, nbr, fwd ? 2 : 1, d.s);  // the needed half, in both halves
-  else IO<P>::load_spinor(in, vh, nbr, d.s);
+  IO<P>::template load_link<NT>(links, lidx, d.u);
+  if (MU == 3) IO<P>::load_spinor_sel(in, nbr, fwd ? 2 : 1, d.s);  // the needed half, in both halves
+  else IO<P>::load_spinor(in, nbr, d.s);
 }
 
 template <int P, int MU>
@@ -254,10 +256,10 @@ __global__ void __launch_bounds__(256) k_hop2(HopArgs a) {
   if (a.skip && *a.skip) return;
   const size_t vh = (size_t)a.g.vh;
   const int blk = blockIdx.x;
-  const int lane = threadIdx.x & 1;
-  const bool fwd = lane == 0;
+  const int half = (threadIdx.x >> 5) & 1;
+  const bool fwd = half == 0;
   size_t i = 0;
-  const bool active = map_site(a, blockDim.x >> 1, threadIdx.x >> 1, i);
+  const bool active = map_site(a, blockDim.x >> 1, ((threadIdx.x >> 6) << 5) | (threadIdx.x & 31), i);
   constexpr int NR = RED == RED_DOT ? 2 : (RED == RED_TS ? 3 : 0);
   double red[3] = {0.0, 0.0, 0.0};
   if (active) {
@@ -306,11 +308,11 @@ __global__ void __launch_bounds__(256) k_hop2(HopArgs a) {
 #undef LD
 #undef CP
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = {acc[k].r + quad_swap<0xB1>(acc[k].r), acc[k].i + quad_swap<0xB1>(acc[k].i)};
+    for (int k = 0; k < 12; ++k) acc[k] = {half_sum(acc[k].r), half_sum(acc[k].i)};
     cx<T> out[12];
     hop_epilogue<P, EPI, CLOV, RED>(a, i, acc, out, red);
-    if (lane != 0) red[0] = red[1] = red[2] = 0.0;
-    IO<P>::store_part(a.out, vh, i, out, lane, 2);
+    if (half != 0) red[0] = red[1] = red[2] = 0.0;
+    IO<P>::store_part(a.out, i, out, half, 2);
   }
   if constexpr (NR > 0) block_reduce<NR>(red, a.partials + (size_t)blk * NR);
 }
@@ -321,12 +323,12 @@ __global__ void __launch_bounds__(256) k_site(const void* clov, const void* in, 
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= vh) return;
   cx<T> s[12], o[12];
-  IO<P>::load_spinor(in, vh, i, s);
+  IO<P>::load_spinor(in, i, s);
   if (clov) {
-    clover_apply<P>(clov, vh, i, s, o);
-    IO<P>::store_spinor(out, vh, i, o);
+    clover_apply<P>(clov, i, s, o);
+    IO<P>::store_spinor(out, i, o);
   } else {
-    IO<P>::store_spinor(out, vh, i, s);
+    IO<P>::store_spinor(out, i, s);
   }
 }
 

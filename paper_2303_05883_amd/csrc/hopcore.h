@@ -92,17 +92,17 @@ __device__ inline void hop_dir(const void* in, const void* links, size_t vh, siz
   if (MU == 3) {
     // (1 - gamma_t) psi = 2 (0, 0, psi_2, psi_3); (1 + gamma_t) psi = 2 (psi_0, psi_1, 0, 0)
     cx<T> half[6];
-    IO<P>::load_half(in, vh, nbr, !FWD, half);
+    IO<P>::load_half(in, nbr, !FWD, half);
     const T two = flip ? T(-2) : T(2);
 #pragma unroll
     for (int k = 0; k < 6; ++k) h[k] = two * half[k];
   } else {
     cx<T> s[12];
-    IO<P>::load_spinor(in, vh, nbr, s);
+    IO<P>::load_spinor(in, nbr, s);
     project<MU, FWD>(s, h);
   }
   cx<T> u[6], w[6];
-  IO<P>::template load_link<NT>(links, vh, lidx, u);
+  IO<P>::template load_link<NT>(links, lidx, u);
   link_mul<FWD>(u, h, w);
   expand<MU, FWD>(acc, w);
 }
@@ -151,7 +151,6 @@ template <int P, int EPI, bool CLOV, int RED>
 __device__ inline void hop_epilogue(const HopArgs& a, size_t i, cx<typename IO<P>::T> acc[12],
                                     cx<typename IO<P>::T> out[12], double red[3]) {
   using T = typename IO<P>::T;
-  const size_t vh = (size_t)a.g.vh;
   const T sc = (T)a.scale;
   if (EPI == EPI_SCALE) {
 #pragma unroll
@@ -159,13 +158,13 @@ __device__ inline void hop_epilogue(const HopArgs& a, size_t i, cx<typename IO<P
   } else if (EPI == EPI_SCALE_CLOV) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
-    clover_apply<P>(a.clov, vh, i, acc, out);
+    clover_apply<P>(a.clov, i, acc, out);
   } else {
     cx<T> xo[12];
-    IO<P>::load_spinor(a.xown, vh, i, xo);
+    IO<P>::load_spinor(a.xown, i, xo);
     if (CLOV) {
       cx<T> cxo[12];
-      clover_apply<P>(a.clov, vh, i, xo, cxo);
+      clover_apply<P>(a.clov, i, xo, cxo);
 #pragma unroll
       for (int k = 0; k < 12; ++k) out[k] = cxo[k] + sc * acc[k];
     } else {
@@ -185,7 +184,7 @@ __device__ inline void hop_epilogue(const HopArgs& a, size_t i, cx<typename IO<P
   }
   if (RED == RED_DOT) {
     cx<T> wv[12];
-    IO<P>::load_spinor(a.w, vh, i, wv);
+    IO<P>::load_spinor(a.w, i, wv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const cx<T> d = cmulc(wv[k], out[k]);
@@ -243,7 +242,7 @@ __device__ inline void hop_site(const HopArgs& a, size_t i, double red[3]) {
 
   cx<T> out[12];
   hop_epilogue<P, EPI, CLOV, RED>(a, i, acc, out, red);
-  IO<P>::store_spinor(a.out, vh, i, out);
+  IO<P>::store_spinor(a.out, i, out);
 }
 
 // ------------------------------------------------------------------ several right-hand sides
@@ -265,7 +264,7 @@ __device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, 
                                      bool flip, cx<typename IO<P>::T> acc[NB][12]) {
   using T = typename IO<P>::T;
   cx<T> u[6], r2[3];
-  IO<P>::template load_link<NT>(links, vh, lidx, u);
+  IO<P>::template load_link<NT>(links, lidx, u);
   reconstruct(u, r2);
   const cx<T> M[9] = {u[0], u[1], u[2], u[3], u[4], u[5], r2[0], r2[1], r2[2]};
 #pragma unroll
@@ -274,13 +273,13 @@ __device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, 
     cx<T> h[6];
     if (MU == 3) {
       cx<T> half[6];
-      IO<P>::load_half(m.in[r], vh, nbr, !FWD, half);
+      IO<P>::load_half(m.in[r], nbr, !FWD, half);
       const T two = flip ? T(-2) : T(2);
 #pragma unroll
       for (int k = 0; k < 6; ++k) h[k] = two * half[k];
     } else {
       cx<T> s[12];
-      IO<P>::load_spinor(m.in[r], vh, nbr, s);
+      IO<P>::load_spinor(m.in[r], nbr, s);
       project<MU, FWD>(s, h);
     }
     cx<T> w[6];
@@ -357,7 +356,7 @@ __device__ inline void hop_site_multi(const HopArgs& a, const MultiPtrs<NB>& m, 
     aq.w = m.w[q];
     cx<T> out[12];
     hop_epilogue<P, EPI, CLOV, RED>(aq, i, acc[q], out, red[q]);
-    IO<P>::store_spinor(m.out[q], vh, i, out);
+    IO<P>::store_spinor(m.out[q], i, out);
   }
 }
 

@@ -3,19 +3,24 @@
 //
 // Native layouts (all fields are checkerboarded: one array per parity, site
 // index i = x/2 + (Lx/2) * (y + Ly * (z + Lz * t)) among the sites of that
-// parity). Every field is a set of "planes"; plane k holds one 16-byte vector
-// per site, so a wavefront's 64 lanes read 1 KiB of contiguous memory per
-// plane (structure of arrays, coalesced).
+// parity). A site's data is a list of "words" of 16 bytes (8 for FP16 links).
+// Fields are site-blocked: blocks of SB = 64 consecutive sites, and inside a
+// block word k of all 64 sites stored together (word-major), so a wavefront
+// reads each word of its 64 sites as one contiguous 1 KiB run and a block of
+// a field is one contiguous region of memory (few DRAM pages and TLB entries
+// per wavefront, where separate full-length planes would touch one page per
+// word). The site count per parity is rounded up to a multiple of SB; the
+// padding sites are never read or written.
 //
 //   spinor, 12 complex (index 3*spin + colour):
-//     F64: 12 planes of double2 (one complex each)
-//     F32:  6 planes of float4  (two complex each)
-//     F16:  3 planes of 8 x fp16 (four complex each) + 1 plane of float, the
-//           per-site scale s = max |re|, |im| over the 24 reals (s = 0 for an
-//           all-zero site, whose codes are then all zero)
+//     F64: 12 words of double2 (one complex each)
+//     F32:  6 words of float4  (two complex each)
+//     F16:  3 words of 8 x fp16 (four complex each) per site, then the block's
+//           64 per-site scales s = max |re|, |im| over the 24 reals (float;
+//           s = 0 for an all-zero site, whose codes are then all zero)
 //   link, rows 0 and 1 of the SU(3) matrix (6 complex, index 3*row + col);
 //     row 2 = conj(row0 x row1) is rebuilt in registers:
-//     F64: 6 planes of double2, F32: 3 planes of float4, F16: 3 planes of 4 x fp16
+//     F64: 6 words of double2, F32: 3 words of float4, F16: 3 words of 4 x fp16
 //     gauge[p][mu] holds U_mu(x) for the sites x of parity p.
 //   clover, one parity: the site matrix A (or A^-1) in the chiral basis
 //     chi_+ = psi_{0,1} - psi_{2,3}, chi_- = psi_{0,1} + psi_{2,3}, where it is
@@ -23,7 +28,7 @@
 //     basis change. Per block 18 complex slots: slots 0..2 hold the real
 //     diagonal as (d0,d1), (d2,d3), (d4,d5); slots 3..17 hold the upper
 //     off-diagonal entries (i<j) in row-major order. Block + then block -.
-//     F64: 36 planes of double2, F32: 18 planes of float4, F16: 9 planes of 8 x fp16.
+//     F64: 36 words of double2, F32: 18 words of float4, F16: 9 words of 8 x fp16.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -77,17 +82,24 @@ template <typename T>
 __host__ __device__ inline cx<T> mul_mi(cx<T> a) { return {a.i, -a.r}; }
 
 // ---------------------------------------------------------------- precisions
-// Number of 16-byte planes per field of each kind, per precision.
-constexpr int spinor_planes(int prec) { return prec == 0 ? 12 : (prec == 1 ? 6 : 3); }
-constexpr int clover_planes(int prec) { return prec == 0 ? 36 : (prec == 1 ? 18 : 9); }
+constexpr int SB = 64;  // sites per block of the site-blocked layout
+// Sites per parity rounded up to whole blocks.
+__host__ __device__ inline size_t padded_sites(size_t vh) { return (vh + SB - 1) / SB * SB; }
+// Number of 16-byte words per site of each kind, per precision.
+constexpr int spinor_words(int prec) { return prec == 0 ? 12 : (prec == 1 ? 6 : 3); }
+constexpr int clover_words(int prec) { return prec == 0 ? 36 : (prec == 1 ? 18 : 9); }
 
 // Bytes of one native half field (one parity) of the given precision.
 __host__ __device__ inline size_t spinor_bytes(int prec, size_t vh) {
-  return (size_t)spinor_planes(prec) * 16 * vh + (prec == 2 ? 4 * vh : 0);
+  return ((size_t)spinor_words(prec) * 16 + (prec == 2 ? 4 : 0)) * padded_sites(vh);
 }
 // Bytes of the links of one (parity, mu).
-__host__ __device__ inline size_t link_bytes(int prec, size_t vh) { return (prec == 2 ? 24 : (prec == 1 ? 48 : 96)) * vh; }
-__host__ __device__ inline size_t clover_bytes(int prec, size_t vh) { return (size_t)clover_planes(prec) * 16 * vh; }
+__host__ __device__ inline size_t link_bytes(int prec, size_t vh) {
+  return (size_t)(prec == 2 ? 24 : (prec == 1 ? 48 : 96)) * padded_sites(vh);
+}
+__host__ __device__ inline size_t clover_bytes(int prec, size_t vh) {
+  return (size_t)clover_words(prec) * 16 * padded_sites(vh);
+}
 
 // ---------------------------------------------------------------- context
 struct Workspace;    // solver vectors, allocated on first use (solver.hip)

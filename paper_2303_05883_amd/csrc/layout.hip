@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) k_import_spinor(Geom g, int p, const doub
     const double2 v = src[k];
     s[k] = {(T)v.x, (T)v.y};
   }
-  IO<P>::store_spinor(half, g.vh, i, s);
+  IO<P>::store_spinor(half, i, s);
 }
 
 template <int P>
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_export_spinor(Geom g, int p, const void
   site_coords(g, p, i, x, y, z, t);
   double2* dst = reinterpret_cast<double2*>(canon) + 12 * full_index(g, x, y, z, t);
   cx<T> s[12];
-  IO<P>::load_spinor(half, g.vh, i, s);
+  IO<P>::load_spinor(half, i, s);
 #pragma unroll
   for (int k = 0; k < 12; ++k) dst[k] = make_double2((double)s[k].r, (double)s[k].i);
 }
@@ -118,17 +118,17 @@ __global__ void __launch_bounds__(256) k_import_gauge(Geom g, int p, const doubl
     float4* d32 = reinterpret_cast<float4*>(reinterpret_cast<char*>(g32) + blkidx * link_bytes(1, vh));
     half4* d16 = reinterpret_cast<half4*>(reinterpret_cast<char*>(g16) + blkidx * link_bytes(2, vh));
 #pragma unroll
-    for (int k = 0; k < 6; ++k) d64[k * vh + i] = make_double2(u[k].r, u[k].i);
+    for (int k = 0; k < 6; ++k) d64[widx(i, k, 6)] = make_double2(u[k].r, u[k].i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      d32[k * vh + i] = make_float4((float)u[2 * k].r, (float)u[2 * k].i, (float)u[2 * k + 1].r,
+      d32[widx(i, k, 3)] = make_float4((float)u[2 * k].r, (float)u[2 * k].i, (float)u[2 * k + 1].r,
                                     (float)u[2 * k + 1].i);
       half4 h;
       h[0] = (_Float16)u[2 * k].r;
       h[1] = (_Float16)u[2 * k].i;
       h[2] = (_Float16)u[2 * k + 1].r;
       h[3] = (_Float16)u[2 * k + 1].i;
-      d16[k * vh + i] = h;
+      d16[widx(i, k, 3)] = h;
     }
   }
   record_error(chk, err);
@@ -142,10 +142,10 @@ __global__ void __launch_bounds__(256) k_convert(const void* src, void* dst, siz
   if (i >= vh) return;
   cx<TS> s[12];
   cx<TD> d[12];
-  IO<PS>::load_spinor(src, vh, i, s);
+  IO<PS>::load_spinor(src, i, s);
 #pragma unroll
   for (int k = 0; k < 12; ++k) d[k] = {(TD)s[k].r, (TD)s[k].i};
-  IO<PD>::store_spinor(dst, vh, i, d);
+  IO<PD>::store_spinor(dst, i, d);
 }
 
 __global__ void __launch_bounds__(256) k_check_finite(const double* p, size_t n, unsigned long long* flag) {
