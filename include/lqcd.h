@@ -187,14 +187,20 @@ int lqcd_apply_native(lqcd_ctx* ctx, int op, int prec, const void* in, void* out
 int lqcd_autotune(lqcd_ctx* ctx, int prec, const char* path);
 
 /* Fix the launch shape of the hop kernels for one precision (the knobs the
- * autotuner searches): block = workgroup size (64, 128, 192 or 256 threads),
- * split = lanes per output site (1; 2 with the forward hops in one lane and the
- * backward hops in the other; 4 with one lattice direction per lane),
- * xcd_map = 0 for blocks in site order, 1 to give each of the chip's 8 XCDs
- * one contiguous range of sites, 2 to give each XCD one slab of Lz/8 z-planes
- * walked z before t (needs Lz divisible by 8),
- * nt = 1 to load the links non-temporally. EINVAL for any other value. The
- * results do not depend on the shape beyond rounding of the fused reductions. */
+ * autotuner searches). Site-parallel kernels: block = workgroup size (64, 128,
+ * 192 or 256 threads), split = lanes per output site (1; 2 with the forward
+ * hops in one lane and the backward hops in the other; 4 with one lattice
+ * direction per lane), xcd_map = 0 for blocks in site order, 1 to give each of
+ * the chip's 8 XCDs one contiguous range of sites, 2 to give each XCD one slab
+ * of Lz/8 z-planes walked z before t (needs Lz divisible by 8).
+ * split = 0 selects the plane march: one workgroup per tile of whole x rows of
+ * an xy plane, marching in z with each plane's input staged in LDS; block =
+ * lanes = (Lx/2) x rows (rows dividing Ly, at most 512 lanes), xcd_map = z
+ * planes per workgroup (dividing Lz).
+ * nt = 1 to load the links non-temporally. EINVAL for any shape that is not
+ * valid on this lattice. The results do not depend on the shape beyond the
+ * rounding of the order in which the hops of a site and the fused reductions
+ * are added. */
 int lqcd_set_hop_shape(lqcd_ctx* ctx, int prec, int block, int split, int xcd_map, int nt);
 
 /* Name of a status code; detail of the last error on this thread. */

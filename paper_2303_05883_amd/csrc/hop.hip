@@ -317,6 +317,196 @@ __global__ void __launch_bounds__(256) k_hop2(HopArgs a) {
   if constexpr (NR > 0) block_reduce<NR>(red, a.partials + (size_t)blk * NR);
 }
 
+// ------------------------------------------------------------------ plane march
+// One workgroup per (tile of `ty` full rows of the xy plane, chunk of `zc`
+// planes in z, t). Lane (xh, y) computes the outputs of its column (xh, y) for
+// the zc planes in turn. At each z the input spinors of the tile's plane pass
+// through LDS, each loaded from memory once, by the lane of the same (xh, y),
+// and supply the x and y neighbours of every lane; the z neighbours are the
+// lane's own column (the next plane's spinor, loaded one step ahead, is the
+// z-forward neighbour and then this lane's LDS entry; the projected half of
+// the previous plane is kept for the z-backward hop); the t neighbours and the
+// links come from memory. Rows above and below the tile are staged by the
+// first and last row of lanes unless the tile is the whole plane (WRAP).
+template <typename T>
+struct LdsWord;
+template <>
+struct LdsWord<double> {
+  using W = double2;
+  static constexpr int N = 12;
+  __device__ static inline void put(W* L, int ns, int slot, const cx<double> s[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) L[k * ns + slot] = make_double2(s[k].r, s[k].i);
+  }
+  __device__ static inline void get(const W* L, int ns, int slot, cx<double> s[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double2 v = L[k * ns + slot];
+      s[k] = {v.x, v.y};
+    }
+  }
+};
+template <>
+struct LdsWord<float> {
+  using W = float4;
+  static constexpr int N = 6;
+  __device__ static inline void put(W* L, int ns, int slot, const cx<float> s[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) L[k * ns + slot] = make_float4(s[2 * k].r, s[2 * k].i, s[2 * k + 1].r, s[2 * k + 1].i);
+  }
+  __device__ static inline void get(const W* L, int ns, int slot, cx<float> s[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float4 v = L[k * ns + slot];
+      s[2 * k] = {v.x, v.y};
+      s[2 * k + 1] = {v.z, v.w};
+    }
+  }
+};
+
+// One hop with the neighbour's projected half h given.
+template <int P, int MU, bool FWD>
+__device__ inline void hop_half(const cx<typename IO<P>::T> h[6], const char* links, size_t lidx,
+                                cx<typename IO<P>::T> acc[12]) {
+  using T = typename IO<P>::T;
+  cx<T> u[6], w[6];
+  IO<P>::template load_link<true>(links, lidx, u);
+  link_mul<FWD>(u, h, w);
+  expand<MU, FWD>(acc, w);
+}
+
+template <int P, int EPI, bool CLOV, int RED, bool WRAP>
+__global__ void __launch_bounds__(512) k_hopz(HopArgs a, int ty, int zc) {
+  using T = typename IO<P>::T;
+  using LW = LdsWord<T>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  typename LW::W* L = reinterpret_cast<typename LW::W*>(lds_raw);
+  constexpr int NR = RED == RED_DOT ? 2 : (RED == RED_TS ? 3 : 0);
+  if (a.skip && *a.skip) return;
+  const Geom& g = a.g;
+  const int lxh = g.lxh;
+  const int ns = (WRAP ? ty : ty + 2) * lxh;  // sites of the LDS plane
+  const int nzc = g.lz / zc, nyt = g.ly / ty;
+  // z chunk fastest, then row tile, then t: each XCD (one contiguous range of
+  // logical blocks) holds whole t slices, so the z and y halos and most t
+  // neighbours are read by blocks of the same XCD
+  const int lb = logical_block(a.remap);
+  const int z0 = (lb % nzc) * zc;
+  const int rest = lb / nzc;
+  const int y0 = (rest % nyt) * ty;
+  const int t = rest / nyt;
+  const int xh = threadIdx.x % lxh, yr = threadIdx.x / lxh;
+  const int y = y0 + yr;
+  const int lr = WRAP ? yr : yr + 1;
+  const int slot = lr * lxh + xh;
+  const int lyf = WRAP ? (yr + 1 == ty ? 0 : yr + 1) : lr + 1;
+  const int lyb = WRAP ? (yr == 0 ? ty - 1 : yr - 1) : lr - 1;
+  const bool hlo = !WRAP && yr == 0, hhi = !WRAP && yr == ty - 1, halo = hlo || hhi;
+  const int yh = hlo ? (y0 == 0 ? g.ly - 1 : y0 - 1) : (y0 + ty == g.ly ? 0 : y0 + ty);
+  const int hslot = hlo ? xh : (ty + 1) * lxh + xh;
+  const size_t yl = (size_t)lxh, zl = yl * g.ly, tl = zl * g.lz;
+  const size_t tbase = tl * t;
+  const size_t itf = (t + 1 == g.lt) ? 0 : tbase + tl;          // plane offsets of t + 1 and t - 1
+  const size_t itb = (t == 0) ? tl * (g.lt - 1) : tbase - tl;
+  const bool flipf = (g.t_bc < 0) && (t + 1 == g.lt);
+  const bool flipb = (g.t_bc < 0) && (t == 0);
+  const int ybk = y == 0 ? g.ly - 1 : y - 1;
+  const char* gf = a.gauge + (size_t)(a.p * 4) * a.link_stride;        // U_mu(x), parity p
+  const char* gb = a.gauge + (size_t)((1 - a.p) * 4) * a.link_stride;  // U_mu(x - mu), parity 1-p
+  const size_t ls = a.link_stride;
+
+  cx<T> nxt[12], hnx[12], zb[6];
+  {
+    const int zm = z0 == 0 ? g.lz - 1 : z0 - 1;
+    cx<T> sp[12];
+    IO<P>::load_spinor(a.in, xh + yl * y + zl * zm + tbase, sp);
+    project<2, false>(sp, zb);
+  }
+  IO<P>::load_spinor(a.in, xh + yl * y + zl * z0 + tbase, nxt);
+  if (halo) IO<P>::load_spinor(a.in, xh + yl * yh + zl * z0 + tbase, hnx);
+  double red[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < zc; ++s) {
+    const int z = z0 + s;
+    const int zf = z + 1 == g.lz ? 0 : z + 1;
+    const int zbk = z == 0 ? g.lz - 1 : z - 1;
+    __syncthreads();  // every lane has read the previous plane
+    LW::put(L, ns, slot, nxt);
+    if (halo) LW::put(L, ns, hslot, hnx);
+    __syncthreads();
+    const size_t row = yl * y + zl * z + tbase;
+    const size_t i = row + xh;
+    IO<P>::load_spinor(a.in, xh + yl * y + zl * zf + tbase, nxt);  // z-forward neighbour, next LDS entry
+    if (halo && s + 1 < zc) IO<P>::load_spinor(a.in, xh + yl * yh + zl * zf + tbase, hnx);
+    const int x = 2 * xh + ((y + z + t + a.p) & 1);
+    const int xf = (x + 1 == g.lx) ? 0 : x + 1;
+    const int xb = (x == 0) ? g.lx - 1 : x - 1;
+    cx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    cx<T> sp[12], h[6];
+    LW::get(L, ns, lr * lxh + (xf >> 1), sp);
+    project<0, true>(sp, h);
+    hop_half<P, 0, true>(h, gf + 0 * ls, i, acc);
+    LW::get(L, ns, lr * lxh + (xb >> 1), sp);
+    project<0, false>(sp, h);
+    hop_half<P, 0, false>(h, gb + 0 * ls, row + (xb >> 1), acc);
+    LW::get(L, ns, lyf * lxh + xh, sp);
+    project<1, true>(sp, h);
+    hop_half<P, 1, true>(h, gf + 1 * ls, i, acc);
+    LW::get(L, ns, lyb * lxh + xh, sp);
+    project<1, false>(sp, h);
+    hop_half<P, 1, false>(h, gb + 1 * ls, xh + yl * ybk + zl * z + tbase, acc);
+    project<2, true>(nxt, h);
+    hop_half<P, 2, true>(h, gf + 2 * ls, i, acc);
+    hop_half<P, 2, false>(zb, gb + 2 * ls, xh + yl * y + zl * zbk + tbase, acc);
+    {
+      cx<T> hf[6];
+      const size_t jf = xh + yl * y + zl * z + itf, jb = xh + yl * y + zl * z + itb;
+      IO<P>::load_half(a.in, jf, false, hf);
+      const T twof = flipf ? T(-2) : T(2);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k] = twof * hf[k];
+      hop_half<P, 3, true>(h, gf + 3 * ls, i, acc);
+      IO<P>::load_half(a.in, jb, true, hf);
+      const T twob = flipb ? T(-2) : T(2);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k] = twob * hf[k];
+      hop_half<P, 3, false>(h, gb + 3 * ls, jb, acc);
+    }
+    // (1 + gamma_z) of this plane's own input: the z-backward neighbour of the next plane
+    LW::get(L, ns, slot, sp);
+    project<2, false>(sp, zb);
+    cx<T> out[12];
+    hop_epilogue<P, EPI, CLOV, RED>(a, i, acc, out, red);
+    IO<P>::store_spinor(a.out, i, out);
+  }
+  if constexpr (NR > 0) {
+    if (blockDim.x % 64 == 0) {
+      block_reduce<NR>(red, a.partials + (size_t)blockIdx.x * NR);
+    } else {  // partial wavefront (small lattices): through the LDS plane, summed in lane order
+      double* R = reinterpret_cast<double*>(lds_raw);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NR; ++k) R[k * blockDim.x + threadIdx.x] = red[k];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          double acc = 0.0;
+          for (unsigned j = 0; j < blockDim.x; ++j) acc += R[k * blockDim.x + j];
+          a.partials[(size_t)blockIdx.x * NR + k] = acc;
+        }
+      }
+    }
+  }
+}
+
+// LDS bytes of one plane tile of the march kernel.
+size_t march_lds_bytes(const Geom& g, int prec, int ty) {
+  const int rows = ty == g.ly ? ty : ty + 2;
+  return (size_t)rows * g.lxh * (prec == 0 ? 192 : 96);
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) k_site(const void* clov, const void* in, void* out, size_t vh) {
   using T = typename IO<P>::T;
@@ -332,7 +522,20 @@ __global__ void __launch_bounds__(256) k_site(const void* clov, const void* in, 
   }
 }
 
+bool march_shape_ok(const Geom& g, int prec, int block, int zc) {
+  if (block < 1 || block > 512 || block % g.lxh != 0) return false;
+  const int ty = block / g.lxh;
+  if (g.ly % ty != 0 || (ty < g.ly && ty < 2)) return false;
+  if (zc < 1 || g.lz % zc != 0) return false;
+  if (block * zc < 16) return false;  // at most V/32 blocks: the per-block partials buffers hold V/32 + 8
+  return march_lds_bytes(g, prec, ty) <= 158 * 1024;  // with the reduction scratch, within gfx950's 160 KiB
+}
+
 int hop_blocks(lqcd_ctx* c, int prec) {
+  if (c->hop_split[prec] == 0) {  // plane march: block = Lx/2 x rows lanes, hop_remap = z planes per block
+    const int ty = c->hop_block[prec] / c->g.lxh;
+    return (c->g.ly / ty) * (c->g.lz / c->hop_remap[prec]) * c->g.lt;
+  }
   const int sites = c->hop_block[prec] / c->hop_split[prec];
   if (c->hop_remap[prec] == 2) {
     const int slab = c->g.vh / 8;  // sites of one XCD slab
@@ -343,7 +546,14 @@ int hop_blocks(lqcd_ctx* c, int prec) {
 
 template <int P, int EPI, bool CLOV, int RED>
 static void launch_t(const HopArgs& a, int nb, int bs, hipStream_t s, bool nt, int split) {
-  if (split == 4) {
+  if (split == 0) {
+    const int ty = bs / a.g.lxh;
+    const size_t lds = march_lds_bytes(a.g, P, ty);
+    HopArgs am = a;
+    am.remap = 1;
+    if (ty == a.g.ly) hipLaunchKernelGGL((k_hopz<P, EPI, CLOV, RED, true>), dim3(nb), dim3(bs), lds, s, am, ty, a.hz);
+    else hipLaunchKernelGGL((k_hopz<P, EPI, CLOV, RED, false>), dim3(nb), dim3(bs), lds, s, am, ty, a.hz);
+  } else if (split == 4) {
     if (nt) hipLaunchKernelGGL((k_hop4<P, EPI, CLOV, RED, true>), dim3(nb), dim3(bs), 0, s, a);
     else hipLaunchKernelGGL((k_hop4<P, EPI, CLOV, RED, false>), dim3(nb), dim3(bs), 0, s, a);
   } else if (split == 2) {
@@ -389,9 +599,13 @@ static int dispatch(lqcd_ctx* c, const HopCall& h, HopArgs& a, int nb, int bs) {
 int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out) {
   if (!c->gauge[h.prec]) return set_error(LQCD_ESTATE, "gauge field not set");
   const int bs = c->hop_block[h.prec];
-  if (bs % 64 != 0 || bs < 64 || bs > 256) return set_error(LQCD_EINVAL, "hop block size must be 64..256, multiple of 64");
-  if (c->hop_split[h.prec] != 1 && c->hop_split[h.prec] != 2 && c->hop_split[h.prec] != 4)
-    return set_error(LQCD_EINVAL, "bad hop split");
+  const int split = c->hop_split[h.prec];
+  if (split == 0) {
+    if (!march_shape_ok(c->g, h.prec, bs, c->hop_remap[h.prec])) return set_error(LQCD_EINVAL, "bad plane-march shape");
+  } else {
+    if (bs % 64 != 0 || bs < 64 || bs > 256) return set_error(LQCD_EINVAL, "hop block size must be 64..256, multiple of 64");
+    if (split != 1 && split != 2 && split != 4) return set_error(LQCD_EINVAL, "bad hop split");
+  }
   const int nb = hop_blocks(c, h.prec);
   if (nblocks_out) *nblocks_out = nb;
   if (h.red != RED_NONE && !h.partials) return set_error(LQCD_EINVAL, "reduction without a partials buffer");
@@ -410,7 +624,11 @@ int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out) {
   a.p = h.out_parity;
   a.remap = c->hop_remap[h.prec];
   a.hz = c->g.lz / 8;
-  if (a.remap == 2 && (c->g.lz % 8 != 0)) return set_error(LQCD_EINVAL, "XCD z-slabs need Lz divisible by 8");
+  if (split == 0) {
+    a.hz = c->hop_remap[h.prec];  // z planes per block of the plane march
+  } else if (a.remap == 2 && (c->g.lz % 8 != 0)) {
+    return set_error(LQCD_EINVAL, "XCD z-slabs need Lz divisible by 8");
+  }
   switch (h.prec) {
     case 0: return dispatch<0>(c, h, a, nb, bs);
     case 1: return dispatch<1>(c, h, a, nb, bs);

@@ -137,7 +137,8 @@ struct lqcd_ctx {
   int hop_block[3] = {256, 256, 256};
   int hop_remap[3] = {1, 1, 1};
   int hop_nt[3] = {0, 0, 0};     // non-temporal link loads
-  int hop_split[3] = {1, 1, 1};  // lanes per output site: 1, 2 (forward / backward) or 4 (one direction each)
+  int hop_split[3] = {1, 1, 1};  // lanes per output site: 1, 2 (forward / backward) or 4 (one direction each);
+                                 // 0: plane march (hop_block = Lx/2 x rows lanes, hop_remap = z planes per block)
 
   lq::Workspace* ws = nullptr;
   // workspace of the last batched solve led by this context (reused when the
@@ -196,6 +197,8 @@ struct HopCall {
 };
 int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out);
 int hop_blocks(lqcd_ctx* c, int prec);
+// Whether (block lanes, zc planes) is a valid plane-march shape on this lattice.
+bool march_shape_ok(const Geom& g, int prec, int block, int zc);
 // most blocks any hop launch shape uses (partials buffers are sized for it)
 inline size_t max_hop_blocks(size_t vh) { return (vh + 15) / 16 + 8; }
 // out = C x (C = clover slot, or identity -> copy)

@@ -98,6 +98,12 @@ bool valid(const Entry& e) {
          (e.nt == 0 || e.nt == 1) && (e.split == 1 || e.split == 2 || e.split == 4);
 }
 
+bool valid_for(const lqcd_ctx* c, int prec, const Entry& e) {
+  if (e.split == 0) return (e.nt == 0 || e.nt == 1) && march_shape_ok(c->g, prec, e.block, e.remap);
+  if (!valid(e)) return false;
+  return e.remap != 2 || c->g.lz % 8 == 0;
+}
+
 }  // namespace
 
 int tune_load_defaults(lqcd_ctx* c) {
@@ -106,7 +112,7 @@ int tune_load_defaults(lqcd_ctx* c) {
   const auto m = read_cache(env);
   for (int p = 0; p < 3; ++p) {
     auto it = m.find(key_of(c, p));
-    if (it != m.end() && valid(it->second)) {
+    if (it != m.end() && valid_for(c, p, it->second)) {
       c->hop_block[p] = it->second.block;
       c->hop_remap[p] = it->second.remap;
       c->hop_nt[p] = it->second.nt;
@@ -146,12 +152,33 @@ extern "C" int lqcd_autotune(lqcd_ctx* c, int prec, const char* path) {
   best.us = 1e30;
   const int save_b = c->hop_block[prec], save_r = c->hop_remap[prec], save_nt = c->hop_nt[prec],
             save_s = c->hop_split[prec];
-  int status = LQCD_OK;
+  // candidates: the site-parallel kernels (split 1, 2, 4 x block x XCD mapping x
+  // non-temporal links) and the plane march (rows per tile x z planes per block)
+  std::vector<Entry> cand;
   for (int split : {1, 2, 4})
-  for (int nt = 0; nt < 2 && status == LQCD_OK; ++nt)
-  for (int remap = 0; remap < 3 && status == LQCD_OK; ++remap)
-    for (int b : blocks) {
-      if (remap == 2 && c->g.lz % 8 != 0) continue;
+    for (int nt = 0; nt < 2; ++nt)
+      for (int remap = 0; remap < 3; ++remap)
+        for (int b : blocks) {
+          Entry e;
+          e.block = b;
+          e.split = split;
+          e.remap = remap;
+          e.nt = nt;
+          if (valid_for(c, prec, e)) cand.push_back(e);
+        }
+  for (int rows = c->g.ly; rows >= 2; rows /= 2)
+    for (int zc : {2, 4, 8}) {
+      Entry e;
+      e.block = rows * c->g.lxh;
+      e.split = 0;
+      e.remap = zc;
+      e.nt = 1;
+      if (e.block >= 64 && valid_for(c, prec, e)) cand.push_back(e);
+    }
+  int status = LQCD_OK;
+  for (const Entry& e : cand) {
+      if (status != LQCD_OK) break;
+      const int b = e.block, remap = e.remap, nt = e.nt, split = e.split;
       c->hop_block[prec] = b;
       c->hop_remap[prec] = remap;
       c->hop_nt[prec] = nt;
@@ -212,8 +239,7 @@ extern "C" int lqcd_set_hop_shape(lqcd_ctx* c, int prec, int block, int split, i
   e.split = split;
   e.remap = xcd_map;
   e.nt = nt;
-  if (!valid(e)) return set_error(LQCD_EINVAL, "bad hop launch shape");
-  if (xcd_map == 2 && c->g.lz % 8 != 0) return set_error(LQCD_EINVAL, "XCD z-slabs need Lz divisible by 8");
+  if (!valid_for(c, prec, e)) return set_error(LQCD_EINVAL, "bad hop launch shape for this lattice");
   c->hop_block[prec] = block;
   c->hop_split[prec] = split;
   c->hop_remap[prec] = xcd_map;

@@ -59,8 +59,23 @@ SHAPES = [(256, 1, 1, 0), (64, 4, 1, 1), (192, 4, 0, 0), (128, 1, 0, 1), (128, 1
           (128, 2, 1, 1), (256, 2, 0, 0), (64, 2, 2, 1)]
 
 
+def march_shapes(dims):
+    """Plane-march shapes (lanes = Lx/2 x rows, split 0, z planes per block, nt)
+    that are valid on dims: whole-plane tiles and half-plane tiles with halo rows."""
+    lxh, ly, lz = dims[0] // 2, dims[1], dims[2]
+    out = []
+    for rows in (ly, ly // 2):
+        if rows < 2 or ly % rows or lxh * rows > 512:
+            continue
+        for zc in (1, 2, 4):
+            if lz % zc == 0 and lxh * rows * zc >= 16:
+                out.append((lxh * rows, 0, zc, 1))
+                break
+    return out
+
+
 def shapes_for(dims):
-    return [s for s in SHAPES if s[2] != 2 or dims[2] % 8 == 0]
+    return [s for s in SHAPES if s[2] != 2 or dims[2] % 8 == 0] + march_shapes(dims)
 REFS = {}
 
 

@@ -34,15 +34,17 @@ def test_wilson_haar_8(prec, graph):
 
 
 @pytest.mark.parametrize("prec", [lqcd.F64, lqcd.F32, lqcd.F16])
-@pytest.mark.parametrize("split", [1, 4])
+@pytest.mark.parametrize("split", [1, 4, 0])
 @pytest.mark.parametrize("reliable", [True, False])
 def test_clover_smooth(prec, split, reliable):
     dims = (8, 8, 8, 8)
     U = fg.gauge_field(dims, 1003, "smooth", 0.3)
     b = fg.gaussian_spinor(dims, 1003)
     lat = lattice(dims, U, 0.137, 1.0)
+    # split 0: the plane march, whole 4 x 8 plane per block, 2 z planes per block
+    shape = {1: (256, 1, 1, 1), 4: (128, 4, 1, 1), 0: (32, 0, 2, 1)}[split]
     for p in (lqcd.F64, lqcd.F32, lqcd.F16):
-        lat.set_hop_shape(p, 128 if split == 4 else 256, split, 1, 1)
+        lat.set_hop_shape(p, *shape)
     x = to_dev(np.zeros_like(b))
     st = lat.solve(to_dev(b), x, inner_prec=prec, reliable_update=reliable)
     r = true_residual(dirac.Operator(U, 0.137, 1.0), from_dev(x), b)
