@@ -202,6 +202,9 @@ int lqcd_autotune(lqcd_ctx* ctx, int prec, const char* path);
  * rounding of the order in which the hops of a site and the fused reductions
  * are added. */
 int lqcd_set_hop_shape(lqcd_ctx* ctx, int prec, int block, int split, int xcd_map, int nt);
+/* The launch shape in use for one precision (as lqcd_set_hop_shape takes it);
+ * any output pointer may be NULL. */
+int lqcd_get_hop_shape(lqcd_ctx* ctx, int prec, int* block, int* split, int* xcd_map, int* nt);
 
 /* Name of a status code; detail of the last error on this thread. */
 const char* lqcd_strerror(int status);

@@ -246,3 +246,13 @@ extern "C" int lqcd_set_hop_shape(lqcd_ctx* c, int prec, int block, int split, i
   c->hop_nt[prec] = nt;
   return LQCD_OK;
 }
+
+extern "C" int lqcd_get_hop_shape(lqcd_ctx* c, int prec, int* block, int* split, int* xcd_map, int* nt) {
+  if (!c) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  if (block) *block = c->hop_block[prec];
+  if (split) *split = c->hop_split[prec];
+  if (xcd_map) *xcd_map = c->hop_remap[prec];
+  if (nt) *nt = c->hop_nt[prec];
+  return LQCD_OK;
+}

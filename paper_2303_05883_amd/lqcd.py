@@ -30,8 +30,8 @@ OPS = {"D": D, "DEE": DEE, "DOO": DOO, "DEO": DEO, "DOE": DOE, "DPREC_PAPER": DP
 
 EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply",
             "lqcd_default_params", "lqcd_solve", "lqcd_solve_batch", "lqcd_field_bytes", "lqcd_import",
-            "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_strerror",
-            "lqcd_last_error"]
+            "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_get_hop_shape",
+            "lqcd_strerror", "lqcd_last_error"]
 
 
 class SolveParams(C.Structure):
@@ -90,13 +90,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_apply_native.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_autotune.argtypes = [vp, ip, C.c_char_p]
     lib.lqcd_set_hop_shape.argtypes = [vp, ip, ip, ip, ip, ip]
+    lib.lqcd_get_hop_shape.argtypes = [vp, ip] + [C.POINTER(C.c_int)] * 4
     lib.lqcd_strerror.argtypes = [ip]
     lib.lqcd_strerror.restype = C.c_char_p
     lib.lqcd_last_error.argtypes = []
     lib.lqcd_last_error.restype = C.c_char_p
     for name in ("lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply", "lqcd_solve",
                  "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune",
-                 "lqcd_set_hop_shape"):
+                 "lqcd_set_hop_shape", "lqcd_get_hop_shape"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -266,6 +267,12 @@ class Lattice:
     def set_hop_shape(self, prec: int, block: int = 256, split: int = 1, xcd_map: int = 1, nt: int = 0):
         _check(self.lib.lqcd_set_hop_shape(self.handle, int(prec), int(block), int(split), int(xcd_map), int(nt)),
                "lqcd_set_hop_shape")
+
+    def get_hop_shape(self, prec: int):
+        """(block, split, xcd_map, nt) of the hop launch shape in use for prec."""
+        v = [C.c_int() for _ in range(4)]
+        _check(self.lib.lqcd_get_hop_shape(self.handle, int(prec), *[C.byref(x) for x in v]), "lqcd_get_hop_shape")
+        return tuple(x.value for x in v)
 
     def autotune(self, prec: int, path: str | None = None):
         _check(self._call(self.lib.lqcd_autotune, self.handle, int(prec), path.encode() if path else None),
