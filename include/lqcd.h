@@ -142,7 +142,7 @@ typedef struct {
 } lqcd_solve_stats;
 
 /* Fill *p with the defaults (tol 1e-10, max_iter 100000, max_outer 100,
- * inner_prec LQCD_F64, inner_tol 1e-6 for F32 / 1e-3 for F16 when 0,
+ * inner_prec LQCD_F64, inner_tol 1e-6 for F32 / 1e-2 for F16 when 0,
  * check_every 8, use_graph 1, x0 NULL, on_device 0, reliable_update 0). */
 void lqcd_default_params(lqcd_solve_params* p);
 

@@ -445,7 +445,7 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   B.xprec = IP == 2 ? 1 : IP;
   B.clover = clover;
   const int check = prm.check_every > 0 ? prm.check_every : 8;
-  const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : (IP == 2 ? 1e-3 : 1e-10));
+  const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : (IP == 2 ? 1e-2 : 1e-10));
 
   // descriptors (rebuilt every call from the current contexts) and buffers
   // (allocated when the batch shape is new)

@@ -379,7 +379,7 @@ int solve_native(lqcd_ctx* c, const lqcd_solve_params& prm, lqcd_solve_stats& st
       LQ_TRY(reliable_mixed(c, prm, iv, target, bnorm2, rnorm, total_iters, restarts, outer, status));
     } else {
     // mixed precision: FP64 defect correction around FP32 / FP16 BiCGStab
-    const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : 1e-3);
+    const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : 1e-2);
     while (rnorm > target) {
       if (total_iters >= prm.max_iter || outer >= prm.max_outer) {
         status = set_error(LQCD_ENOCONV, "mixed-precision solve did not reach the tolerance");
