@@ -20,6 +20,9 @@ Modules:
 * ``dense``   -- brute-force 12V x 12V matrix of the operator for tiny
   lattices (an independent, loop-by-loop construction used as a pin).
 * ``freefield`` -- momentum-space closed forms for unit links.
+* ``sap``     -- the Schwarz alternating procedure preconditioner (block
+  decomposition, Dirichlet block operator, minimal-residual block solves)
+  and flexible BiCGStab.
 
 Parity status: every function here is pinned by a CPU test (``tests/
 test_oracle_*.py``) except the overall sign and trace convention of the clover

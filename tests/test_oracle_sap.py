@@ -1,0 +1,129 @@
+"""Pins of the SAP preconditioner and flexible BiCGStab oracle (oracle/sap.py)
+against facts fixed independently of it: the brute-force dense matrix
+restricted to the block sites, LAPACK solves of the block systems and of the
+full system (Schwarz iteration with exact block solves converges to D^-1),
+homogeneity and gauge covariance of the preconditioner, and BiCGStab itself
+(flexible BiCGStab with the identity as preconditioner is BiCGStab)."""
+
+import numpy as np
+import pytest
+
+import fieldgen as fg
+from oracle import dense, dirac, sap, solvers
+
+DIMS = (4, 4, 4, 4)
+BDIMS = (2, 2, 2, 2)
+
+
+def setup(kappa, csw, seed=31, kind="smooth"):
+    U = fg.gauge_field(DIMS, seed, kind, 0.3)
+    op = dirac.Operator(U, kappa, csw)
+    return U, op
+
+
+def colour_index(blocks, colour):
+    """Dense-vector indices (12 * site + 3 * spin + colour) of one colour's sites."""
+    lx, ly, lz, lt = DIMS
+    idx = []
+    for t in range(lt):
+        for z in range(lz):
+            for y in range(ly):
+                for x in range(lx):
+                    if blocks.colour[t, z, y, x] == colour:
+                        s = dense.site_index(DIMS, x, y, z, t)
+                        idx.extend(range(12 * s, 12 * s + 12))
+    return np.array(idx)
+
+
+def test_blocks_colouring():
+    b = sap.Blocks(DIMS, BDIMS)
+    assert b.count == 16 and b.nblocks == (2, 2, 2, 2)
+    # neighbouring blocks differ in colour; every block holds 16 sites
+    assert np.bincount(b.block_id.ravel()).tolist() == [16] * 16
+    for axis in range(4):
+        assert np.all(b.colour != np.roll(b.colour, 2, axis=axis))
+    with pytest.raises(ValueError):
+        sap.Blocks((4, 4, 4, 6), (2, 2, 2, 2))  # three blocks in t
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+def test_block_operator_is_dense_restriction(csw):
+    U, op = setup(0.13, csw)
+    blocks = sap.Blocks(DIMS, BDIMS)
+    M = dense.dense_dirac(U, 0.13, csw)
+    psi = fg.gaussian_spinor(DIMS, 7)
+    v = dense.to_vector(psi)
+    for colour in (0, 1):
+        idx = colour_index(blocks, colour)
+        want = np.zeros_like(v)
+        want[idx] = M[np.ix_(idx, idx)] @ v[idx]
+        got = dense.to_vector(sap.block_apply(op.D, blocks, colour, psi))
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_mr_converges_to_block_solve():
+    U, op = setup(0.10, 1.0)
+    blocks = sap.Blocks(DIMS, BDIMS)
+    M = dense.dense_dirac(U, 0.10, 1.0)
+    rho = fg.gaussian_spinor(DIMS, 8)
+    for colour in (0, 1):
+        idx = colour_index(blocks, colour)
+        want = np.zeros(M.shape[0], dtype=np.complex128)
+        want[idx] = np.linalg.solve(M[np.ix_(idx, idx)], dense.to_vector(rho)[idx])
+        got = dense.to_vector(sap.mr_blocks(op.D, blocks, colour, rho, 200))
+        assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+
+
+def test_sap_with_exact_blocks_converges_to_solution():
+    U, op = setup(0.10, 1.0)
+    blocks = sap.Blocks(DIMS, BDIMS)
+    M = dense.dense_dirac(U, 0.10, 1.0)
+    eta = fg.gaussian_spinor(DIMS, 9)
+    want = np.linalg.solve(M, dense.to_vector(eta))
+    got = dense.to_vector(sap.sap(op.D, blocks, eta, ncy=40, n_mr=60))
+    assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want)
+    # a planted mistake: the block right-hand side taken from eta alone
+    # instead of the current residual eta - D psi does not converge
+    psi = np.zeros_like(eta)
+    for _ in range(40):
+        for colour in (0, 1):
+            rho = np.where(blocks.mask(colour), eta, 0)
+            psi = psi + sap.mr_blocks(op.D, blocks, colour, rho, 60)
+    assert np.linalg.norm(dense.to_vector(psi) - want) > 1e-3 * np.linalg.norm(want)
+
+
+def test_sap_homogeneous_and_gauge_covariant():
+    U, op = setup(0.13, 1.0, kind="haar")
+    blocks = sap.Blocks(DIMS, BDIMS)
+    eta = fg.gaussian_spinor(DIMS, 10)
+    m = sap.sap(op.D, blocks, eta, ncy=2, n_mr=4)
+    c = 0.7 - 1.9j
+    assert np.abs(sap.sap(op.D, blocks, c * eta, 2, 4) - c * m).max() <= 1e-12 * np.abs(c * m).max()
+    G = fg.random_su3_field(DIMS, 11)
+    opg = dirac.Operator(dirac.gauge_transform(U, G), 0.13, 1.0)
+    mg = sap.sap(opg.D, blocks, dirac.transform_spinor(eta, G), ncy=2, n_mr=4)
+    want = dirac.transform_spinor(m, G)
+    assert np.abs(mg - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_fbicgstab_with_identity_is_bicgstab():
+    U, op = setup(0.13, 1.0)
+    b = fg.gaussian_spinor(DIMS, 12)
+    x1, i1 = solvers.bicgstab(op.D, b, tol=1e-10)
+    x2, i2 = sap.fbicgstab(op.D, lambda v: v, b, tol=1e-10)
+    assert i1.iterations == i2.iterations and i1.converged and i2.converged
+    assert np.abs(x1 - x2).max() <= 1e-10 * np.abs(x1).max()
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+def test_fbicgstab_sap_matches_lapack(csw):
+    kappa = 0.135
+    U, op = setup(kappa, csw)
+    blocks = sap.Blocks(DIMS, BDIMS)
+    b = fg.gaussian_spinor(DIMS, 13)
+    x, info = sap.fbicgstab(op.D, lambda v: sap.sap(op.D, blocks, v, 2, 4), b, tol=1e-10)
+    assert info.converged and info.residual <= 1e-10
+    want = np.linalg.solve(dense.dense_dirac(U, kappa, csw), dense.to_vector(b))
+    assert np.linalg.norm(dense.to_vector(x) - want) <= 1e-8 * np.linalg.norm(want)
+    _, plain = solvers.bicgstab(op.D, b, tol=1e-10)
+    assert info.iterations < plain.iterations
