@@ -165,6 +165,37 @@ int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const
                      double* const* x, int nlattices, const lqcd_solve_params* prm,
                      lqcd_solve_stats* stats);
 
+/* Schwarz alternating procedure (SAP) preconditioner, the smoother of the
+ * paper's multigrid solver (Sec. 3): the lattice is cut into blocks of
+ * block[0] x block[1] x block[2] x block[3] sites (x, y, z, t), every extent
+ * holding an even number of blocks, 64, 128, 192 or 256 sites per block;
+ * blocks are coloured like a checkerboard. One application M eta runs
+ * ncycles cycles from psi = 0; a cycle updates the colour-0 blocks, then the
+ * colour-1 blocks, each by nmr minimal-residual iterations on the block
+ * equation D_B delta = P_B (eta - D psi), D_B = D with the hops that enter or
+ * leave the block removed, one MR coefficient per block. M works in FP32 on
+ * the FP32 copies of the links and clover term (the full operator D, both
+ * parities, not the even-odd Schur complement). */
+typedef struct {
+  int block[4];   /* block extents (x, y, z, t) */
+  int ncycles;    /* SAP cycles per application (>= 1) */
+  int nmr;        /* minimal-residual iterations per block solve (>= 1) */
+} lqcd_sap_params;
+
+/* psi = M eta, canonical full-lattice vectors (as lqcd_apply); on_device as
+ * in lqcd_apply. EINVAL for a block shape that does not tile the lattice as
+ * stated above; ESTATE before set_gauge / set_clover. */
+int lqcd_apply_sap(lqcd_ctx* ctx, const lqcd_sap_params* sap, const double* eta, double* psi, int on_device);
+
+/* Solve D x = b on the full lattice by flexible BiCGStab in FP64 with M as a
+ * right preconditioner, until the true residual ||b - D x|| / ||b|| <= prm->tol.
+ * From prm: tol, max_iter (outer iterations), max_outer (restarts), on_device,
+ * x0. stats: outer_iters = flexible BiCGStab iterations, inner_iters =
+ * applications of M, restarts, true_rel_resid, timings. Returns ENOCONV /
+ * EBREAKDOWN as lqcd_solve does, with x the last iterate. */
+int lqcd_solve_sap(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_params* prm,
+                   const lqcd_sap_params* sap, lqcd_solve_stats* stats);
+
 /* Native fast path (benchmarks, solvers in the caller): half-lattice fields of
  * one parity in the library's internal layout on the device (site-blocked:
  * sites in blocks of 64, the count per parity rounded up to whole blocks). */

@@ -8,6 +8,7 @@
 #include "blas.h"
 #include "internal.h"
 #include "ops.h"
+#include "sap.h"
 #include "solver.h"
 #include "tune.h"
 
@@ -345,6 +346,72 @@ int lqcd_solve(lqcd_ctx* c, const double* b, double* x, const lqcd_solve_params*
   double* dx = prm.on_device ? x : reinterpret_cast<double*>(c->canon_b);
   LQ_TRY(launch_export_spinor(c, 0, 0, w->x_e, dx));
   LQ_TRY(launch_export_spinor(c, 0, 1, w->x_o, dx));
+  if (!prm.on_device) LQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  if (stats) *stats = st;
+  return status;
+}
+
+static int validate_sap(const lqcd_ctx* c, const lqcd_sap_params* sp) {
+  if (!sp) return set_error(LQCD_EINVAL, "null SAP parameters");
+  if (!sap_shape_ok(c->g, sp->block))
+    return set_error(LQCD_EINVAL, "SAP blocks must tile the lattice with an even number per direction and "
+                                  "64, 128, 192 or 256 sites per block");
+  if (sp->ncycles < 1 || sp->nmr < 1) return set_error(LQCD_EINVAL, "SAP needs ncycles >= 1 and nmr >= 1");
+  return LQCD_OK;
+}
+
+int lqcd_apply_sap(lqcd_ctx* c, const lqcd_sap_params* sp, const double* eta, double* psi, int on_device) {
+  if (!c || !eta || !psi) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_sap(c, sp));
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  LQ_TRY(ensure_apply_buffers(c, 1));
+  const size_t bytes = full_sites(c) * 192;
+  const double* din = nullptr;
+  LQ_TRY(stage_in(c, eta, on_device, c->canon_a, bytes, &din));
+  double* dout = on_device ? psi : reinterpret_cast<double*>(c->canon_b);
+  void *ie = c->half_a[1], *io = c->half_b[1], *oe = c->half_c[1], *oo = c->half_d[1];
+  LQ_TRY(launch_import_spinor(c, 1, 0, din, ie));
+  LQ_TRY(launch_import_spinor(c, 1, 1, din, io));
+  LQ_TRY(sap_apply(c, sp->block, sp->ncycles, sp->nmr, ie, io, oe, oo));
+  LQ_TRY(launch_export_spinor(c, 1, 0, oe, dout));
+  LQ_TRY(launch_export_spinor(c, 1, 1, oo, dout));
+  if (!on_device) {
+    LQ_HIP(hipMemcpyAsync(psi, dout, bytes, hipMemcpyDeviceToHost, c->stream));
+    LQ_HIP(hipStreamSynchronize(c->stream));
+  }
+  return LQCD_OK;
+}
+
+int lqcd_solve_sap(lqcd_ctx* c, const double* b, double* x, const lqcd_solve_params* prm_in,
+                   const lqcd_sap_params* sp, lqcd_solve_stats* stats) {
+  if (!c || !b || !x) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_params(prm_in));
+  LQ_TRY(validate_sap(c, sp));
+  lqcd_solve_params prm;
+  if (prm_in) prm = *prm_in;
+  else lqcd_default_params(&prm);
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  LQ_TRY(ensure_apply_buffers(c, 0));
+  const size_t bytes = full_sites(c) * 192;
+  const double* db = nullptr;
+  LQ_TRY(stage_in(c, b, prm.on_device, c->canon_a, bytes, &db));
+  LQ_TRY(check_finite(c, db, full_sites(c) * 24));
+  void *be = c->half_a[0], *bo = c->half_b[0], *xe = c->half_c[0], *xo = c->half_d[0];
+  LQ_TRY(launch_import_spinor(c, 0, 0, db, be));
+  LQ_TRY(launch_import_spinor(c, 0, 1, db, bo));
+  if (prm.x0) {
+    const double* dx0 = nullptr;
+    LQ_TRY(stage_in(c, prm.x0, prm.on_device, c->canon_b, bytes, &dx0));
+    LQ_TRY(launch_import_spinor(c, 0, 0, dx0, xe));
+    LQ_TRY(launch_import_spinor(c, 0, 1, dx0, xo));
+  }
+  lqcd_solve_stats st{};
+  const int status = solve_sap(c, prm, sp->block, sp->ncycles, sp->nmr, be, bo, xe, xo, prm.x0 == nullptr, st);
+  if (status != LQCD_OK && status != LQCD_ENOCONV && status != LQCD_EBREAKDOWN) return status;
+  double* dx = prm.on_device ? x : reinterpret_cast<double*>(c->canon_b);
+  LQ_TRY(launch_export_spinor(c, 0, 0, xe, dx));
+  LQ_TRY(launch_export_spinor(c, 0, 1, xo, dx));
   if (!prm.on_device) LQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, c->stream));
   LQ_HIP(hipStreamSynchronize(c->stream));
   if (stats) *stats = st;

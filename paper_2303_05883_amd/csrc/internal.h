@@ -35,6 +35,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -196,6 +197,13 @@ struct HopCall {
   const int* skip;      // optional device flag: when nonzero the launch does nothing
 };
 int launch_hop(lqcd_ctx* c, const HopCall& h, int* nblocks_out);
+// Progress lines on stderr when LQCD_LOG is set (each outer pass, and every
+// inner convergence check when LQCD_LOG=2).
+inline int log_level() {
+  const char* e = std::getenv("LQCD_LOG");
+  return e ? std::atoi(e) : 0;
+}
+
 int hop_blocks(lqcd_ctx* c, int prec);
 // Whether (block lanes, zc planes) is a valid plane-march shape on this lattice.
 bool march_shape_ok(const Geom& g, int prec, int block, int zc);

@@ -28,13 +28,6 @@
 
 namespace lq {
 
-// Progress lines on stderr when LQCD_LOG is set (each outer pass, and every
-// inner convergence check when LQCD_LOG=2).
-static int log_level() {
-  const char* e = std::getenv("LQCD_LOG");
-  return e ? std::atoi(e) : 0;
-}
-
 static int alloc(void** p, size_t bytes) {
   if (hipMalloc(p, bytes) != hipSuccess) {
     *p = nullptr;

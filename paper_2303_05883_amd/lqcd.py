@@ -31,13 +31,25 @@ OPS = {"D": D, "DEE": DEE, "DOO": DOO, "DEO": DEO, "DOE": DOE, "DPREC_PAPER": DP
 EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply",
             "lqcd_default_params", "lqcd_solve", "lqcd_solve_batch", "lqcd_field_bytes", "lqcd_import",
             "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_get_hop_shape",
-            "lqcd_strerror", "lqcd_last_error"]
+            "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_strerror", "lqcd_last_error"]
 
 
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("max_outer", C.c_int), ("inner_prec", C.c_int),
                 ("inner_tol", C.c_double), ("check_every", C.c_int), ("use_graph", C.c_int),
                 ("x0", C.c_void_p), ("on_device", C.c_int), ("reliable_update", C.c_int)]
+
+
+class SapParams(C.Structure):
+    _fields_ = [("block", C.c_int * 4), ("ncycles", C.c_int), ("nmr", C.c_int)]
+
+
+def sap_params(block=(4, 4, 4, 4), ncycles: int = 2, nmr: int = 4) -> SapParams:
+    sp = SapParams()
+    for k in range(4):
+        sp.block[k] = int(block[k])
+    sp.ncycles, sp.nmr = int(ncycles), int(nmr)
+    return sp
 
 
 class SolveStats(C.Structure):
@@ -91,13 +103,15 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_autotune.argtypes = [vp, ip, C.c_char_p]
     lib.lqcd_set_hop_shape.argtypes = [vp, ip, ip, ip, ip, ip]
     lib.lqcd_get_hop_shape.argtypes = [vp, ip] + [C.POINTER(C.c_int)] * 4
+    lib.lqcd_apply_sap.argtypes = [vp, C.POINTER(SapParams), vp, vp, ip]
+    lib.lqcd_solve_sap.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SapParams), C.POINTER(SolveStats)]
     lib.lqcd_strerror.argtypes = [ip]
     lib.lqcd_strerror.restype = C.c_char_p
     lib.lqcd_last_error.argtypes = []
     lib.lqcd_last_error.restype = C.c_char_p
     for name in ("lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply", "lqcd_solve",
                  "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune",
-                 "lqcd_set_hop_shape", "lqcd_get_hop_shape"):
+                 "lqcd_set_hop_shape", "lqcd_get_hop_shape", "lqcd_apply_sap", "lqcd_solve_sap"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -296,6 +310,35 @@ class Lattice:
         status = self._call(self.lib.lqcd_solve, self.handle, pb, px, C.byref(prm), C.byref(st))
         if raise_on_fail:
             _check(status, "lqcd_solve")
+        return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
+                     st.seconds_setup, status)
+
+    def apply_sap(self, eta, psi, block=(4, 4, 4, 4), ncycles=2, nmr=4):
+        """psi = M eta, the FP32 SAP preconditioner (canonical full-lattice vectors)."""
+        pi, di = _ptr(eta)
+        po, do = _ptr(psi)
+        if di != do:
+            raise ValueError("eta and psi must both be host or both be device")
+        sp = sap_params(block, ncycles, nmr)
+        _check(self._call(self.lib.lqcd_apply_sap, self.handle, C.byref(sp), pi, po, di), "lqcd_apply_sap")
+        return psi
+
+    def solve_sap(self, b, x, block=(4, 4, 4, 4), ncycles=2, nmr=4, tol=1e-10, max_iter=10000, max_outer=20,
+                  x0=None, raise_on_fail=True) -> Stats:
+        """D x = b by FP64 flexible BiCGStab with the SAP preconditioner on the right."""
+        prm = default_params()
+        pb, db = _ptr(b)
+        px, dx = _ptr(x)
+        if db != dx:
+            raise ValueError("b and x must both be host or both be device")
+        prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
+        if x0 is not None:
+            prm.x0 = _ptr(x0)[0]
+        sp = sap_params(block, ncycles, nmr)
+        st = SolveStats()
+        status = self._call(self.lib.lqcd_solve_sap, self.handle, pb, px, C.byref(prm), C.byref(sp), C.byref(st))
+        if raise_on_fail:
+            _check(status, "lqcd_solve_sap")
         return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
                      st.seconds_setup, status)
 

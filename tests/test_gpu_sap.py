@@ -1,0 +1,98 @@
+"""GPU parity of the SAP preconditioner and the SAP-preconditioned flexible
+BiCGStab against the oracle (oracle/sap.py), through the C ABI.
+
+Tolerance of one preconditioner application: the GPU runs M in FP32 through
+2 ncycles (nmr + 1) operator applications and the per-block MR coefficients
+computed from them; with the FP32 single-application error of ~1e-6
+(rel-L2, tests/test_gpu_parity.py) this stays below 5e-5 for the shapes here.
+"""
+
+import numpy as np
+import pytest
+
+import fieldgen as fg
+from gpuutil import from_dev, lattice, to_dev
+from oracle import dirac, sap
+
+pytestmark = pytest.mark.gpu
+
+SAP_TOL = 5e-5
+DIMS = (8, 8, 8, 8)
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+@pytest.mark.parametrize("ncy,nmr", [(1, 1), (2, 4)])
+def test_apply_sap_matches_oracle(csw, ncy, nmr):
+    kappa = 0.135
+    U = fg.gauge_field(DIMS, 41, "smooth", 0.3)
+    eta = fg.gaussian_spinor(DIMS, 42)
+    op = dirac.Operator(U, kappa, csw)
+    want = sap.sap(op.D, sap.Blocks(DIMS, (4, 4, 4, 4)), eta, ncy, nmr)
+    lat = lattice(DIMS, U, kappa, csw)
+    got = from_dev(lat.apply_sap(to_dev(eta), to_dev(np.zeros_like(eta)), (4, 4, 4, 4), ncy, nmr))
+    err = dirac.rel_l2(got, want)
+    assert err <= SAP_TOL, err
+
+
+def test_apply_sap_block_shapes_and_host_pointers():
+    kappa, csw = 0.13, 1.0
+    dims = (8, 4, 8, 8)
+    U = fg.gauge_field(dims, 43, "haar")
+    eta = fg.gaussian_spinor(dims, 44)
+    op = dirac.Operator(U, kappa, csw)
+    lat = lattice(dims, U, kappa, csw)
+    for block in [(4, 2, 4, 4), (2, 2, 4, 4), (4, 2, 2, 4)]:
+        want = sap.sap(op.D, sap.Blocks(dims, block), eta, 2, 3)
+        got = lat.apply_sap(eta, np.zeros_like(eta), block, 2, 3)  # host arrays
+        assert dirac.rel_l2(got, want) <= SAP_TOL, block
+
+
+def test_bad_sap_shapes_rejected():
+    from paper_2303_05883_amd import lqcd
+    dims = (8, 8, 8, 8)
+    U = fg.gauge_field(dims, 45, "haar")
+    lat = lattice(dims, U, 0.12, 0.0)
+    eta = to_dev(fg.gaussian_spinor(dims, 46))
+    out = to_dev(np.zeros_like(fg.gaussian_spinor(dims, 46)))
+    # three blocks in x; 8 sites per block; 512 sites per block
+    for block in [(3, 4, 4, 4), (2, 2, 2, 1), (8, 8, 8, 1)]:
+        with pytest.raises(lqcd.LqcdError) as e:
+            lat.apply_sap(eta, out, block, 1, 1)
+        assert e.value.status == lqcd.EINVAL
+    with pytest.raises(lqcd.LqcdError):
+        lat.apply_sap(eta, out, (4, 4, 4, 4), 0, 1)
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+def test_solve_sap_reaches_tolerance_and_matches_oracle(csw):
+    kappa = 0.136
+    U = fg.gauge_field(DIMS, 47, "smooth", 0.3)
+    b = fg.gaussian_spinor(DIMS, 48)
+    op = dirac.Operator(U, kappa, csw)
+    lat = lattice(DIMS, U, kappa, csw)
+    x = to_dev(np.zeros_like(b))
+    st = lat.solve_sap(to_dev(b), x, (4, 4, 4, 4), 2, 4, tol=1e-10)
+    xh = from_dev(x)
+    r = np.linalg.norm(b - op.D(xh)) / np.linalg.norm(b)
+    assert st.true_rel_resid <= 1e-10 and r <= 1e-10, (st, r)
+    # the same system solved by the oracle's flexible BiCGStab with its own SAP
+    blocks = sap.Blocks(DIMS, (4, 4, 4, 4))
+    xo, info = sap.fbicgstab(op.D, lambda v: sap.sap(op.D, blocks, v, 2, 4), b, tol=1e-10)
+    assert info.converged
+    assert dirac.rel_l2(xh, xo) <= 1e-8
+    # the same algorithm with an FP32 instead of FP64 preconditioner: a similar iteration count
+    assert abs(st.outer_iters - info.iterations) <= max(3, 0.3 * info.iterations), (st, info.iterations)
+
+
+def test_solve_sap_agrees_with_even_odd_solver():
+    dims = (8, 8, 8, 16)
+    kappa, csw = 0.137, 1.0
+    U = fg.gauge_field(dims, 49, "smooth", 0.3)
+    b = fg.gaussian_spinor(dims, 50)
+    lat = lattice(dims, U, kappa, csw)
+    x1 = to_dev(np.zeros_like(b))
+    x2 = to_dev(np.zeros_like(b))
+    s1 = lat.solve_sap(to_dev(b), x1, (4, 4, 4, 4), 2, 4, tol=1e-10)
+    s2 = lat.solve(to_dev(b), x2, tol=1e-10)
+    assert s1.true_rel_resid <= 1e-10 and s2.true_rel_resid <= 1e-10
+    assert dirac.rel_l2(from_dev(x1), from_dev(x2)) <= 1e-8
