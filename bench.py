@@ -23,6 +23,8 @@ Other workloads (not the headline line; same JSON shape):
                      clover lattices (own fields), one batched solve per step,
                      against 36 sequential single-RHS FP64 solves
   --workload large   64^3x128 clover, eps = 0.25, kappa = 0.1372
+  --workload sap     the clover workload solved on the full lattice by FP64
+                     flexible BiCGStab with the FP32 SAP preconditioner
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -345,12 +347,91 @@ def run_batch(a, torch, lqcd):
     return value, ms_step, config, roof, hop, compare, None, inner
 
 
+SAP_BLOCK, SAP_NCY, SAP_NMR = (16, 4, 2, 2), 6, 6
+
+
+def sap_flops(vh, st, ncy, nmr):
+    """Hop flops of one SAP-preconditioned solve: 2 full-lattice D per flexible
+    BiCGStab iteration plus 1 per restart, and per preconditioner application
+    ncy cycles of (residual + nmr block operators) over the whole lattice."""
+    full = 2 * vh
+    return HOP_FLOPS * full * (2 * st.outer_iters + st.restarts + 1 + st.inner_iters * ncy * (1 + nmr))
+
+
+def sap_kernel_roofline(torch, lat, vh):
+    """Average duration of the SAP block kernel, from HIP events on the library's
+    stream: preconditioner applications with ncy cycles minus those with one
+    cycle (the import/export around them cancels), per block-kernel launch.
+    Work per launch (half the lattice's sites): a residual (1320 + 504 + 48
+    flop) and nmr block-operator + MR steps (1320 + 504 + 96 flop) per site."""
+    b = torch.from_numpy(fg.gaussian_spinor(lat.dims, 5)).cuda()
+    out = torch.zeros_like(b)
+
+    def run(ncy, reps=4):
+        lat.apply_sap(b, out, SAP_BLOCK, ncy, SAP_NMR)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(lat.stream)
+        for _ in range(reps):
+            lat.apply_sap(b, out, SAP_BLOCK, ncy, SAP_NMR)
+        e1.record(lat.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = (run(SAP_NCY) - run(1)) / (2 * (SAP_NCY - 1))
+    flops = vh * ((1320 + 504 + 48) + SAP_NMR * (1320 + 504 + 96))
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(tf, 3), "peak": 157.3, "unit": "TFLOP/s", "frac": round(tf / 157.3, 4),
+            "traffic": None, "kernel": "k_sap_block (FP32, one workgroup per block)", "us_per_launch": round(1000 * ms, 1),
+            "flops_per_launch": flops}
+
+
+def run_sap(a, torch, lqcd):
+    w = WORKLOADS["clover"]
+    dims = w["dims"]
+    vh = int(np.prod(dims)) // 2
+    lat, U, b = make_lattice(torch, lqcd, dims, w["seed"], w["eps"], w["kappa"], w["csw"])
+    bd = torch.from_numpy(b).cuda()
+    tune(lat, lqcd, a.cached, str(dims))
+    x = torch.zeros_like(bd)
+    for _ in range(a.warmup):
+        lat.solve_sap(bd, x, SAP_BLOCK, SAP_NCY, SAP_NMR)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = [lat.solve_sap(bd, x, SAP_BLOCK, SAP_NCY, SAP_NMR) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    worst = max(s.true_rel_resid for s in stats)
+    if not worst <= 1e-10:
+        log(f"true residual {worst} above 1e-10")
+        sys.exit(1)
+    value = sum(sap_flops(vh, s, SAP_NCY, SAP_NMR) for s in stats) / elapsed / 1e9
+    ms_step = 1000 * elapsed / a.steps
+    log(f"timed {a.steps} SAP solves: {ms_step:.1f} ms each, {stats[-1]}")
+    roof = sap_kernel_roofline(torch, lat, vh)
+    log(f"SAP kernel: {roof}")
+    compare = None
+    if not a.no_compare:
+        compare = compare_solves(torch, lat, lqcd, bd)
+        compare["sap_fbicgstab"] = {"ms": round(ms_step, 2), "outer": stats[-1].outer_iters,
+                                    "preconditioner_applications": stats[-1].inner_iters,
+                                    "true_rel_resid": stats[-1].true_rel_resid,
+                                    "speedup_vs_f64": round(compare["f64"]["ms"] / ms_step, 3)}
+    config = {"workload": w["text"].replace("even-odd BiCGStab", "full-lattice flexible BiCGStab (FP64)") +
+              f", SAP preconditioner (FP32) blocks {'x'.join(map(str, SAP_BLOCK))}, {SAP_NCY} cycles, "
+              f"{SAP_NMR} MR steps, to true residual 1e-10",
+              "lattice": list(dims), "kappa": w["kappa"], "csw": w["csw"], "step": "one whole solve",
+              "outer_iters_per_solve": stats[-1].outer_iters, "parallelism": "single GPU"}
+    return value, ms_step, config, roof, None, compare, None, lqcd.F32
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large"], default="wilson")
+    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large", "sap"], default="wilson")
     ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-vs-mixed solve comparison")
@@ -374,7 +455,8 @@ def main():
     a.cached = bool(a.tune_cache) and os.path.exists(a.tune_cache)
     if a.tune_cache:
         os.environ["LQCD_TUNE_CACHE"] = os.path.abspath(a.tune_cache)
-    res = run_batch(a, torch, lqcd) if a.workload == "batch" else run_single(a, torch, lqcd)
+    runner = {"batch": run_batch, "sap": run_sap}.get(a.workload, run_single)
+    res = runner(a, torch, lqcd)
     if res is None:
         return
     value, ms_step, config, roof, hop, compare, cpu, inner = res
