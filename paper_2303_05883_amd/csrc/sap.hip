@@ -51,10 +51,13 @@ __device__ inline void project_any(const cx<float> s[12], cx<float> h[6]) {
   }
 }
 
+// acc += f (1 -+ gamma_mu) U s for a neighbour spinor s and link u given
 template <int MU, bool FWD>
-__device__ inline void hop_given(const cx<float> s[12], const cx<float> u[6], cx<float> acc[12]) {
+__device__ inline void hop_given(const cx<float> s[12], const cx<float> u[6], float f, cx<float> acc[12]) {
   cx<float> h[6], w[6];
   project_any<MU, FWD>(s, h);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) h[k] = f * h[k];
   link_mul<FWD>(u, h, w);
   expand<MU, FWD>(acc, w);
 }
@@ -145,7 +148,7 @@ __global__ void __launch_bounds__(256) k_sap_block(SapArgs a) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
   const void* pin = a.psi[1 - p];
-#pragma unroll
+#pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     int f[4] = {c[0], c[1], c[2], c[3]}, bk[4] = {c[0], c[1], c[2], c[3]};
     f[mu] = c[mu] + 1 == L[mu] ? 0 : c[mu] + 1;
@@ -172,15 +175,18 @@ __global__ void __launch_bounds__(256) k_sap_block(SapArgs a) {
         break;
     }
   }
-  cx<float> ps[12], aps[12], r[12];
-  IO<1>::load_spinor(a.psi[p], i, ps);
-  if (a.clov[p]) clover_apply<1>(a.clov[p], i, ps, aps);
-  else
+  cx<float> r[12];
+  {
+    cx<float> ps[12], aps[12];
+    IO<1>::load_spinor(a.psi[p], i, ps);
+    if (a.clov[p]) clover_apply<1>(a.clov[p], i, ps, aps);
+    else
 #pragma unroll
-    for (int k = 0; k < 12; ++k) aps[k] = ps[k];
-  IO<1>::load_spinor(a.eta[p], i, r);
+      for (int k = 0; k < 12; ++k) aps[k] = ps[k];
+    IO<1>::load_spinor(a.eta[p], i, r);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) r[k] = r[k] - aps[k] + a.kappa * acc[k];
+    for (int k = 0; k < 12; ++k) r[k] = r[k] - aps[k] + a.kappa * acc[k];
+  }
 
   // ---- the block's internal forward links into LDS
 #pragma unroll
@@ -199,39 +205,36 @@ __global__ void __launch_bounds__(256) k_sap_block(SapArgs a) {
     lds_put12(Lr, n, l, r);
     __syncthreads();
     // q = D_B r = A r - kappa sum of the hops that stay in the block
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      cx<float> s[12], u[6];
-      if (lc[mu] + 1 < a.b[mu]) {
-        lds_get12(Lr, n, l + stride[mu], s);
-        lds_get6(Lu + mu * 3 * n, n, l, u);
-        switch (mu) {
-          case 0: hop_given<0, true>(s, u, acc); break;
-          case 1: hop_given<1, true>(s, u, acc); break;
-          case 2: hop_given<2, true>(s, u, acc); break;
-          default: hop_given<3, true>(s, u, acc); break;
-        }
-      }
-      if (lc[mu] > 0) {
-        lds_get12(Lr, n, l - stride[mu], s);
-        lds_get6(Lu + mu * 3 * n, n, l - stride[mu], u);
-        switch (mu) {
-          case 0: hop_given<0, false>(s, u, acc); break;
-          case 1: hop_given<1, false>(s, u, acc); break;
-          case 2: hop_given<2, false>(s, u, acc); break;
-          default: hop_given<3, false>(s, u, acc); break;
-        }
-      }
-    }
     cx<float> qv[12];
     if (a.clov[p]) clover_apply<1>(a.clov[p], i, r, qv);
     else
 #pragma unroll
       for (int k = 0; k < 12; ++k) qv[k] = r[k];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) qv[k] = qv[k] - a.kappa * acc[k];
+    const float mk = -a.kappa;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {  // not unrolled: one direction's LDS data live at a time
+      cx<float> sp[12], u[6];
+      if (lc[mu] + 1 < a.b[mu]) {
+        lds_get12(Lr, n, l + stride[mu], sp);
+        lds_get6(Lu + mu * 3 * n, n, l, u);
+        switch (mu) {
+          case 0: hop_given<0, true>(sp, u, mk, qv); break;
+          case 1: hop_given<1, true>(sp, u, mk, qv); break;
+          case 2: hop_given<2, true>(sp, u, mk, qv); break;
+          default: hop_given<3, true>(sp, u, mk, qv); break;
+        }
+      }
+      if (lc[mu] > 0) {
+        lds_get12(Lr, n, l - stride[mu], sp);
+        lds_get6(Lu + mu * 3 * n, n, l - stride[mu], u);
+        switch (mu) {
+          case 0: hop_given<0, false>(sp, u, mk, qv); break;
+          case 1: hop_given<1, false>(sp, u, mk, qv); break;
+          case 2: hop_given<2, false>(sp, u, mk, qv); break;
+          default: hop_given<3, false>(sp, u, mk, qv); break;
+        }
+      }
+    }
     double dv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -250,6 +253,8 @@ __global__ void __launch_bounds__(256) k_sap_block(SapArgs a) {
     }
   }
   // ---- psi += delta on this block
+  cx<float> ps[12];
+  IO<1>::load_spinor(a.psi[p], i, ps);
 #pragma unroll
   for (int k = 0; k < 12; ++k) ps[k] = ps[k] + delta[k];
   IO<1>::store_spinor(a.psi[p], i, ps);
