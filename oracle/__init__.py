@@ -23,6 +23,7 @@ Modules:
 * ``sap``     -- the Schwarz alternating procedure preconditioner (block
   decomposition, Dirichlet block operator, minimal-residual block solves)
   and flexible BiCGStab.
+* ``staggered`` -- the staggered operator, its even-odd normal system and CG.
 
 Parity status: every function here is pinned by a CPU test (``tests/
 test_oracle_*.py``) except the overall sign and trace convention of the clover
