@@ -196,6 +196,32 @@ int lqcd_apply_sap(lqcd_ctx* ctx, const lqcd_sap_params* sap, const double* eta,
 int lqcd_solve_sap(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_params* prm,
                    const lqcd_sap_params* sap, lqcd_solve_stats* stats);
 
+/* Staggered fermions (one of the operator kinds the paper lists, Sec. 2), on
+ * the gauge field already set: D = m + H with
+ *   (H psi)(x) = 1/2 sum_mu eta_mu(x) [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)],
+ * eta_x = 1, eta_y = (-1)^x, eta_z = (-1)^(x+y), eta_t = (-1)^(x+y+z), the
+ * context's time boundary factor on hops across the t boundary. Vectors are
+ * canonical full-lattice colour vectors: complex128 [Lt][Lz][Ly][Lx][3]
+ * (48 bytes per site), host or device as on_device says. */
+typedef enum {
+  LQCD_STAG_D = 0,      /* out = D in on the whole lattice */
+  LQCD_STAG_SCHUR = 1   /* out_e = (m^2 - H_eo H_oe) in_e, out_o = 0 (even-odd normal operator) */
+} lqcd_stag_op;
+
+/* prec LQCD_F64 or LQCD_F32 (FP32 links and vectors, FP32 arithmetic).
+ * EINVAL for another precision, op or a non-finite mass; ESTATE before
+ * set_gauge. */
+int lqcd_stag_apply(lqcd_ctx* ctx, int op, int prec, double mass, const double* in, double* out, int on_device);
+
+/* Solve D x = b (mass > 0) by FP64 CG on the even-odd normal system
+ * (m^2 + H_eo H_eo^dag on the even sites, Hermitian positive definite), x_o
+ * rebuilt as (b_o - H_oe x_e) / m, until the true residual
+ * ||b - D x|| / ||b|| <= prm->tol. From prm: tol, max_iter (CG iterations),
+ * max_outer (CG restarts from the true residual), on_device. stats:
+ * inner_iters = CG iterations, outer_iters = passes, true_rel_resid, timings. */
+int lqcd_stag_solve(lqcd_ctx* ctx, double mass, const double* b, double* x, const lqcd_solve_params* prm,
+                    lqcd_solve_stats* stats);
+
 /* Native fast path (benchmarks, solvers in the caller): half-lattice fields of
  * one parity in the library's internal layout on the device (site-blocked:
  * sites in blocks of 64, the count per parity rounded up to whole blocks). */

@@ -9,6 +9,7 @@
 #include "internal.h"
 #include "ops.h"
 #include "sap.h"
+#include "stag.h"
 #include "solver.h"
 #include "tune.h"
 
@@ -415,6 +416,96 @@ int lqcd_solve_sap(lqcd_ctx* c, const double* b, double* x, const lqcd_solve_par
   if (!prm.on_device) LQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, c->stream));
   LQ_HIP(hipStreamSynchronize(c->stream));
   if (stats) *stats = st;
+  return status;
+}
+
+int lqcd_stag_apply(lqcd_ctx* c, int op, int prec, double mass, const double* in, double* out, int on_device) {
+  if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
+  if (prec != 0 && prec != 1) return set_error(LQCD_EINVAL, "staggered operator: precision must be F64 or F32");
+  if (op != LQCD_STAG_D && op != LQCD_STAG_SCHUR) return set_error(LQCD_EINVAL, "unknown staggered operator");
+  if (!std::isfinite(mass)) return set_error(LQCD_EINVAL, "mass must be finite");
+  if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
+  LQ_TRY(ensure_canon(c));
+  const size_t bytes = full_sites(c) * 48;
+  const double* din = nullptr;
+  LQ_TRY(stage_in(c, in, on_device, c->canon_a, bytes, &din));
+  double* dout = on_device ? out : reinterpret_cast<double*>(c->canon_b);
+  const size_t hb = stag_field_bytes(prec, c->g.vh);
+  void* h[5] = {};
+  int st = LQCD_OK;
+  for (auto& p : h) {
+    if (hipMalloc(&p, hb) != hipSuccess) {
+      (void)hipGetLastError();
+      st = set_error(LQCD_ENOMEM, "staggered apply buffers");
+      break;
+    }
+  }
+  if (st == LQCD_OK) st = stag_import(c, prec, 0, din, h[0]);
+  if (st == LQCD_OK) st = stag_import(c, prec, 1, din, h[1]);
+  if (st == LQCD_OK && op == LQCD_STAG_D) {
+    st = stag_hop(c, prec, 0, h[1], h[0], mass, 1.0, h[2]);
+    if (st == LQCD_OK) st = stag_hop(c, prec, 1, h[0], h[1], mass, 1.0, h[3]);
+    if (st == LQCD_OK) st = stag_export(c, prec, 0, h[2], dout);
+    if (st == LQCD_OK) st = stag_export(c, prec, 1, h[3], dout);
+  } else if (st == LQCD_OK) {
+    st = stag_schur(c, prec, mass, h[0], h[4], h[2]);
+    if (st == LQCD_OK && hipMemsetAsync(dout, 0, bytes, c->stream) != hipSuccess) st = set_error(LQCD_EHIP, "memset");
+    if (st == LQCD_OK) st = stag_export(c, prec, 0, h[2], dout);
+  }
+  if (st == LQCD_OK && !on_device) {
+    if (hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      st = set_error(LQCD_EHIP, "copy back");
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess && st == LQCD_OK) st = set_error(LQCD_EHIP, "synchronise");
+  for (void* p : h)
+    if (p) (void)hipFree(p);
+  return st;
+}
+
+int lqcd_stag_solve(lqcd_ctx* c, double mass, const double* b, double* x, const lqcd_solve_params* prm_in,
+                    lqcd_solve_stats* stats) {
+  if (!c || !b || !x) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_params(prm_in));
+  if (!(mass > 0) || !std::isfinite(mass)) return set_error(LQCD_EINVAL, "staggered solve needs a finite mass > 0");
+  lqcd_solve_params prm;
+  if (prm_in) prm = *prm_in;
+  else lqcd_default_params(&prm);
+  if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
+  LQ_TRY(ensure_canon(c));
+  const size_t bytes = full_sites(c) * 48;
+  const double* db = nullptr;
+  LQ_TRY(stage_in(c, b, prm.on_device, c->canon_a, bytes, &db));
+  LQ_TRY(check_finite(c, db, full_sites(c) * 6));
+  const size_t hb = stag_field_bytes(0, c->g.vh);
+  void* h[4] = {};
+  int st = LQCD_OK;
+  for (auto& p : h) {
+    if (hipMalloc(&p, hb) != hipSuccess) {
+      (void)hipGetLastError();
+      st = set_error(LQCD_ENOMEM, "staggered solve buffers");
+      break;
+    }
+  }
+  if (st == LQCD_OK) st = stag_import(c, 0, 0, db, h[0]);
+  if (st == LQCD_OK) st = stag_import(c, 0, 1, db, h[1]);
+  lqcd_solve_stats ss{};
+  int status = st;
+  if (st == LQCD_OK) {
+    status = stag_solve(c, mass, prm, h[0], h[1], h[2], h[3], ss);
+    if (status == LQCD_OK || status == LQCD_ENOCONV || status == LQCD_EBREAKDOWN) {
+      double* dx = prm.on_device ? x : reinterpret_cast<double*>(c->canon_b);
+      st = stag_export(c, 0, 0, h[2], dx);
+      if (st == LQCD_OK) st = stag_export(c, 0, 1, h[3], dx);
+      if (st == LQCD_OK && !prm.on_device &&
+          hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        st = set_error(LQCD_EHIP, "copy back");
+      if (st != LQCD_OK) status = st;
+    }
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess && status == LQCD_OK) status = set_error(LQCD_EHIP, "synchronise");
+  for (void* p : h)
+    if (p) (void)hipFree(p);
+  if (stats) *stats = ss;
   return status;
 }
 

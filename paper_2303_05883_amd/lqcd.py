@@ -31,7 +31,9 @@ OPS = {"D": D, "DEE": DEE, "DOO": DOO, "DEO": DEO, "DOE": DOE, "DPREC_PAPER": DP
 EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply",
             "lqcd_default_params", "lqcd_solve", "lqcd_solve_batch", "lqcd_field_bytes", "lqcd_import",
             "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_get_hop_shape",
-            "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_strerror", "lqcd_last_error"]
+            "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_strerror",
+            "lqcd_last_error"]
+STAG_OPS = {"D": 0, "SCHUR": 1}
 
 
 class SolveParams(C.Structure):
@@ -104,6 +106,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_set_hop_shape.argtypes = [vp, ip, ip, ip, ip, ip]
     lib.lqcd_get_hop_shape.argtypes = [vp, ip] + [C.POINTER(C.c_int)] * 4
     lib.lqcd_apply_sap.argtypes = [vp, C.POINTER(SapParams), vp, vp, ip]
+    lib.lqcd_stag_apply.argtypes = [vp, ip, ip, dp, vp, vp, ip]
+    lib.lqcd_stag_solve.argtypes = [vp, dp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
     lib.lqcd_solve_sap.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SapParams), C.POINTER(SolveStats)]
     lib.lqcd_strerror.argtypes = [ip]
     lib.lqcd_strerror.restype = C.c_char_p
@@ -111,7 +115,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_last_error.restype = C.c_char_p
     for name in ("lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply", "lqcd_solve",
                  "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune",
-                 "lqcd_set_hop_shape", "lqcd_get_hop_shape", "lqcd_apply_sap", "lqcd_solve_sap"):
+                 "lqcd_set_hop_shape", "lqcd_get_hop_shape", "lqcd_apply_sap", "lqcd_solve_sap",
+                 "lqcd_stag_apply", "lqcd_stag_solve"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -339,6 +344,32 @@ class Lattice:
         status = self._call(self.lib.lqcd_solve_sap, self.handle, pb, px, C.byref(prm), C.byref(sp), C.byref(st))
         if raise_on_fail:
             _check(status, "lqcd_solve_sap")
+        return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
+                     st.seconds_setup, status)
+
+    def stag_apply(self, op, prec, mass, x, out):
+        """Staggered operator (STAG_OPS) on canonical colour-vector fields [Lt, Lz, Ly, Lx, 3]."""
+        op = STAG_OPS[op] if isinstance(op, str) else int(op)
+        pi, di = _ptr(x)
+        po, do = _ptr(out)
+        if di != do:
+            raise ValueError("in and out must both be host or both be device")
+        _check(self._call(self.lib.lqcd_stag_apply, self.handle, op, int(prec), float(mass), pi, po, di),
+               "lqcd_stag_apply")
+        return out
+
+    def stag_solve(self, mass, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True) -> Stats:
+        """Staggered D x = b by FP64 CG on the even-odd normal system."""
+        prm = default_params()
+        pb, db = _ptr(b)
+        px, dx = _ptr(x)
+        if db != dx:
+            raise ValueError("b and x must both be host or both be device")
+        prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
+        st = SolveStats()
+        status = self._call(self.lib.lqcd_stag_solve, self.handle, float(mass), pb, px, C.byref(prm), C.byref(st))
+        if raise_on_fail:
+            _check(status, "lqcd_stag_solve")
         return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
                      st.seconds_setup, status)
 
