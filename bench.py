@@ -25,6 +25,8 @@ Other workloads (not the headline line; same JSON shape):
   --workload large   64^3x128 clover, eps = 0.25, kappa = 0.1372
   --workload sap     the clover workload solved on the full lattice by FP64
                      flexible BiCGStab with the FP32 SAP preconditioner
+  --workload staggered  32^3x64 staggered operator, mass 0.05, FP64 CG on the
+                     even-odd normal system
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -426,12 +428,89 @@ def run_sap(a, torch, lqcd):
     return value, ms_step, config, roof, None, compare, None, lqcd.F32
 
 
+STAG_MASS = 0.05
+STAG_FLOPS = 570            # per output site per staggered hop
+STAG_BYTES = {0: 8 * 96 + 48 + 48, 1: 8 * 48 + 24 + 24}  # 8 links x 12 reals, vector in, vector out
+
+
+def stag_hops(st):
+    """Staggered hops of one solve: 2 per CG iteration, 1 for the source, and
+    per pass 2 (normal-operator residual) + 3 (reconstruction, true residual)."""
+    return 2 * st.inner_iters + 1 + 5 * (st.outer_iters + 1)
+
+
+def time_stag_hop(torch, lat, prec, reps=40, nbuf=3):
+    nbytes = lat.stag_field_bytes(prec)
+    ins = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    outs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    lx, ly, lz, lt = lat.dims
+    rng = np.random.default_rng(5)
+    src = torch.from_numpy(rng.normal(size=(lt, lz, ly, lx, 3)) + 1j * rng.normal(size=(lt, lz, ly, lx, 3))).cuda()
+    for t in ins:
+        lat.stag_import(prec, 1, src, t)
+    del src
+    lat.stag_hop_native_repeat(prec, 0, ins, outs, 3)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.stag_hop_native_repeat(prec, 0, ins, outs, reps)
+    e1.record(lat.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_staggered(a, torch, lqcd):
+    w = WORKLOADS["wilson"]
+    dims = w["dims"]
+    vh = int(np.prod(dims)) // 2
+    U, _ = generate(dims, w["seed"], w["eps"], source=False)
+    lat = lqcd.Lattice(dims, -1)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    del U
+    lat.set_clover(w["kappa"], 0.0)
+    lx, ly, lz, lt = dims
+    rng = np.random.default_rng(w["seed"])
+    b = torch.from_numpy((rng.normal(size=(lt, lz, ly, lx, 3)) + 1j * rng.normal(size=(lt, lz, ly, lx, 3))) /
+                         np.sqrt(2)).cuda()
+    x = torch.zeros_like(b)
+    for _ in range(a.warmup):
+        lat.stag_solve(STAG_MASS, b, x)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = [lat.stag_solve(STAG_MASS, b, x) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    worst = max(s.true_rel_resid for s in stats)
+    if not worst <= 1e-10:
+        log(f"true residual {worst} above 1e-10")
+        sys.exit(1)
+    value = STAG_FLOPS * vh * sum(stag_hops(s) for s in stats) / elapsed / 1e9
+    ms_step = 1000 * elapsed / a.steps
+    log(f"timed {a.steps} staggered CG solves: {ms_step:.1f} ms each, {stats[-1]}")
+    hop = {}
+    for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32")):
+        ms = time_stag_hop(torch, lat, p)
+        gbs = STAG_BYTES[p] * vh / (ms * 1e-3) / 1e9
+        hop[name] = {"us": round(1000 * ms, 2), "gflops": round(STAG_FLOPS * vh / (ms * 1e-3) / 1e9, 1),
+                     "gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"staggered hop kernel: {hop}")
+    roof = {"bound": "hbm", "achieved": hop["f64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": hop["f64"]["frac_hbm"], "traffic": None,
+            "kernel": "k_stag_hop<0> (staggered hop, f64 storage)", "bytes_per_launch": STAG_BYTES[0] * vh}
+    config = {"workload": f"32^3x64 staggered, mass {STAG_MASS}, links of the Wilson workload (eps 0.3), "
+                          "antiperiodic t, FP64 CG on the even-odd normal system to true residual 1e-10",
+              "lattice": list(dims), "mass": STAG_MASS, "step": "one whole solve",
+              "cg_iters_per_solve": stats[-1].inner_iters, "parallelism": "single GPU"}
+    return value, ms_step, config, roof, hop, None, None, lqcd.F64
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large", "sap"], default="wilson")
+    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large", "sap", "staggered"], default="wilson")
     ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-vs-mixed solve comparison")
@@ -455,7 +534,7 @@ def main():
     a.cached = bool(a.tune_cache) and os.path.exists(a.tune_cache)
     if a.tune_cache:
         os.environ["LQCD_TUNE_CACHE"] = os.path.abspath(a.tune_cache)
-    runner = {"batch": run_batch, "sap": run_sap}.get(a.workload, run_single)
+    runner = {"batch": run_batch, "sap": run_sap, "staggered": run_staggered}.get(a.workload, run_single)
     res = runner(a, torch, lqcd)
     if res is None:
         return
@@ -471,7 +550,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if inner == lqcd.F32 else "f16+f32+f64",
+        "dtype": {lqcd.F64: "f64", lqcd.F32: "f32+f64"}.get(inner, "f16+f32+f64"),
         "data": "synthetic (seeded SU(3) links exp(i eps H), Gaussian or point sources)",
         "config": config,
         "roofline": roof,

@@ -222,6 +222,18 @@ int lqcd_stag_apply(lqcd_ctx* ctx, int op, int prec, double mass, const double* 
 int lqcd_stag_solve(lqcd_ctx* ctx, double mass, const double* b, double* x, const lqcd_solve_params* prm,
                     lqcd_solve_stats* stats);
 
+/* Native staggered fields (benchmarks): half-lattice colour-vector fields of
+ * one parity in the library's site-blocked layout on the device. */
+size_t lqcd_stag_field_bytes(lqcd_ctx* ctx, int prec);
+/* canonical full-lattice device colour vector -> native half field of a parity */
+int lqcd_stag_import(lqcd_ctx* ctx, int prec, int parity, const double* canon, void* native);
+/* native half field of a parity -> its sites of a canonical device colour
+ * vector (the other parity's sites are left untouched) */
+int lqcd_stag_export(lqcd_ctx* ctx, int prec, int parity, const void* native, double* canon);
+/* out = H in (the staggered hopping term, from parity 1 - out_parity to
+ * out_parity) on native device fields, enqueued without synchronising. */
+int lqcd_stag_hop_native(lqcd_ctx* ctx, int prec, int out_parity, const void* in, void* out);
+
 /* Native fast path (benchmarks, solvers in the caller): half-lattice fields of
  * one parity in the library's internal layout on the device (site-blocked:
  * sites in blocks of 64, the count per parity rounded up to whole blocks). */

@@ -509,6 +509,31 @@ int lqcd_stag_solve(lqcd_ctx* c, double mass, const double* b, double* x, const 
   return status;
 }
 
+size_t lqcd_stag_field_bytes(lqcd_ctx* c, int prec) {
+  if (!c || (prec != 0 && prec != 1)) return 0;
+  return stag_field_bytes(prec, c->g.vh);
+}
+
+int lqcd_stag_import(lqcd_ctx* c, int prec, int parity, const double* canon, void* native) {
+  if (!c || !canon || !native) return set_error(LQCD_EINVAL, "null argument");
+  if ((prec != 0 && prec != 1) || (parity != 0 && parity != 1)) return set_error(LQCD_EINVAL, "bad precision or parity");
+  return stag_import(c, prec, parity, canon, native);
+}
+
+int lqcd_stag_export(lqcd_ctx* c, int prec, int parity, const void* native, double* canon) {
+  if (!c || !canon || !native) return set_error(LQCD_EINVAL, "null argument");
+  if ((prec != 0 && prec != 1) || (parity != 0 && parity != 1)) return set_error(LQCD_EINVAL, "bad precision or parity");
+  return stag_export(c, prec, parity, native, canon);
+}
+
+int lqcd_stag_hop_native(lqcd_ctx* c, int prec, int out_parity, const void* in, void* out) {
+  if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
+  if ((prec != 0 && prec != 1) || (out_parity != 0 && out_parity != 1))
+    return set_error(LQCD_EINVAL, "bad precision or parity");
+  if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
+  return stag_hop(c, prec, out_parity, in, nullptr, 0.0, 1.0, out);
+}
+
 size_t lqcd_field_bytes(lqcd_ctx* c, int prec) {
   if (!c || prec < 0 || prec > 2) return 0;
   return spinor_bytes(prec, c->g.vh);

@@ -31,7 +31,8 @@ OPS = {"D": D, "DEE": DEE, "DOO": DOO, "DEO": DEO, "DOE": DOE, "DPREC_PAPER": DP
 EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply",
             "lqcd_default_params", "lqcd_solve", "lqcd_solve_batch", "lqcd_field_bytes", "lqcd_import",
             "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_get_hop_shape",
-            "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_strerror",
+            "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_field_bytes",
+            "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_strerror",
             "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
@@ -108,6 +109,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_apply_sap.argtypes = [vp, C.POINTER(SapParams), vp, vp, ip]
     lib.lqcd_stag_apply.argtypes = [vp, ip, ip, dp, vp, vp, ip]
     lib.lqcd_stag_solve.argtypes = [vp, dp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
+    lib.lqcd_stag_field_bytes.argtypes = [vp, ip]
+    lib.lqcd_stag_field_bytes.restype = C.c_size_t
+    lib.lqcd_stag_import.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_stag_export.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_stag_hop_native.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_solve_sap.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SapParams), C.POINTER(SolveStats)]
     lib.lqcd_strerror.argtypes = [ip]
     lib.lqcd_strerror.restype = C.c_char_p
@@ -116,7 +122,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     for name in ("lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", "lqcd_apply", "lqcd_solve",
                  "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune",
                  "lqcd_set_hop_shape", "lqcd_get_hop_shape", "lqcd_apply_sap", "lqcd_solve_sap",
-                 "lqcd_stag_apply", "lqcd_stag_solve"):
+                 "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_import", "lqcd_stag_export",
+                 "lqcd_stag_hop_native"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -357,6 +364,30 @@ class Lattice:
         _check(self._call(self.lib.lqcd_stag_apply, self.handle, op, int(prec), float(mass), pi, po, di),
                "lqcd_stag_apply")
         return out
+
+    def stag_field_bytes(self, prec: int) -> int:
+        return int(self.lib.lqcd_stag_field_bytes(self.handle, int(prec)))
+
+    def stag_import(self, prec, parity, canon, native):
+        _check(self._call(self.lib.lqcd_stag_import, self.handle, int(prec), int(parity), _ptr(canon)[0],
+                          _ptr(native)[0]), "lqcd_stag_import")
+
+    def stag_export(self, prec, parity, native, canon):
+        _check(self._call(self.lib.lqcd_stag_export, self.handle, int(prec), int(parity), _ptr(native)[0],
+                          _ptr(canon)[0]), "lqcd_stag_export")
+
+    def stag_hop_native_repeat(self, prec, out_parity, ins, outs, reps: int):
+        """reps launches of the staggered hop on native fields, cycling over the (in, out) pairs."""
+        pi = [_ptr(t)[0] for t in ins]
+        po = [_ptr(t)[0] for t in outs]
+        self._enter()
+        try:
+            for r in range(int(reps)):
+                k = r % len(pi)
+                _check(self.lib.lqcd_stag_hop_native(self.handle, int(prec), int(out_parity), pi[k], po[k]),
+                       "lqcd_stag_hop_native")
+        finally:
+            self._exit()
 
     def stag_solve(self, mass, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True) -> Stats:
         """Staggered D x = b by FP64 CG on the even-odd normal system."""

@@ -78,3 +78,24 @@ def test_stag_zero_source():
     x = to_dev(np.ones_like(b))
     st = lat.stag_solve(0.1, to_dev(b), x)
     assert st.true_rel_resid == 0.0 and np.all(from_dev(x) == 0)
+
+
+def test_stag_native_hop_matches_oracle():
+    import torch
+    dims = (4, 6, 8, 10)
+    U = fg.gauge_field(dims, 88, "haar")
+    psi = colour_field(dims, 89)
+    op = staggered.Staggered(U, 0.0)
+    lat = lattice(dims, U, 0.12, 0.0)
+    for prec in (0, 1):
+        nb = lat.stag_field_bytes(prec)
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        for out_parity in (0, 1):
+            lat.stag_import(prec, 1 - out_parity, to_dev(psi), src)
+            lat.stag_hop_native_repeat(prec, out_parity, [src], [dst], 1)
+            got = to_dev(np.zeros_like(psi))
+            lat.stag_export(prec, out_parity, dst, got)
+            torch.cuda.synchronize()
+            want = op.hop_pq(out_parity, 1 - out_parity, psi)
+            assert dirac.rel_l2(from_dev(got), want) <= TOL[prec]
