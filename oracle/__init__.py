@@ -14,7 +14,7 @@ Modules:
 * ``dirac``   -- lattice geometry, the gamma basis, the hopping term, the
   Wilson operator, the clover term, the parity blocks of Eq. (1) and the
   Schur complement.
-* ``solvers`` -- BiCGStab and the FP64 defect-correction outer loop.
+* ``solvers`` -- BiCGStab, CG and the FP64 defect-correction outer loop.
 * ``sampled`` -- the same operators evaluated at a list of sites only, for
   checks on lattices too large for the whole-field oracle.
 * ``dense``   -- brute-force 12V x 12V matrix of the operator for tiny
@@ -24,6 +24,8 @@ Modules:
   decomposition, Dirichlet block operator, minimal-residual block solves)
   and flexible BiCGStab.
 * ``staggered`` -- the staggered operator, its even-odd normal system and CG.
+* ``dwf``     -- the domain-wall operator (Shamir form), its adjoint and the
+  normal-equation solve.
 
 Parity status: every function here is pinned by a CPU test (``tests/
 test_oracle_*.py``) except the overall sign and trace convention of the clover

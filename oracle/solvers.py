@@ -1,4 +1,4 @@
-"""Oracle solvers: BiCGStab and the FP64 defect-correction outer loop.
+"""Oracle solvers: BiCGStab, CG and the FP64 defect-correction outer loop.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring). Plain float64 NumPy.
 
@@ -118,3 +118,39 @@ def defect_correction(apply: Callable[[np.ndarray], np.ndarray], b: np.ndarray,
     info.residual = rnorm / bnorm
     info.converged = rnorm <= tol * bnorm
     return x, info
+
+
+def cg(apply: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float = 1e-10, max_iter: int = 10000):
+    """Conjugate gradients for a Hermitian positive-definite operator, stopping
+    on the recomputed true residual ||b - A x|| <= tol ||b|| (restarting from
+    x whenever the iterated residual passes but the true one does not)."""
+    info = SolveInfo()
+    bnorm = norm(b)
+    x = np.zeros_like(b)
+    if bnorm == 0.0:
+        info.converged, info.residual = True, 0.0
+        return x, info
+    target = tol * bnorm
+    while True:
+        r = b - apply(x)
+        rr = np.vdot(r, r).real
+        info.residual = np.sqrt(rr) / bnorm
+        if np.sqrt(rr) <= target:
+            info.converged = True
+            return x, info
+        if info.iterations >= max_iter or info.restarts > 10:
+            return x, info
+        p = r.copy()
+        while info.iterations < max_iter:
+            q = apply(p)
+            alpha = rr / np.vdot(p, q).real
+            x = x + alpha * p
+            r = r - alpha * q
+            rr_new = np.vdot(r, r).real
+            info.iterations += 1
+            info.history.append(np.sqrt(rr_new) / bnorm)
+            if np.sqrt(rr_new) <= target:
+                break
+            p = r + (rr_new / rr) * p
+            rr = rr_new
+        info.restarts += 1

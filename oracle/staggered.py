@@ -25,8 +25,6 @@ that cross the t boundary):
 
 from __future__ import annotations
 
-from typing import Callable
-
 import numpy as np
 
 from . import dirac, solvers
@@ -92,44 +90,8 @@ class Staggered:
         return self.mask(xe, 0) + (self.mask(b, 1) - self.hop_pq(1, 0, xe)) / self.mass
 
 
-def cg(apply: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float = 1e-10, max_iter: int = 10000):
-    """Conjugate gradients for a Hermitian positive-definite operator, stopping
-    on the recomputed true residual ||b - A x|| <= tol ||b|| (restarting from
-    x whenever the iterated residual passes but the true one does not)."""
-    info = solvers.SolveInfo()
-    bnorm = solvers.norm(b)
-    x = np.zeros_like(b)
-    if bnorm == 0.0:
-        info.converged, info.residual = True, 0.0
-        return x, info
-    target = tol * bnorm
-    while True:
-        r = b - apply(x)
-        rr = np.vdot(r, r).real
-        info.residual = np.sqrt(rr) / bnorm
-        if np.sqrt(rr) <= target:
-            info.converged = True
-            return x, info
-        if info.iterations >= max_iter or info.restarts > 10:
-            return x, info
-        p = r.copy()
-        while info.iterations < max_iter:
-            q = apply(p)
-            alpha = rr / np.vdot(p, q).real
-            x = x + alpha * p
-            r = r - alpha * q
-            rr_new = np.vdot(r, r).real
-            info.iterations += 1
-            info.history.append(np.sqrt(rr_new) / bnorm)
-            if np.sqrt(rr_new) <= target:
-                break
-            p = r + (rr_new / rr) * p
-            rr = rr_new
-        info.restarts += 1
-
-
 def solve(op: Staggered, b: np.ndarray, tol: float = 1e-10):
     """D x = b through the even-odd normal system and CG."""
     be = op.eo_source(b)
-    xe, info = cg(op.schur, be, tol=tol * 0.1)
+    xe, info = solvers.cg(op.schur, be, tol=tol * 0.1)
     return op.eo_reconstruct(xe, b), info
