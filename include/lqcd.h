@@ -222,6 +222,33 @@ int lqcd_stag_apply(lqcd_ctx* ctx, int op, int prec, double mass, const double* 
 int lqcd_stag_solve(lqcd_ctx* ctx, double mass, const double* b, double* x, const lqcd_solve_params* prm,
                     lqcd_solve_stats* stats);
 
+/* Domain-wall fermions, Shamir form (an operator kind the paper lists and
+ * benchmarks, Sec. 2-3), on the gauge field already set:
+ *   (D psi)_s = (5 - M5) psi_s - 1/2 H psi_s - P_- psi_{s+1} - P_+ psi_{s-1},
+ * H the Wilson hopping term (the context's boundary factor in t),
+ * P_+- = (1 +- gamma5)/2, s = 0..Ls-1, walls psi_{Ls} -> -mf psi_0 and
+ * psi_{-1} -> -mf psi_{Ls-1}. Vectors are canonical 5-d spinor fields
+ * complex128 [Ls][Lt][Lz][Ly][Lx][4][3] (s slowest), host or device. */
+typedef struct {
+  int Ls;        /* >= 1 */
+  double M5;     /* domain-wall height */
+  double mf;     /* quark mass at the walls */
+} lqcd_dwf_params;
+
+/* out = D in (dag = 0) or D^dagger in (dag = 1), prec LQCD_F64 or LQCD_F32.
+ * EINVAL for Ls < 1, non-finite M5 / mf or another precision; ESTATE before
+ * set_gauge. */
+int lqcd_dwf_apply(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const double* in, double* out,
+                   int on_device);
+
+/* Solve D x = b by FP64 CG on the normal equations D^dag D x = D^dag b (D is
+ * not positive definite: its Wilson kernel has mass -M5) until the true
+ * residual ||b - D x|| / ||b|| <= prm->tol. From prm: tol, max_iter (CG
+ * iterations), max_outer (passes restarted from the true residual),
+ * on_device. stats: inner_iters = CG iterations, outer_iters = passes. */
+int lqcd_dwf_solve(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, const double* b, double* x,
+                   const lqcd_solve_params* prm, lqcd_solve_stats* stats);
+
 /* Native staggered fields (benchmarks): half-lattice colour-vector fields of
  * one parity in the library's site-blocked layout on the device. */
 size_t lqcd_stag_field_bytes(lqcd_ctx* ctx, int prec);

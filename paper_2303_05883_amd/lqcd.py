@@ -32,8 +32,8 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
             "lqcd_default_params", "lqcd_solve", "lqcd_solve_batch", "lqcd_field_bytes", "lqcd_import",
             "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_get_hop_shape",
             "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_field_bytes",
-            "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_strerror",
-            "lqcd_last_error"]
+            "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_dwf_apply",
+            "lqcd_dwf_solve", "lqcd_strerror", "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
 
@@ -53,6 +53,16 @@ def sap_params(block=(4, 4, 4, 4), ncycles: int = 2, nmr: int = 4) -> SapParams:
         sp.block[k] = int(block[k])
     sp.ncycles, sp.nmr = int(ncycles), int(nmr)
     return sp
+
+
+class DwfParams(C.Structure):
+    _fields_ = [("Ls", C.c_int), ("M5", C.c_double), ("mf", C.c_double)]
+
+
+def dwf_params(Ls: int, M5: float, mf: float) -> DwfParams:
+    d = DwfParams()
+    d.Ls, d.M5, d.mf = int(Ls), float(M5), float(mf)
+    return d
 
 
 class SolveStats(C.Structure):
@@ -113,6 +123,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_stag_field_bytes.restype = C.c_size_t
     lib.lqcd_stag_import.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_stag_export.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_dwf_apply.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp, ip]
+    lib.lqcd_dwf_solve.argtypes = [vp, C.POINTER(DwfParams), vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
     lib.lqcd_stag_hop_native.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_solve_sap.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SapParams), C.POINTER(SolveStats)]
     lib.lqcd_strerror.argtypes = [ip]
@@ -123,7 +135,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune",
                  "lqcd_set_hop_shape", "lqcd_get_hop_shape", "lqcd_apply_sap", "lqcd_solve_sap",
                  "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_import", "lqcd_stag_export",
-                 "lqcd_stag_hop_native"):
+                 "lqcd_stag_hop_native", "lqcd_dwf_apply", "lqcd_dwf_solve"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -364,6 +376,33 @@ class Lattice:
         _check(self._call(self.lib.lqcd_stag_apply, self.handle, op, int(prec), float(mass), pi, po, di),
                "lqcd_stag_apply")
         return out
+
+    def dwf_apply(self, Ls, M5, mf, prec, x, out, dag=False):
+        """Domain-wall D (or D^dag) on canonical 5-d fields [Ls, Lt, Lz, Ly, Lx, 4, 3]."""
+        pi, di = _ptr(x)
+        po, do = _ptr(out)
+        if di != do:
+            raise ValueError("in and out must both be host or both be device")
+        d = dwf_params(Ls, M5, mf)
+        _check(self._call(self.lib.lqcd_dwf_apply, self.handle, C.byref(d), int(bool(dag)), int(prec), pi, po, di),
+               "lqcd_dwf_apply")
+        return out
+
+    def dwf_solve(self, Ls, M5, mf, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True) -> Stats:
+        """Domain-wall D x = b by FP64 CG on the normal equations."""
+        prm = default_params()
+        pb, db = _ptr(b)
+        px, dx = _ptr(x)
+        if db != dx:
+            raise ValueError("b and x must both be host or both be device")
+        prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
+        d = dwf_params(Ls, M5, mf)
+        st = SolveStats()
+        status = self._call(self.lib.lqcd_dwf_solve, self.handle, C.byref(d), pb, px, C.byref(prm), C.byref(st))
+        if raise_on_fail:
+            _check(status, "lqcd_dwf_solve")
+        return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
+                     st.seconds_setup, status)
 
     def stag_field_bytes(self, prec: int) -> int:
         return int(self.lib.lqcd_stag_field_bytes(self.handle, int(prec)))
