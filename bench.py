@@ -505,12 +505,113 @@ def run_staggered(a, torch, lqcd):
     return value, ms_step, config, roof, hop, None, None, lqcd.F64
 
 
+DWF = dict(dims=(64, 32, 16, 8), Ls=8, M5=1.8, mf=0.05, eps=0.3, seed=1007)
+DWF_LAUNCHES = 1            # one fused kernel per D application (both parities)
+DWF_KERNEL = "k_dwf<0,false> (fused domain-wall D, f64 storage)"
+DWF_FLOPS = 1320 + 96       # per 5-d site per D: the 4-d hop + diagonal and the two projected s-hops
+# algorithmic bytes per 5-d output site: the hop input, the own spinor, the
+# output, and the 8 links shared by the Ls slices of the 4-d site
+DWF_BYTES = {0: lambda ls: 3 * 192 + 8 * 96 / ls, 1: lambda ls: 3 * 96 + 8 * 48 / ls}
+
+
+def dwf_applications(st):
+    """D and D^dag applications of one domain-wall CG solve: D^dag b, then per
+    pass the true residual D x (one more at the end) and D^dag of it, and two
+    per CG iteration."""
+    return 2 + 2 * st.outer_iters + 2 * st.inner_iters
+
+
+def time_dwf_apply(torch, lat, d, prec, dag, reps=20, nbuf=2):
+    """Average duration (ms) of one D (or D^dag) application on native 5-d
+    fields, with HIP events on the library's stream."""
+    Ls = d["Ls"]
+    nbytes = lat.dwf_field_bytes(prec, Ls)
+    ins = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    outs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    lx, ly, lz, lt = lat.dims
+    shape = (Ls, lt, lz, ly, lx, 4, 3)
+    rng = np.random.default_rng(6)
+    src = torch.from_numpy(rng.normal(size=shape) + 1j * rng.normal(size=shape)).cuda()
+    for t in ins:
+        lat.dwf_import(prec, Ls, src, t)
+    del src
+    args = (Ls, d["M5"], d["mf"], prec, ins, outs)
+    lat.dwf_apply_native_repeat(*args, 2, dag=dag)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.dwf_apply_native_repeat(*args, reps, dag=dag)
+    e1.record(lat.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_dwf(a, torch, lqcd):
+    d = DWF
+    dims, Ls = d["dims"], d["Ls"]
+    vol5 = int(np.prod(dims)) * Ls
+    U, _ = generate(dims, d["seed"], d["eps"], source=False)
+    lat = lqcd.Lattice(dims, -1)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    del U
+    lat.set_clover(0.12, 0.0)
+    if a.kernels_only:
+        for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32")):
+            for dag in (False, True):
+                ms = time_dwf_apply(torch, lat, d, p, dag, reps=10)
+                log(f"dwf {name}{' dag' if dag else ''}: {1000 * ms:.2f} us, "
+                    f"{DWF_BYTES[p](Ls) * vol5 / (ms * 1e-3) / 1e9:.1f} GB/s")
+        log(f"copy probe: {copy_probe(torch, mib=512):.1f} GB/s (512 MiB read + 512 MiB written per launch)")
+        return None
+    lx, ly, lz, lt = dims
+    shape = (Ls, lt, lz, ly, lx, 4, 3)
+    rng = np.random.default_rng(d["seed"])
+    b = torch.from_numpy((rng.normal(size=shape) + 1j * rng.normal(size=shape)) / np.sqrt(2)).cuda()
+    x = torch.zeros_like(b)
+    for _ in range(a.warmup):
+        lat.dwf_solve(Ls, d["M5"], d["mf"], b, x)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = [lat.dwf_solve(Ls, d["M5"], d["mf"], b, x) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    worst = max(s.true_rel_resid for s in stats)
+    if not worst <= 1e-10:
+        log(f"true residual {worst} above 1e-10")
+        sys.exit(1)
+    value = DWF_FLOPS * vol5 * sum(dwf_applications(s) for s in stats) / elapsed / 1e9
+    ms_step = 1000 * elapsed / a.steps
+    log(f"timed {a.steps} domain-wall CG solves: {ms_step:.1f} ms each, {stats[-1]}")
+    del b, x
+    torch.cuda.empty_cache()
+    ops = {}
+    for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32")):
+        for dag in (False, True):
+            ms = time_dwf_apply(torch, lat, d, p, dag)
+            launch_ms = ms / DWF_LAUNCHES
+            gbs = DWF_BYTES[p](Ls) * vol5 / (launch_ms * 1e-3) / 1e9
+            ops[name + ("_dag" if dag else "")] = {
+                "us_per_D": round(1000 * ms, 2), "us_per_launch": round(1000 * launch_ms, 2),
+                "gflops": round(DWF_FLOPS * vol5 / (ms * 1e-3) / 1e9, 1), "gbs": round(gbs, 1),
+                "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"domain-wall operator: {ops}")
+    roof = {"bound": "hbm", "achieved": ops["f64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ops["f64"]["frac_hbm"], "traffic": None, "kernel": DWF_KERNEL,
+            "bytes_per_launch": DWF_BYTES[0](Ls) * vol5}
+    config = {"workload": f"64x32x16x8 x Ls {Ls} Shamir domain-wall, M5 {d['M5']}, m_f {d['mf']}, links exp(i eps H) "
+                          f"with eps {d['eps']}, antiperiodic t, FP64 CG on the normal equations to true residual 1e-10",
+              "lattice": list(dims), "Ls": Ls, "M5": d["M5"], "mf": d["mf"], "step": "one whole solve",
+              "cg_iters_per_solve": stats[-1].inner_iters, "parallelism": "single GPU"}
+    return value, ms_step, config, roof, ops, None, None, lqcd.F64
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large", "sap", "staggered"], default="wilson")
+    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large", "sap", "staggered", "dwf"], default="wilson")
     ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-vs-mixed solve comparison")
@@ -534,7 +635,7 @@ def main():
     a.cached = bool(a.tune_cache) and os.path.exists(a.tune_cache)
     if a.tune_cache:
         os.environ["LQCD_TUNE_CACHE"] = os.path.abspath(a.tune_cache)
-    runner = {"batch": run_batch, "sap": run_sap, "staggered": run_staggered}.get(a.workload, run_single)
+    runner = {"batch": run_batch, "sap": run_sap, "staggered": run_staggered, "dwf": run_dwf}.get(a.workload, run_single)
     res = runner(a, torch, lqcd)
     if res is None:
         return

@@ -230,14 +230,14 @@ int lqcd_stag_solve(lqcd_ctx* ctx, double mass, const double* b, double* x, cons
  * psi_{-1} -> -mf psi_{Ls-1}. Vectors are canonical 5-d spinor fields
  * complex128 [Ls][Lt][Lz][Ly][Lx][4][3] (s slowest), host or device. */
 typedef struct {
-  int Ls;        /* >= 1 */
+  int Ls;        /* 1 .. 256 */
   double M5;     /* domain-wall height */
   double mf;     /* quark mass at the walls */
 } lqcd_dwf_params;
 
 /* out = D in (dag = 0) or D^dagger in (dag = 1), prec LQCD_F64 or LQCD_F32.
- * EINVAL for Ls < 1, non-finite M5 / mf or another precision; ESTATE before
- * set_gauge. */
+ * EINVAL for Ls outside 1..256, non-finite M5 / mf or another precision;
+ * ESTATE before set_gauge. */
 int lqcd_dwf_apply(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const double* in, double* out,
                    int on_device);
 
@@ -248,6 +248,20 @@ int lqcd_dwf_apply(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec,
  * on_device. stats: inner_iters = CG iterations, outer_iters = passes. */
 int lqcd_dwf_solve(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, const double* b, double* x,
                    const lqcd_solve_params* prm, lqcd_solve_stats* stats);
+
+/* Native domain-wall fields (benchmarks), on the device: the fifth coordinate
+ * is the fastest index of a site (5-d index i Ls + s, i the 4-d checkerboard
+ * index of the library's spinor layout), two parity halves in the
+ * site-blocked layout, the even half first. 0 for a bad precision or Ls. */
+size_t lqcd_dwf_field_bytes(lqcd_ctx* ctx, int prec, int Ls);
+/* canonical 5-d device field -> native 5-d field */
+int lqcd_dwf_import(lqcd_ctx* ctx, int prec, int Ls, const double* canon, void* native);
+/* native 5-d field -> canonical 5-d device field */
+int lqcd_dwf_export(lqcd_ctx* ctx, int prec, int Ls, const void* native, double* canon);
+/* out = D in (dag 0) or D^dag in (dag 1) on native 5-d fields, one kernel
+ * enqueued without synchronising; in and out must be different fields
+ * (EINVAL otherwise). Padding sites of out are not written. */
+int lqcd_dwf_apply_native(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const void* in, void* out);
 
 /* Native staggered fields (benchmarks): half-lattice colour-vector fields of
  * one parity in the library's site-blocked layout on the device. */

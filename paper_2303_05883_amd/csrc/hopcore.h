@@ -84,7 +84,9 @@ __device__ inline void link_mul(const cx<T> u[6], const cx<T> h[6], cx<T> w[6]) 
   }
 }
 
-template <int P, int MU, bool FWD, bool NT>
+// G5: the hop acts on gamma5 psi instead of psi (gamma5 of the Dirac-Pauli
+// basis swaps the upper and lower spin pairs with a minus sign).
+template <int P, int MU, bool FWD, bool NT, bool G5 = false>
 __device__ inline void hop_dir(const void* in, const void* links, size_t vh, size_t nbr, size_t lidx, bool flip,
                                cx<typename IO<P>::T> acc[12]) {
   using T = typename IO<P>::T;
@@ -92,13 +94,21 @@ __device__ inline void hop_dir(const void* in, const void* links, size_t vh, siz
   if (MU == 3) {
     // (1 - gamma_t) psi = 2 (0, 0, psi_2, psi_3); (1 + gamma_t) psi = 2 (psi_0, psi_1, 0, 0)
     cx<T> half[6];
-    IO<P>::load_half(in, nbr, !FWD, half);
-    const T two = flip ? T(-2) : T(2);
+    IO<P>::load_half(in, nbr, G5 ? FWD : !FWD, half);
+    const T two = (flip != G5) ? T(-2) : T(2);
 #pragma unroll
     for (int k = 0; k < 6; ++k) h[k] = two * half[k];
   } else {
     cx<T> s[12];
     IO<P>::load_spinor(in, nbr, s);
+    if (G5) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const cx<T> u = s[k];
+        s[k] = T(-1) * s[6 + k];
+        s[6 + k] = T(-1) * u;
+      }
+    }
     project<MU, FWD>(s, h);
   }
   cx<T> u[6], w[6];

@@ -33,7 +33,9 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
             "lqcd_export", "lqcd_apply_native", "lqcd_autotune", "lqcd_set_hop_shape", "lqcd_get_hop_shape",
             "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_field_bytes",
             "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_dwf_apply",
-            "lqcd_dwf_solve", "lqcd_strerror", "lqcd_last_error"]
+            "lqcd_dwf_solve", "lqcd_dwf_field_bytes", "lqcd_dwf_import", "lqcd_dwf_export", "lqcd_dwf_apply_native",
+            "lqcd_strerror",
+            "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
 
@@ -125,6 +127,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_stag_export.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_dwf_apply.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp, ip]
     lib.lqcd_dwf_solve.argtypes = [vp, C.POINTER(DwfParams), vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
+    lib.lqcd_dwf_field_bytes.argtypes = [vp, ip, ip]
+    lib.lqcd_dwf_field_bytes.restype = C.c_size_t
+    lib.lqcd_dwf_import.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_dwf_export.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_dwf_apply_native.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp]
     lib.lqcd_stag_hop_native.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_solve_sap.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SapParams), C.POINTER(SolveStats)]
     lib.lqcd_strerror.argtypes = [ip]
@@ -135,7 +142,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "lqcd_solve_batch", "lqcd_import", "lqcd_export", "lqcd_apply_native", "lqcd_autotune",
                  "lqcd_set_hop_shape", "lqcd_get_hop_shape", "lqcd_apply_sap", "lqcd_solve_sap",
                  "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_import", "lqcd_stag_export",
-                 "lqcd_stag_hop_native", "lqcd_dwf_apply", "lqcd_dwf_solve"):
+                 "lqcd_stag_hop_native", "lqcd_dwf_apply", "lqcd_dwf_solve", "lqcd_dwf_import",
+                 "lqcd_dwf_export", "lqcd_dwf_apply_native"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -403,6 +411,31 @@ class Lattice:
             _check(status, "lqcd_dwf_solve")
         return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
                      st.seconds_setup, status)
+
+    def dwf_field_bytes(self, prec: int, Ls: int) -> int:
+        return int(self.lib.lqcd_dwf_field_bytes(self.handle, int(prec), int(Ls)))
+
+    def dwf_import(self, prec, Ls, canon, native):
+        _check(self._call(self.lib.lqcd_dwf_import, self.handle, int(prec), int(Ls), _ptr(canon)[0], _ptr(native)[0]),
+               "lqcd_dwf_import")
+
+    def dwf_export(self, prec, Ls, native, canon):
+        _check(self._call(self.lib.lqcd_dwf_export, self.handle, int(prec), int(Ls), _ptr(native)[0], _ptr(canon)[0]),
+               "lqcd_dwf_export")
+
+    def dwf_apply_native_repeat(self, Ls, M5, mf, prec, ins, outs, reps: int, dag=False):
+        """reps domain-wall applications on native fields, cycling over the (in, out) pairs."""
+        d = dwf_params(Ls, M5, mf)
+        pi = [_ptr(t)[0] for t in ins]
+        po = [_ptr(t)[0] for t in outs]
+        self._enter()
+        try:
+            for r in range(int(reps)):
+                k = r % len(pi)
+                _check(self.lib.lqcd_dwf_apply_native(self.handle, C.byref(d), int(bool(dag)), int(prec), pi[k], po[k]),
+                       "lqcd_dwf_apply_native")
+        finally:
+            self._exit()
 
     def stag_field_bytes(self, prec: int) -> int:
         return int(self.lib.lqcd_stag_field_bytes(self.handle, int(prec)))

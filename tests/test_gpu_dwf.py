@@ -68,3 +68,24 @@ def test_dwf_solve_matches_oracle():
     xo, info = dwf.solve(op, b, tol=1e-12)
     assert info.converged
     assert dirac.rel_l2(xh, xo) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dwf_native_apply_matches_oracle(prec):
+    """The bench's path: import, D and D^dag on native fields (left
+    uninitialised before the import, padding included), export."""
+    import torch
+    dims, Ls = (4, 6, 8, 10), 5
+    U = fg.gauge_field(dims, 117, "haar")
+    psi = field5(dims, Ls, 118)
+    op = dwf.DomainWall(U, 1.8, 0.04, Ls)
+    lat = lattice(dims, U, 0.12, 0.0)
+    nb = lat.dwf_field_bytes(prec, Ls)
+    src, dst = (torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(2))
+    lat.dwf_import(prec, Ls, to_dev(psi), src)
+    for dag, want in ((False, op.D(psi)), (True, op.Ddag(psi))):
+        lat.dwf_apply_native_repeat(Ls, 1.8, 0.04, prec, [src], [dst], 1, dag=dag)
+        got = to_dev(np.zeros_like(psi))
+        lat.dwf_export(prec, Ls, dst, got)
+        torch.cuda.synchronize()
+        assert dirac.rel_l2(from_dev(got), want) <= TOL[prec]
