@@ -1,10 +1,14 @@
 """Pins of the domain-wall oracle (oracle/dwf.py) against facts fixed
 independently of it: a dense 5-d matrix assembled from the brute-force dense
 4-d hopping matrix (oracle/dense.py) and explicit chiral projectors written
-from gamma5's entries, Gamma5-hermiticity (D^dag = gamma5 R D R gamma5 with
-R the reflection s -> Ls-1-s), the Ls = 1 reduction to a Wilson operator,
-gauge covariance, the adjoint, and the CG solve of the normal equations
-against LAPACK."""
+from gamma5's entries; the textbook effective 4-d operator of a finite-Ls
+domain-wall operator, (1 + m_f)/2 + (1 - m_f)/2 gamma5 tanh(Ls artanh H_M)
+with the Moebius kernel H_M = gamma5 (b5 + c5) D_W (2 + (b5 - c5) D_W)^-1
+(exact at every Ls, computed here with dense inverses and matrix powers);
+Gamma5-hermiticity of the Shamir case (D^dag = gamma5 R D R gamma5 with R the
+reflection s -> Ls-1-s); the Ls = 1 reduction to a Wilson operator; gauge
+covariance; the adjoint; and the CG solve of the normal equations against
+LAPACK."""
 
 import numpy as np
 import pytest
@@ -28,22 +32,34 @@ def gamma5_written():
     return g
 
 
-def dense_dwf(U, M5, mf, Ls, t_bc):
+def dense_parts(U, M5, t_bc):
+    """Dense 4-d D_W = (4 - M5) - H/2, gamma5 and the chiral projectors over
+    the lattice, from the brute-force hopping matrix and gamma5's entries."""
     H = dense.dense_hop(U, t_bc)
     n4 = H.shape[0]
     V = n4 // 12
     g5 = gamma5_written()
+    G5 = np.kron(np.eye(V), np.kron(g5, np.eye(3)))
     pp = np.kron(np.eye(V), np.kron((np.eye(4) + g5) / 2, np.eye(3)))
     pm = np.kron(np.eye(V), np.kron((np.eye(4) - g5) / 2, np.eye(3)))
+    return (4.0 - M5) * np.eye(n4) - 0.5 * H, G5, pp, pm
+
+
+def dense_dwf(U, M5, mf, Ls, t_bc, b5=1.0, c5=0.0):
+    """Block by block: diagonal blocks b5 D_W + 1, the s+1 block
+    (c5 D_W - 1) P_- and the s-1 block (c5 D_W - 1) P_+, the wall blocks
+    times -m_f."""
+    DW, _, pp, pm = dense_parts(U, M5, t_bc)
+    n4 = DW.shape[0]
     D = np.zeros((Ls * n4, Ls * n4), dtype=np.complex128)
-    blk = (5.0 - M5) * np.eye(n4) - 0.5 * H
+    off = c5 * DW - np.eye(n4)
     for s in range(Ls):
         rs = slice(s * n4, (s + 1) * n4)
-        D[rs, rs] += blk
+        D[rs, rs] += b5 * DW + np.eye(n4)
         up = (s + 1) % Ls
         dn = (s - 1) % Ls
-        D[rs, up * n4:(up + 1) * n4] -= (1.0 if s + 1 < Ls else -mf) * pm
-        D[rs, dn * n4:(dn + 1) * n4] -= (1.0 if s > 0 else -mf) * pp
+        D[rs, up * n4:(up + 1) * n4] += (1.0 if s + 1 < Ls else -mf) * off @ pm
+        D[rs, dn * n4:(dn + 1) * n4] += (1.0 if s > 0 else -mf) * off @ pp
     return D
 
 
@@ -57,12 +73,75 @@ def test_gamma5_entries():
 
 @pytest.mark.parametrize("dims,Ls", [((2, 2, 2, 2), 4), ((2, 2, 2, 4), 3), ((4, 2, 2, 2), 1)])
 @pytest.mark.parametrize("t_bc", [-1, 1])
-def test_dense_brute_force(dims, Ls, t_bc):
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_dense_brute_force(dims, Ls, t_bc, b5, c5):
     U = fg.gauge_field(dims, 91, "haar")
-    op = dwf.DomainWall(U, 1.8, 0.07, Ls, t_bc)
+    op = dwf.DomainWall(U, 1.8, 0.07, Ls, t_bc, b5, c5)
     psi = field5(dims, Ls, 92)
-    D = dense_dwf(U, 1.8, 0.07, Ls, t_bc)
+    D = dense_dwf(U, 1.8, 0.07, Ls, t_bc, b5, c5)
     assert np.abs(vec5(op.D(psi)) - D @ vec5(psi)).max() <= 1e-13
+    assert np.abs(vec5(op.Ddag(psi)) - D.conj().T @ vec5(psi)).max() <= 1e-13
+
+
+def dense_of(apply, dims, Ls):
+    """The matrix of a linear map on 5-d fields, column by column."""
+    n = Ls * int(np.prod(dims)) * 12
+    lx, ly, lz, lt = dims
+    cols = []
+    for k in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[k] = 1.0
+        cols.append(vec5(apply(e.reshape(Ls, lt, lz, ly, lx, 4, 3))))
+    return np.array(cols).T
+
+
+def effective_4d(D, D1, n4, Ls, pp, pm):
+    """[P^-1 D(1)^-1 D(m_f) P] restricted to the s = 0 block, with
+    P = P_- delta_{s,s'} + P_+ delta_{s+1,s'} (s + 1 mod Ls)."""
+    P = np.zeros((Ls * n4, Ls * n4), dtype=np.complex128)
+    for s in range(Ls):
+        P[s * n4:(s + 1) * n4, s * n4:(s + 1) * n4] += pm
+        sp = (s + 1) % Ls
+        P[s * n4:(s + 1) * n4, sp * n4:(sp + 1) * n4] += pp
+    return (np.linalg.solve(P, np.linalg.solve(D1, D @ P)))[:n4, :n4]
+
+
+def polar_approx(DW, G5, mf, Ls, b5, c5):
+    n4 = DW.shape[0]
+    I = np.eye(n4)
+    Hm = G5 @ ((b5 + c5) * DW) @ np.linalg.inv(2 * I + (b5 - c5) * DW)
+    A = np.linalg.matrix_power(I + Hm, Ls)
+    B = np.linalg.matrix_power(I - Hm, Ls)
+    return (1 + mf) / 2 * I + (1 - mf) / 2 * G5 @ (A - B) @ np.linalg.inv(A + B)
+
+
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5), (2.0, 1.0)])
+def test_effective_operator_is_polar_approximation(b5, c5):
+    dims, Ls, M5, mf = (2, 2, 2, 2), 5, 1.8, 0.07
+    U = fg.gauge_field(dims, 104, "haar")
+    DW, G5, pp, pm = dense_parts(U, M5, -1)
+    n4 = DW.shape[0]
+    D = dense_of(dwf.DomainWall(U, M5, mf, Ls, -1, b5, c5).D, dims, Ls)
+    D1 = dense_of(dwf.DomainWall(U, M5, 1.0, Ls, -1, b5, c5).D, dims, Ls)
+    got = effective_4d(D, D1, n4, Ls, pp, pm)
+    assert np.abs(got - polar_approx(DW, G5, mf, Ls, b5, c5)).max() <= 1e-11
+
+
+def test_effective_operator_catches_wrong_order():
+    """A planted mistake in the oracle (c5 S applied after D_W instead of
+    before) fails the effective-operator pin."""
+
+    class Swapped(dwf.DomainWall):
+        def D(self, psi):
+            return self.b5 * self.DW(psi) + self.c5 * self.S(self.DW(psi)) + psi - self.S(psi)
+
+    dims, Ls, M5, mf, b5, c5 = (2, 2, 2, 2), 5, 1.8, 0.07, 1.5, 0.5
+    U = fg.gauge_field(dims, 104, "haar")
+    DW, G5, pp, pm = dense_parts(U, M5, -1)
+    D = dense_of(Swapped(U, M5, mf, Ls, -1, b5, c5).D, dims, Ls)
+    D1 = dense_of(Swapped(U, M5, 1.0, Ls, -1, b5, c5).D, dims, Ls)
+    got = effective_4d(D, D1, DW.shape[0], Ls, pp, pm)
+    assert np.abs(got - polar_approx(DW, G5, mf, Ls, b5, c5)).max() > 1e-3
 
 
 def test_gamma5_hermiticity():
@@ -80,14 +159,19 @@ def test_gamma5_hermiticity():
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
 
 
-def test_ls1_is_wilson():
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.7, 0.6)])
+def test_ls1_is_wilson(b5, c5):
+    """At Ls = 1, S = -m_f, so D = (b5 - c5 m_f) D_W + 1 + m_f: a Wilson
+    operator A (1 - kappa H) with A = (b5 - c5 m_f)(4 - M5) + 1 + m_f and
+    kappa = (b5 - c5 m_f) / (2 A)."""
     dims = (4, 4, 4, 4)
     U = fg.gauge_field(dims, 96, "haar")
     M5, mf = 1.4, 0.2
-    op = dwf.DomainWall(U, M5, mf, 1)
+    op = dwf.DomainWall(U, M5, mf, 1, -1, b5, c5)
     psi = field5(dims, 1, 97)
-    m = 5.0 - M5 + mf
-    want = m * dirac.wilson(U, psi[0], 1.0 / (2 * m), -1)
+    B = b5 - c5 * mf
+    A = B * (4.0 - M5) + 1.0 + mf
+    want = A * dirac.wilson(U, psi[0], B / (2 * A), -1)
     assert np.abs(op.D(psi)[0] - want).max() <= 1e-12
 
 
@@ -103,14 +187,15 @@ def test_gauge_covariance():
     assert np.abs(opg.D(gpsi) - want).max() <= 1e-12
 
 
-def test_adjoint_and_normal_solve_match_lapack():
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_adjoint_and_normal_solve_match_lapack(b5, c5):
     dims, Ls = (2, 2, 2, 4), 4
     U = fg.gauge_field(dims, 101, "smooth", 0.3)
-    op = dwf.DomainWall(U, 1.8, 0.1, Ls)
+    op = dwf.DomainWall(U, 1.8, 0.1, Ls, -1, b5, c5)
     a, b = field5(dims, Ls, 102), field5(dims, Ls, 103)
     assert abs(np.vdot(a, op.D(b)) - np.vdot(op.Ddag(a), b)) <= 1e-12 * np.abs(a).sum()
     x, info = dwf.solve(op, b, tol=1e-12)
     assert info.converged
-    want = np.linalg.solve(dense_dwf(U, 1.8, 0.1, Ls, -1), vec5(b))
+    want = np.linalg.solve(dense_dwf(U, 1.8, 0.1, Ls, -1, b5, c5), vec5(b))
     assert np.linalg.norm(vec5(x) - want) <= 1e-8 * np.linalg.norm(want)
     assert np.linalg.norm(vec5(b - op.D(x))) <= 1e-10 * np.linalg.norm(vec5(b))
