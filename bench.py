@@ -134,34 +134,44 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x64.txt")
 KERNEL_SOURCES = ("hop.hip", "hopcore.h", "fieldio.h")
 
 
-def kernel_sources_hash():
+def kernel_sources_hash(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2303_05883_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec_name):
-    """HBM bytes per launch of the Dslash kernel from the committed rocprofv3
-    counter summary (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy),
-    or None when the kernel sources changed since the counters were taken."""
+def measured_traffic(prec_name, path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None
+    when the kernel sources changed since the counters were taken."""
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(path).read().splitlines()
     except OSError:
         return None
     want = None
     for ln in lines:
         if ln.startswith("sources_sha256_16:"):
             want = ln.split(":", 1)[1].strip()
-    if want != kernel_sources_hash():
+    if want != kernel_sources_hash(sources):
         return None
     for ln in lines:
         if ln.startswith(prec_name + ":"):
             parts = ln.split()
             return int(parts[parts.index("traffic_bytes") + 1])
     return None
+
+
+DWF_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dwf_traffic_64x32x16x8_ls8.txt")
+DWF_SOURCES = ("dwf.hip", "hopcore.h", "fieldio.h")
+
+
+def dwf_traffic():
+    """HBM bytes per launch of the FP64 D^dag domain-wall kernel from the
+    committed counter summary, or None when its sources changed since."""
+    return measured_traffic("f64_Ddag", DWF_TRAFFIC_FILE, DWF_SOURCES)
 
 
 def hop_applications(st):
@@ -505,12 +515,13 @@ def run_staggered(a, torch, lqcd):
     return value, ms_step, config, roof, hop, None, None, lqcd.F64
 
 
-DWF = dict(dims=(64, 32, 16, 8), Ls=8, M5=1.8, mf=0.05, eps=0.3, seed=1007)
-DWF_LAUNCHES = 1            # one fused kernel per D application (both parities)
-DWF_KERNEL = "k_dwf<0,false> (fused domain-wall D, f64 storage)"
-DWF_FLOPS = 1320 + 96       # per 5-d site per D: the 4-d hop + diagonal and the two projected s-hops
-# algorithmic bytes per 5-d output site: the hop input, the own spinor, the
-# output, and the 8 links shared by the Ls slices of the 4-d site
+DWF = dict(dims=(64, 32, 16, 8), Ls=8, M5=1.8, mf=0.05, b5=1.5, c5=0.5, eps=0.3, seed=1007)
+DWF_KERNEL = "k_dwf<0,true,false> (fused Moebius domain-wall D^dag, one launch per application, f64 storage)"
+# per 5-d site per D or D^dag application: the 4-d hop (1320) and the
+# diagonal, s-hop and Moebius combination terms (192)
+DWF_FLOPS = 1320 + 192
+# algorithmic bytes per 5-d output site of the D^dag kernel: the hop input,
+# the own spinor, the output, and the 8 links shared by the Ls slices
 DWF_BYTES = {0: lambda ls: 3 * 192 + 8 * 96 / ls, 1: lambda ls: 3 * 96 + 8 * 48 / ls}
 
 
@@ -528,6 +539,7 @@ def time_dwf_apply(torch, lat, d, prec, dag, reps=20, nbuf=2):
     nbytes = lat.dwf_field_bytes(prec, Ls)
     ins = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
     outs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    tmp = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     lx, ly, lz, lt = lat.dims
     shape = (Ls, lt, lz, ly, lx, 4, 3)
     rng = np.random.default_rng(6)
@@ -536,12 +548,13 @@ def time_dwf_apply(torch, lat, d, prec, dag, reps=20, nbuf=2):
         lat.dwf_import(prec, Ls, src, t)
     del src
     args = (Ls, d["M5"], d["mf"], prec, ins, outs)
-    lat.dwf_apply_native_repeat(*args, 2, dag=dag)
+    kw = dict(dag=dag, b5=d["b5"], c5=d["c5"], tmp=tmp)
+    lat.dwf_apply_native_repeat(*args, 2, **kw)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(lat.stream)
-    lat.dwf_apply_native_repeat(*args, reps, dag=dag)
+    lat.dwf_apply_native_repeat(*args, reps, **kw)
     e1.record(lat.stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -560,8 +573,8 @@ def run_dwf(a, torch, lqcd):
         for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32")):
             for dag in (False, True):
                 ms = time_dwf_apply(torch, lat, d, p, dag, reps=10)
-                log(f"dwf {name}{' dag' if dag else ''}: {1000 * ms:.2f} us, "
-                    f"{DWF_BYTES[p](Ls) * vol5 / (ms * 1e-3) / 1e9:.1f} GB/s")
+                bw = f", {DWF_BYTES[p](Ls) * vol5 / (ms * 1e-3) / 1e9:.1f} GB/s" if dag else ""
+                log(f"dwf {name} {'D^dag' if dag else 'D'}: {1000 * ms:.2f} us{bw}")
         log(f"copy probe: {copy_probe(torch, mib=512):.1f} GB/s (512 MiB read + 512 MiB written per launch)")
         return None
     lx, ly, lz, lt = dims
@@ -569,11 +582,12 @@ def run_dwf(a, torch, lqcd):
     rng = np.random.default_rng(d["seed"])
     b = torch.from_numpy((rng.normal(size=shape) + 1j * rng.normal(size=shape)) / np.sqrt(2)).cuda()
     x = torch.zeros_like(b)
+    mob = dict(b5=d["b5"], c5=d["c5"])
     for _ in range(a.warmup):
-        lat.dwf_solve(Ls, d["M5"], d["mf"], b, x)
+        lat.dwf_solve(Ls, d["M5"], d["mf"], b, x, **mob)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    stats = [lat.dwf_solve(Ls, d["M5"], d["mf"], b, x) for _ in range(a.steps)]
+    stats = [lat.dwf_solve(Ls, d["M5"], d["mf"], b, x, **mob) for _ in range(a.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     worst = max(s.true_rel_resid for s in stats)
@@ -589,19 +603,20 @@ def run_dwf(a, torch, lqcd):
     for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32")):
         for dag in (False, True):
             ms = time_dwf_apply(torch, lat, d, p, dag)
-            launch_ms = ms / DWF_LAUNCHES
-            gbs = DWF_BYTES[p](Ls) * vol5 / (launch_ms * 1e-3) / 1e9
-            ops[name + ("_dag" if dag else "")] = {
-                "us_per_D": round(1000 * ms, 2), "us_per_launch": round(1000 * launch_ms, 2),
-                "gflops": round(DWF_FLOPS * vol5 / (ms * 1e-3) / 1e9, 1), "gbs": round(gbs, 1),
-                "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+            e = {"us": round(1000 * ms, 2), "gflops": round(DWF_FLOPS * vol5 / (ms * 1e-3) / 1e9, 1)}
+            if dag:  # one kernel per application: its HBM roofline
+                gbs = DWF_BYTES[p](Ls) * vol5 / (ms * 1e-3) / 1e9
+                e.update(gbs=round(gbs, 1), frac_hbm=round(gbs / HBM_PEAK_GBS, 4))
+            ops[name + ("_Ddag" if dag else "_D")] = e
     log(f"domain-wall operator: {ops}")
-    roof = {"bound": "hbm", "achieved": ops["f64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ops["f64"]["frac_hbm"], "traffic": None, "kernel": DWF_KERNEL,
+    roof = {"bound": "hbm", "achieved": ops["f64_Ddag"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ops["f64_Ddag"]["frac_hbm"], "traffic": dwf_traffic(), "kernel": DWF_KERNEL,
             "bytes_per_launch": DWF_BYTES[0](Ls) * vol5}
-    config = {"workload": f"64x32x16x8 x Ls {Ls} Shamir domain-wall, M5 {d['M5']}, m_f {d['mf']}, links exp(i eps H) "
-                          f"with eps {d['eps']}, antiperiodic t, FP64 CG on the normal equations to true residual 1e-10",
-              "lattice": list(dims), "Ls": Ls, "M5": d["M5"], "mf": d["mf"], "step": "one whole solve",
+    config = {"workload": f"64x32x16x8 x Ls {Ls} Moebius domain-wall, b5 {d['b5']}, c5 {d['c5']}, M5 {d['M5']}, "
+                          f"m_f {d['mf']}, links exp(i eps H) with eps {d['eps']}, antiperiodic t, FP64 CG on the "
+                          "normal equations to true residual 1e-10",
+              "lattice": list(dims), "Ls": Ls, "M5": d["M5"], "mf": d["mf"], "b5": d["b5"], "c5": d["c5"],
+              "step": "one whole solve",
               "cg_iters_per_solve": stats[-1].inner_iters, "parallelism": "single GPU"}
     return value, ms_step, config, roof, ops, None, None, lqcd.F64
 

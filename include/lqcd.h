@@ -222,21 +222,24 @@ int lqcd_stag_apply(lqcd_ctx* ctx, int op, int prec, double mass, const double* 
 int lqcd_stag_solve(lqcd_ctx* ctx, double mass, const double* b, double* x, const lqcd_solve_params* prm,
                     lqcd_solve_stats* stats);
 
-/* Domain-wall fermions, Shamir form (an operator kind the paper lists and
+/* Domain-wall fermions, Moebius form (the operator kind the paper lists and
  * benchmarks, Sec. 2-3), on the gauge field already set:
- *   (D psi)_s = (5 - M5) psi_s - 1/2 H psi_s - P_- psi_{s+1} - P_+ psi_{s-1},
+ *   D = D_W (b5 + c5 S) + (1 - S),   D_W = (4 - M5) - 1/2 H on every slice,
+ *   (S psi)_s = P_- psi_{s+1} + P_+ psi_{s-1},
  * H the Wilson hopping term (the context's boundary factor in t),
  * P_+- = (1 +- gamma5)/2, s = 0..Ls-1, walls psi_{Ls} -> -mf psi_0 and
- * psi_{-1} -> -mf psi_{Ls-1}. Vectors are canonical 5-d spinor fields
- * complex128 [Ls][Lt][Lz][Ly][Lx][4][3] (s slowest), host or device. */
+ * psi_{-1} -> -mf psi_{Ls-1}. b5 = 1, c5 = 0 is the Shamir operator
+ * (5 - M5) psi_s - 1/2 H psi_s - (S psi)_s. Vectors are canonical 5-d spinor
+ * fields complex128 [Ls][Lt][Lz][Ly][Lx][4][3] (s slowest), host or device. */
 typedef struct {
   int Ls;        /* 1 .. 256 */
   double M5;     /* domain-wall height */
   double mf;     /* quark mass at the walls */
+  double b5, c5; /* Moebius coefficients (Shamir: 1, 0) */
 } lqcd_dwf_params;
 
 /* out = D in (dag = 0) or D^dagger in (dag = 1), prec LQCD_F64 or LQCD_F32.
- * EINVAL for Ls outside 1..256, non-finite M5 / mf or another precision;
+ * EINVAL for Ls outside 1..256, non-finite M5 / mf / b5 / c5 or another precision;
  * ESTATE before set_gauge. */
 int lqcd_dwf_apply(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const double* in, double* out,
                    int on_device);
@@ -258,10 +261,13 @@ size_t lqcd_dwf_field_bytes(lqcd_ctx* ctx, int prec, int Ls);
 int lqcd_dwf_import(lqcd_ctx* ctx, int prec, int Ls, const double* canon, void* native);
 /* native 5-d field -> canonical 5-d device field */
 int lqcd_dwf_export(lqcd_ctx* ctx, int prec, int Ls, const void* native, double* canon);
-/* out = D in (dag 0) or D^dag in (dag 1) on native 5-d fields, one kernel
- * enqueued without synchronising; in and out must be different fields
- * (EINVAL otherwise). Padding sites of out are not written. */
-int lqcd_dwf_apply_native(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const void* in, void* out);
+/* out = D in (dag 0) or D^dag in (dag 1) on native 5-d fields, enqueued
+ * without synchronising (one kernel; two for D with c5 != 0). tmp is a
+ * caller-owned native 5-d scratch field, needed by D with c5 != 0 only (NULL
+ * allowed otherwise). in, out and tmp must be different fields (EINVAL
+ * otherwise). Padding sites of out are not written. */
+int lqcd_dwf_apply_native(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const void* in, void* out,
+                          void* tmp);
 
 /* Native staggered fields (benchmarks): half-lattice colour-vector fields of
  * one parity in the library's site-blocked layout on the device. */

@@ -512,8 +512,9 @@ int lqcd_stag_solve(lqcd_ctx* c, double mass, const double* b, double* x, const 
 
 static int validate_dwf(const lqcd_dwf_params* d) {
   if (!d) return set_error(LQCD_EINVAL, "null domain-wall parameters");
-  if (d->Ls < 1 || d->Ls > 256 || !std::isfinite(d->M5) || !std::isfinite(d->mf))
-    return set_error(LQCD_EINVAL, "domain wall: Ls must be 1..256, M5 and mf finite");
+  if (d->Ls < 1 || d->Ls > 256 || !std::isfinite(d->M5) || !std::isfinite(d->mf) || !std::isfinite(d->b5) ||
+      !std::isfinite(d->c5))
+    return set_error(LQCD_EINVAL, "domain wall: Ls must be 1..256, M5, mf, b5 and c5 finite");
   return LQCD_OK;
 }
 
@@ -544,7 +545,7 @@ int lqcd_dwf_apply(lqcd_ctx* c, const lqcd_dwf_params* d, int dag, int prec, con
   const size_t cbytes = full_sites(c) * 192 * (size_t)d->Ls;
   const size_t fb = dwf_field_bytes(prec, c->g.vh, d->Ls);
   Bufs b;
-  void *cin = nullptr, *cout = nullptr, *f[2];
+  void *cin = nullptr, *cout = nullptr, *f[3];
   const double* din = in;
   double* dout = out;
   if (!on_device) {
@@ -556,7 +557,7 @@ int lqcd_dwf_apply(lqcd_ctx* c, const lqcd_dwf_params* d, int dag, int prec, con
   }
   for (auto& q : f) LQ_TRY(b.get(c, fb, &q));
   LQ_TRY(dwf_import(c, prec, d->Ls, din, f[0]));
-  LQ_TRY(dwf_apply(c, prec, *d, dag, f[0], f[1]));
+  LQ_TRY(dwf_apply(c, prec, *d, dag, f[0], f[1], f[2]));
   LQ_TRY(dwf_export(c, prec, d->Ls, f[1], dout));
   if (!on_device) LQ_HIP(hipMemcpyAsync(out, dout, cbytes, hipMemcpyDeviceToHost, c->stream));
   LQ_HIP(hipStreamSynchronize(c->stream));
@@ -616,13 +617,15 @@ int lqcd_dwf_export(lqcd_ctx* c, int prec, int Ls, const void* native, double* c
   return dwf_export(c, prec, Ls, native, canon);
 }
 
-int lqcd_dwf_apply_native(lqcd_ctx* c, const lqcd_dwf_params* d, int dag, int prec, const void* in, void* out) {
+int lqcd_dwf_apply_native(lqcd_ctx* c, const lqcd_dwf_params* d, int dag, int prec, const void* in, void* out,
+                          void* tmp) {
   if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
-  if (in == out) return set_error(LQCD_EINVAL, "domain-wall operator: in and out must be different fields");
+  if (in == out || (tmp && (tmp == in || tmp == out)))
+    return set_error(LQCD_EINVAL, "domain-wall operator: in, out and tmp must be different fields");
   LQ_TRY(validate_dwf(d));
   if ((prec != 0 && prec != 1) || (dag != 0 && dag != 1)) return set_error(LQCD_EINVAL, "bad precision or dag");
   if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
-  return dwf_apply(c, prec, *d, dag, in, out);
+  return dwf_apply(c, prec, *d, dag, in, out, tmp);
 }
 
 size_t lqcd_stag_field_bytes(lqcd_ctx* c, int prec) {

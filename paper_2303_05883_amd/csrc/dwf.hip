@@ -1,10 +1,12 @@
-// Domain-wall fermions (Shamir form; one of the operator kinds the paper
-// lists and benchmarks for Bridge++, Sec. 2-3):
-//   (D psi)_s = (5 - M5) psi_s - 1/2 H psi_s - P_- psi_{s+1} - P_+ psi_{s-1},
-//   P_+- = (1 +- gamma5)/2, psi_{Ls} -> -m_f psi_0, psi_{-1} -> -m_f psi_{Ls-1},
-// H the Wilson hopping term of hopcore.h. D^dag = (5 - M5) - 1/2 gamma5 H
-// gamma5 - P_+ S_+ - P_- S_- (same walls). Solved by CG on the normal
-// equations D^dag D x = D^dag b in FP64.
+// Domain-wall fermions, Moebius form (the operator kind the paper lists and
+// benchmarks for Bridge++, Sec. 2-3; Shamir is b5 = 1, c5 = 0):
+//   D = D_W (b5 + c5 S) + (1 - S),  D_W = (4 - M5) - 1/2 H on every slice,
+//   (S psi)_s = P_- psi_{s+1} + P_+ psi_{s-1},  P_+- = (1 +- gamma5)/2,
+//   psi_{Ls} -> -m_f psi_0, psi_{-1} -> -m_f psi_{Ls-1},
+// H the Wilson hopping term of hopcore.h, and
+//   D^dag = (b5 + c5 S^dag) D_W^dag + (1 - S^dag),  D_W^dag = gamma5 D_W gamma5,
+// S^dag with the projectors exchanged. Solved by CG on the normal equations
+// D^dag D x = D^dag b in FP64.
 //
 // The fifth coordinate is an inner degree of freedom of the 4-d site (the
 // paper, Sec. 2, reports this beating a construction from the 4-d Wilson
@@ -13,10 +15,13 @@
 // first. One lane computes one 5-d site: the Ls lanes of a 4-d site load the
 // same links (one cache line serves them all) and spinors at consecutive j, and
 // the s-hops come from the neighbouring lanes through LDS. A launch covers
-// both parities, so one D application is one kernel. Where lz is a multiple
-// of 8 the workgroups walk XCD z-slabs (dwf_site); measured on 64x32x16x8 x 8
-// this cuts the L2 misses of the z and t neighbours and the FP64 D time by
-// about 8 %, FP32 by about 15 %.
+// both parities. Where lz is a multiple of 8 the workgroups walk XCD z-slabs
+// (dwf_site); measured on 64x32x16x8 x 8 this cuts the L2 misses of the z and
+// t neighbours and the FP64 D time by about 8 %, FP32 by about 15 %.
+//
+// Kernels per application: D with c5 = 0 (b5 folded into the diagonal and the
+// hop scale) and D^dag are one kernel each; D with c5 != 0 first forms
+// phi = (b5 + c5 S) psi (k_dwf_phi), then the hop of phi in k_dwf.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -37,12 +42,14 @@ struct DwfArgs {
   size_t link_stride;
   Geom g;
   const char* in;
+  const char* phi;  // Moebius D: (b5 + c5 S) in
   char* out;
   size_t hb;  // bytes of one parity half
   int Ls;
   int spb;  // 5-d sites per workgroup
   int hz;   // > 0: z extent of one XCD slab (lz = 8 hz); 0: linear order
-  double diag, mf;
+  double d4;         // 4 - M5
+  double b5, c5, mf;
 };
 
 // The 5-d site of this lane, or false past the end. With hz > 0, XCD k (the
@@ -68,67 +75,123 @@ __device__ inline bool dwf_site(const DwfArgs& a, size_t& j) {
   return true;
 }
 
-// upper spin pair of P_+ w (its lower pair is minus this) and of P_- w (lower = upper)
+// The s-neighbours of a lane: P_+ and P_- of every lane's field x go to LDS
+// (as their upper spin pairs: P_+ x = (pp, -pp), P_- x = (pm, pm)); after the
+// barrier the lane reads those of s + 1 and s - 1 (the walls wrap inside the
+// 4-d site's Ls lanes) with the wall factors.
 template <typename T>
-__device__ inline void chiral_halves(const cx<T> w[12], cx<T> pp[6], cx<T> pm[6]) {
+struct SNeighbours {
+  cx<T> (*lp)[DWB];
+  cx<T> (*lm)[DWB];
+  int up, dn;
+  T wu, wd;
+};
+
+template <typename T>
+__device__ inline void put_halves(cx<T> (*lp)[DWB], cx<T> (*lm)[DWB], const cx<T> x[12]) {
   const T half = T(0.5);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    pp[k] = half * (w[k] - w[6 + k]);
-    pm[k] = half * (w[k] + w[6 + k]);
+    lp[k][threadIdx.x] = half * (x[k] - x[6 + k]);
+    lm[k][threadIdx.x] = half * (x[k] + x[6 + k]);
   }
 }
 
+template <typename T>
+__device__ inline SNeighbours<T> neighbours(cx<T> (*lp)[DWB], cx<T> (*lm)[DWB], int s, int Ls, double mf) {
+  SNeighbours<T> n;
+  n.lp = lp;
+  n.lm = lm;
+  const int base = (int)threadIdx.x - s;
+  n.up = base + (s + 1 < Ls ? s + 1 : 0);
+  n.dn = base + (s > 0 ? s - 1 : Ls - 1);
+  n.wu = s + 1 < Ls ? T(1) : T(-mf);
+  n.wd = s > 0 ? T(1) : T(-mf);
+  return n;
+}
+
+// o += f S x (DAG: S^dag x)
+template <bool DAG, typename T>
+__device__ inline void add_s(const SNeighbours<T>& n, T f, cx<T> o[12]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    // S x = P_- x_{s+1} + P_+ x_{s-1};  S^dag x = P_+ x_{s+1} + P_- x_{s-1}
+    const cx<T> a = (f * n.wu) * (DAG ? n.lp[k][n.up] : n.lm[k][n.up]);
+    const cx<T> b = (f * n.wd) * (DAG ? n.lm[k][n.dn] : n.lp[k][n.dn]);
+    o[k] = o[k] + a + b;
+    o[6 + k] = DAG ? o[6 + k] - a + b : o[6 + k] + a - b;
+  }
+}
+
+// H (DAG: gamma5 H gamma5) of the other parity of f5 at this lane's 5-d site
 template <int P, bool DAG>
+__device__ inline void dwf_hop(const DwfArgs& a, const char* f5, int p, int i, int s, cx<typename IO<P>::T> acc[12]) {
+  const Geom& g = a.g;
+  const int Ls = a.Ls;
+  const char* other = f5 + (size_t)(1 - p) * a.hb;
+  const int xh = i % g.lxh;
+  int r = i / g.lxh;
+  const int y = r % g.ly;
+  r /= g.ly;
+  const int z = r % g.lz;
+  const int t = r / g.lz;
+  const int x = 2 * xh + ((y + z + t + p) & 1);
+  const int row = i - xh;
+  const int xf = (x + 1 == g.lx) ? 0 : x + 1;
+  const int xb = (x == 0) ? g.lx - 1 : x - 1;
+  const int yl = g.lxh, zl = g.lxh * g.ly, tl = g.lxh * g.ly * g.lz;
+  const int ixf = row + (xf >> 1), ixb = row + (xb >> 1);
+  const int iyf = i + ((y + 1 == g.ly) ? -(g.ly - 1) * yl : yl);
+  const int iyb = i + ((y == 0) ? (g.ly - 1) * yl : -yl);
+  const int izf = i + ((z + 1 == g.lz) ? -(g.lz - 1) * zl : zl);
+  const int izb = i + ((z == 0) ? (g.lz - 1) * zl : -zl);
+  const int itf = i + ((t + 1 == g.lt) ? -(g.lt - 1) * tl : tl);
+  const int itb = i + ((t == 0) ? (g.lt - 1) * tl : -tl);
+  const bool flipf = (g.t_bc < 0) && (t + 1 == g.lt);
+  const bool flipb = (g.t_bc < 0) && (t == 0);
+  const char* gf = a.gauge + (size_t)(p * 4) * a.link_stride;
+  const char* gb = a.gauge + (size_t)((1 - p) * 4) * a.link_stride;
+  const size_t ls = a.link_stride, vh = (size_t)g.vh;
+  auto at = [&](int site) { return (size_t)site * Ls + s; };
+  hop_dir<P, 0, true, false, DAG>(other, gf + 0 * ls, vh, at(ixf), (size_t)i, false, acc);
+  hop_dir<P, 0, false, false, DAG>(other, gb + 0 * ls, vh, at(ixb), (size_t)ixb, false, acc);
+  hop_dir<P, 1, true, false, DAG>(other, gf + 1 * ls, vh, at(iyf), (size_t)i, false, acc);
+  hop_dir<P, 1, false, false, DAG>(other, gb + 1 * ls, vh, at(iyb), (size_t)iyb, false, acc);
+  hop_dir<P, 2, true, false, DAG>(other, gf + 2 * ls, vh, at(izf), (size_t)i, false, acc);
+  hop_dir<P, 2, false, false, DAG>(other, gb + 2 * ls, vh, at(izb), (size_t)izb, false, acc);
+  hop_dir<P, 3, true, false, DAG>(other, gf + 3 * ls, vh, at(itf), (size_t)i, flipf, acc);
+  hop_dir<P, 3, false, false, DAG>(other, gb + 3 * ls, vh, at(itb), (size_t)itb, flipb, acc);
+  if (DAG) {  // gamma5 on the hop of gamma5 psi
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const cx<typename IO<P>::T> u = acc[k];
+      acc[k] = typename IO<P>::T(-1) * acc[6 + k];
+      acc[6 + k] = typename IO<P>::T(-1) * u;
+    }
+  }
+}
+
+// D (DAG false) or D^dag (DAG true) at every 5-d site. MOB (D only, c5 != 0):
+// the hop acts on phi = (b5 + c5 S) psi, precomputed.
+//   D, c5 = 0:  out = (b5 d4 + 1) psi - b5/2 H psi - S psi
+//   D, MOB:     out = d4 phi - 1/2 H phi + psi - S psi
+//   D^dag:      u = d4 psi - 1/2 gamma5 H gamma5 psi,
+//               out = b5 u + psi + S^dag (c5 u - psi)
+template <int P, bool DAG, bool MOB>
 __global__ void __launch_bounds__(DWB) k_dwf(DwfArgs a) {
   using T = typename IO<P>::T;
   __shared__ cx<T> lp[6][DWB], lm[6][DWB];
   const int p = blockIdx.y, Ls = a.Ls;
-  const Geom& g = a.g;
   size_t j = 0;
   const bool live = dwf_site(a, j);
   const int i = live ? (int)(j / Ls) : 0;
   const int s = live ? (int)(j - (size_t)i * Ls) : 0;
   const char* own = a.in + (size_t)p * a.hb;
-  const char* other = a.in + (size_t)(1 - p) * a.hb;
 
   cx<T> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
-  if (live) {
-    const int xh = i % g.lxh;
-    int r = i / g.lxh;
-    const int y = r % g.ly;
-    r /= g.ly;
-    const int z = r % g.lz;
-    const int t = r / g.lz;
-    const int x = 2 * xh + ((y + z + t + p) & 1);
-    const int row = i - xh;
-    const int xf = (x + 1 == g.lx) ? 0 : x + 1;
-    const int xb = (x == 0) ? g.lx - 1 : x - 1;
-    const int yl = g.lxh, zl = g.lxh * g.ly, tl = g.lxh * g.ly * g.lz;
-    const int ixf = row + (xf >> 1), ixb = row + (xb >> 1);
-    const int iyf = i + ((y + 1 == g.ly) ? -(g.ly - 1) * yl : yl);
-    const int iyb = i + ((y == 0) ? (g.ly - 1) * yl : -yl);
-    const int izf = i + ((z + 1 == g.lz) ? -(g.lz - 1) * zl : zl);
-    const int izb = i + ((z == 0) ? (g.lz - 1) * zl : -zl);
-    const int itf = i + ((t + 1 == g.lt) ? -(g.lt - 1) * tl : tl);
-    const int itb = i + ((t == 0) ? (g.lt - 1) * tl : -tl);
-    const bool flipf = (g.t_bc < 0) && (t + 1 == g.lt);
-    const bool flipb = (g.t_bc < 0) && (t == 0);
-    const char* gf = a.gauge + (size_t)(p * 4) * a.link_stride;
-    const char* gb = a.gauge + (size_t)((1 - p) * 4) * a.link_stride;
-    const size_t ls = a.link_stride, vh = (size_t)g.vh;
-    auto at = [&](int site) { return (size_t)site * Ls + s; };
-    hop_dir<P, 0, true, false, DAG>(other, gf + 0 * ls, vh, at(ixf), (size_t)i, false, acc);
-    hop_dir<P, 0, false, false, DAG>(other, gb + 0 * ls, vh, at(ixb), (size_t)ixb, false, acc);
-    hop_dir<P, 1, true, false, DAG>(other, gf + 1 * ls, vh, at(iyf), (size_t)i, false, acc);
-    hop_dir<P, 1, false, false, DAG>(other, gb + 1 * ls, vh, at(iyb), (size_t)iyb, false, acc);
-    hop_dir<P, 2, true, false, DAG>(other, gf + 2 * ls, vh, at(izf), (size_t)i, false, acc);
-    hop_dir<P, 2, false, false, DAG>(other, gb + 2 * ls, vh, at(izb), (size_t)izb, false, acc);
-    hop_dir<P, 3, true, false, DAG>(other, gf + 3 * ls, vh, at(itf), (size_t)i, flipf, acc);
-    hop_dir<P, 3, false, false, DAG>(other, gb + 3 * ls, vh, at(itb), (size_t)itb, flipb, acc);
-  }
+  if (live) dwf_hop<P, DAG>(a, MOB ? a.phi : a.in, p, i, s, acc);
   cx<T> v[12];
   if (live) {
     IO<P>::load_spinor(own, j, v);
@@ -136,41 +199,68 @@ __global__ void __launch_bounds__(DWB) k_dwf(DwfArgs a) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = {T(0), T(0)};
   }
-  {
-    cx<T> pp[6], pm[6];
-    chiral_halves(v, pp, pm);
+  const T d4 = (T)a.d4, half = T(-0.5);
+  if (DAG) {
+    const T c5 = (T)a.c5;
+    cx<T> w[12];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      lp[k][threadIdx.x] = pp[k];
-      lm[k][threadIdx.x] = pm[k];
+    for (int k = 0; k < 12; ++k) {
+      acc[k] = d4 * v[k] + half * acc[k];  // u
+      w[k] = c5 * acc[k] - v[k];
     }
+    put_halves(lp, lm, w);
+  } else {
+    put_halves(lp, lm, v);
   }
   __syncthreads();
   if (!live) return;
-  const int base = (int)threadIdx.x - s;
-  const int up = base + (s + 1 < Ls ? s + 1 : 0), dn = base + (s > 0 ? s - 1 : Ls - 1);
-  const T wu = s + 1 < Ls ? T(1) : T(-a.mf), wd = s > 0 ? T(1) : T(-a.mf);
-  const T dg = (T)a.diag, sc = T(-0.5);
-  if (DAG) {  // gamma5 on the hop of gamma5 psi
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const cx<T> u = acc[k];
-      acc[k] = T(-1) * acc[6 + k];
-      acc[6 + k] = T(-1) * u;
-    }
-  }
+  const SNeighbours<T> nb = neighbours(lp, lm, s, Ls, a.mf);
   cx<T> o[12];
+  if (DAG) {
+    const T b5 = (T)a.b5;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    // D: - P_- psi_{s+1} - P_+ psi_{s-1};  D^dag: - P_+ psi_{s+1} - P_- psi_{s-1}
-    const cx<T> a_up = DAG ? lp[k][up] : lm[k][up];
-    const cx<T> b_dn = DAG ? lm[k][dn] : lp[k][dn];
-    const cx<T> ua = wu * a_up, db = wd * b_dn;
-    const cx<T> lo_a = DAG ? T(-1) * ua : ua, lo_b = DAG ? db : T(-1) * db;
-    o[k] = dg * v[k] + sc * acc[k] - ua - db;
-    o[6 + k] = dg * v[6 + k] + sc * acc[6 + k] - lo_a - lo_b;
+    for (int k = 0; k < 12; ++k) o[k] = b5 * acc[k] + v[k];
+    add_s<true>(nb, T(1), o);
+  } else if (MOB) {
+    cx<T> f[12];
+    IO<P>::load_spinor(a.phi + (size_t)p * a.hb, j, f);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[k] = d4 * f[k] + half * acc[k] + v[k];
+    add_s<false>(nb, T(-1), o);
+  } else {
+    const T b5 = (T)a.b5, dg = b5 * d4 + T(1), sc = half * b5;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[k] = dg * v[k] + sc * acc[k];
+    add_s<false>(nb, T(-1), o);
   }
   IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, o);
+}
+
+// out = (b5 + c5 S) in, every 5-d site
+template <int P>
+__global__ void __launch_bounds__(DWB) k_dwf_phi(DwfArgs a) {
+  using T = typename IO<P>::T;
+  __shared__ cx<T> lp[6][DWB], lm[6][DWB];
+  const int p = blockIdx.y;
+  size_t j = 0;
+  const bool live = dwf_site(a, j);
+  const int s = live ? (int)(j % (size_t)a.Ls) : 0;
+  cx<T> v[12];
+  if (live) {
+    IO<P>::load_spinor(a.in + (size_t)p * a.hb, j, v);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = {T(0), T(0)};
+  }
+  put_halves(lp, lm, v);
+  __syncthreads();
+  if (!live) return;
+  const SNeighbours<T> nb = neighbours(lp, lm, s, a.Ls, a.mf);
+  const T b5 = (T)a.b5;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = b5 * v[k];
+  add_s<false>(nb, (T)a.c5, v);
+  IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, v);
 }
 
 // canonical [s][t][z][y][x][spin][colour] complex128 <-> native 5-d field
@@ -272,34 +362,46 @@ int dwf_export(lqcd_ctx* c, int prec, int Ls, const void* f5, double* canon) {
   return LQCD_OK;
 }
 
-// out = D in (dag = 0) or D^dag in (dag = 1) on native 5-d fields (in != out)
-int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out) {
+// out = D in (dag = 0) or D^dag in (dag = 1) on native 5-d fields (in != out;
+// tmp, a third field, holds phi for D with c5 != 0)
+int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tmp) {
   if (!c->gauge[prec]) return set_error(LQCD_ESTATE, "gauge field not set");
   if (d.Ls < 1 || d.Ls > DWB) return set_error(LQCD_EINVAL, "domain-wall operator: Ls must be in [1, 256]");
+  if (prec != 0 && prec != 1) return set_error(LQCD_EINVAL, "domain-wall operator: precision must be F64 or F32");
+  const bool mob = !dag && d.c5 != 0.0;
+  if (mob && !tmp) return set_error(LQCD_EINVAL, "domain-wall operator: D with c5 != 0 needs a scratch field");
   DwfArgs a{};
   a.gauge = reinterpret_cast<const char*>(c->gauge[prec]);
   a.link_stride = link_bytes(prec, c->g.vh);
   a.g = c->g;
   a.in = reinterpret_cast<const char*>(in);
+  a.phi = reinterpret_cast<const char*>(tmp);
   a.out = reinterpret_cast<char*>(out);
   a.hb = half_bytes(prec, c->g.vh, d.Ls);
   a.Ls = d.Ls;
   a.spb = (DWB / d.Ls) * d.Ls;
-  a.diag = 5.0 - d.M5;
-  a.mf = d.mf;
   a.hz = c->g.lz % 8 == 0 ? c->g.lz / 8 : 0;
+  a.d4 = 4.0 - d.M5;
+  a.b5 = d.b5;
+  a.c5 = d.c5;
+  a.mf = d.mf;
   const size_t n = (size_t)c->g.vh * d.Ls;
   const unsigned nb = a.hz ? 8u * (unsigned)((n / 8 + a.spb - 1) / a.spb) : (unsigned)((n + a.spb - 1) / a.spb);
-  const dim3 grid(nb, 2);
-  const int threads = (a.spb + 63) / 64 * 64;
+  const dim3 grid(nb, 2), block((a.spb + 63) / 64 * 64);
+  if (mob) {
+    DwfArgs f = a;
+    f.out = reinterpret_cast<char*>(tmp);
+    if (prec == 0) hipLaunchKernelGGL(k_dwf_phi<0>, grid, block, 0, c->stream, f);
+    else hipLaunchKernelGGL(k_dwf_phi<1>, grid, block, 0, c->stream, f);
+  }
   if (prec == 0) {
-    if (dag) hipLaunchKernelGGL((k_dwf<0, true>), grid, dim3(threads), 0, c->stream, a);
-    else hipLaunchKernelGGL((k_dwf<0, false>), grid, dim3(threads), 0, c->stream, a);
-  } else if (prec == 1) {
-    if (dag) hipLaunchKernelGGL((k_dwf<1, true>), grid, dim3(threads), 0, c->stream, a);
-    else hipLaunchKernelGGL((k_dwf<1, false>), grid, dim3(threads), 0, c->stream, a);
+    if (dag) hipLaunchKernelGGL((k_dwf<0, true, false>), grid, block, 0, c->stream, a);
+    else if (mob) hipLaunchKernelGGL((k_dwf<0, false, true>), grid, block, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_dwf<0, false, false>), grid, block, 0, c->stream, a);
   } else {
-    return set_error(LQCD_EINVAL, "domain-wall operator: precision must be F64 or F32");
+    if (dag) hipLaunchKernelGGL((k_dwf<1, true, false>), grid, block, 0, c->stream, a);
+    else if (mob) hipLaunchKernelGGL((k_dwf<1, false, true>), grid, block, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_dwf<1, false, false>), grid, block, 0, c->stream, a);
   }
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
@@ -358,8 +460,8 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
   const auto t0 = clk::now();
   DWork w;
   const size_t bytes = dwf_field_bytes(0, c->g.vh, d.Ls), n = 2 * padded_sites((size_t)c->g.vh * d.Ls);
-  void *bn, *r, *p, *q, *t;
-  for (void** f : {&bn, &r, &p, &q, &t}) LQ_TRY(w.alloc(c, bytes, f));
+  void *bn, *r, *p, *q, *t, *ph;
+  for (void** f : {&bn, &r, &p, &q, &t, &ph}) LQ_TRY(w.alloc(c, bytes, f));
   LQ_HIP(hipMalloc(&w.partials, (size_t)((n + 255) / 256) * 2 * sizeof(double)));
   double bb = 0.0;
   LQ_TRY(dot(c, w, n, b, b, nullptr, &bb));
@@ -369,7 +471,7 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
   st.seconds_setup = std::chrono::duration<double>(ts - t0).count();
   LQ_HIP(hipMemsetAsync(x, 0, bytes, c->stream));  // x = 0 (padding included)
   if (bnorm == 0.0) return LQCD_OK;
-  LQ_TRY(dwf_apply(c, 0, d, 1, b, bn));  // D^dag b
+  LQ_TRY(dwf_apply(c, 0, d, 1, b, bn, ph));  // D^dag b
   double bnn = 0.0;
   LQ_TRY(dot(c, w, n, bn, bn, nullptr, &bnn));
   int iters = 0, passes = 0, status = LQCD_OK;
@@ -377,7 +479,7 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
   double target = 0.1 * prm.tol * std::sqrt(bnn);
   for (;;) {
     // true residual of D x = b, and the normal-equation residual
-    LQ_TRY(dwf_apply(c, 0, d, 0, x, q));
+    LQ_TRY(dwf_apply(c, 0, d, 0, x, q, ph));
     LQ_TRY(axpy(c, n, t, b, q, -1.0));
     double tt = 0.0;
     LQ_TRY(dot(c, w, n, t, t, nullptr, &tt));
@@ -394,13 +496,13 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
       break;
     }
     ++passes;
-    LQ_TRY(dwf_apply(c, 0, d, 1, t, r));  // r = D^dag (b - D x)
+    LQ_TRY(dwf_apply(c, 0, d, 1, t, r, ph));  // r = D^dag (b - D x)
     LQ_TRY(dot(c, w, n, r, r, nullptr, &rr));
     LQ_TRY(axpy(c, n, p, r, r, 0.0));             // p = r
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
     while (iters < prm.max_iter) {
-      LQ_TRY(dwf_apply(c, 0, d, 0, p, t));
-      LQ_TRY(dwf_apply(c, 0, d, 1, t, q));  // q = D^dag D p
+      LQ_TRY(dwf_apply(c, 0, d, 0, p, t, ph));
+      LQ_TRY(dwf_apply(c, 0, d, 1, t, q, ph));  // q = D^dag D p
       double pq = 0.0;
       LQ_TRY(dot(c, w, n, p, q, &pq, nullptr));
       if (!(pq > 0.0)) break;

@@ -58,12 +58,12 @@ def sap_params(block=(4, 4, 4, 4), ncycles: int = 2, nmr: int = 4) -> SapParams:
 
 
 class DwfParams(C.Structure):
-    _fields_ = [("Ls", C.c_int), ("M5", C.c_double), ("mf", C.c_double)]
+    _fields_ = [("Ls", C.c_int), ("M5", C.c_double), ("mf", C.c_double), ("b5", C.c_double), ("c5", C.c_double)]
 
 
-def dwf_params(Ls: int, M5: float, mf: float) -> DwfParams:
+def dwf_params(Ls: int, M5: float, mf: float, b5: float = 1.0, c5: float = 0.0) -> DwfParams:
     d = DwfParams()
-    d.Ls, d.M5, d.mf = int(Ls), float(M5), float(mf)
+    d.Ls, d.M5, d.mf, d.b5, d.c5 = int(Ls), float(M5), float(mf), float(b5), float(c5)
     return d
 
 
@@ -131,7 +131,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_dwf_field_bytes.restype = C.c_size_t
     lib.lqcd_dwf_import.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_dwf_export.argtypes = [vp, ip, ip, vp, vp]
-    lib.lqcd_dwf_apply_native.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp]
+    lib.lqcd_dwf_apply_native.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp, vp]
     lib.lqcd_stag_hop_native.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_solve_sap.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SapParams), C.POINTER(SolveStats)]
     lib.lqcd_strerror.argtypes = [ip]
@@ -385,26 +385,27 @@ class Lattice:
                "lqcd_stag_apply")
         return out
 
-    def dwf_apply(self, Ls, M5, mf, prec, x, out, dag=False):
-        """Domain-wall D (or D^dag) on canonical 5-d fields [Ls, Lt, Lz, Ly, Lx, 4, 3]."""
+    def dwf_apply(self, Ls, M5, mf, prec, x, out, dag=False, b5=1.0, c5=0.0):
+        """Moebius domain-wall D (or D^dag) on canonical 5-d fields [Ls, Lt, Lz, Ly, Lx, 4, 3]."""
         pi, di = _ptr(x)
         po, do = _ptr(out)
         if di != do:
             raise ValueError("in and out must both be host or both be device")
-        d = dwf_params(Ls, M5, mf)
+        d = dwf_params(Ls, M5, mf, b5, c5)
         _check(self._call(self.lib.lqcd_dwf_apply, self.handle, C.byref(d), int(bool(dag)), int(prec), pi, po, di),
                "lqcd_dwf_apply")
         return out
 
-    def dwf_solve(self, Ls, M5, mf, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True) -> Stats:
-        """Domain-wall D x = b by FP64 CG on the normal equations."""
+    def dwf_solve(self, Ls, M5, mf, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True, b5=1.0,
+                  c5=0.0) -> Stats:
+        """Moebius domain-wall D x = b by FP64 CG on the normal equations."""
         prm = default_params()
         pb, db = _ptr(b)
         px, dx = _ptr(x)
         if db != dx:
             raise ValueError("b and x must both be host or both be device")
         prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
-        d = dwf_params(Ls, M5, mf)
+        d = dwf_params(Ls, M5, mf, b5, c5)
         st = SolveStats()
         status = self._call(self.lib.lqcd_dwf_solve, self.handle, C.byref(d), pb, px, C.byref(prm), C.byref(st))
         if raise_on_fail:
@@ -423,17 +424,18 @@ class Lattice:
         _check(self._call(self.lib.lqcd_dwf_export, self.handle, int(prec), int(Ls), _ptr(native)[0], _ptr(canon)[0]),
                "lqcd_dwf_export")
 
-    def dwf_apply_native_repeat(self, Ls, M5, mf, prec, ins, outs, reps: int, dag=False):
+    def dwf_apply_native_repeat(self, Ls, M5, mf, prec, ins, outs, reps: int, dag=False, b5=1.0, c5=0.0, tmp=None):
         """reps domain-wall applications on native fields, cycling over the (in, out) pairs."""
-        d = dwf_params(Ls, M5, mf)
+        d = dwf_params(Ls, M5, mf, b5, c5)
         pi = [_ptr(t)[0] for t in ins]
         po = [_ptr(t)[0] for t in outs]
+        pt = _ptr(tmp)[0] if tmp is not None else None
         self._enter()
         try:
             for r in range(int(reps)):
                 k = r % len(pi)
-                _check(self.lib.lqcd_dwf_apply_native(self.handle, C.byref(d), int(bool(dag)), int(prec), pi[k], po[k]),
-                       "lqcd_dwf_apply_native")
+                _check(self.lib.lqcd_dwf_apply_native(self.handle, C.byref(d), int(bool(dag)), int(prec), pi[k], po[k],
+                                                      pt), "lqcd_dwf_apply_native")
         finally:
             self._exit()
 

@@ -1,5 +1,6 @@
-"""GPU parity of the domain-wall operator, its adjoint and the normal-equation
-CG against the oracle (oracle/dwf.py), through the C ABI. Tolerances:
+"""GPU parity of the Moebius domain-wall operator (Shamir included), its
+adjoint and the normal-equation CG against the oracle (oracle/dwf.py),
+through the C ABI. Tolerances:
 rel-L2 1e-13 (FP64) and 1e-5 (FP32) per application; solves to a true FP64
 residual of 1e-10."""
 
@@ -26,15 +27,16 @@ def field5(dims, Ls, seed):
                                      ((4, 4, 4, 4), 1)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("t_bc", [-1, 1])
-def test_dwf_apply_matches_oracle(dims, Ls, prec, t_bc):
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5), (1.3, 0.0)])
+def test_dwf_apply_matches_oracle(dims, Ls, prec, t_bc, b5, c5):
     U = fg.gauge_field(dims, 111, "haar")
     psi = field5(dims, Ls, 112)
-    op = dwf.DomainWall(U, 1.8, 0.03, Ls, t_bc)
+    op = dwf.DomainWall(U, 1.8, 0.03, Ls, t_bc, b5, c5)
     lat = lattice(dims, U, 0.12, 0.0, t_bc)
     out = to_dev(np.zeros_like(psi))
-    lat.dwf_apply(Ls, 1.8, 0.03, prec, to_dev(psi), out)
+    lat.dwf_apply(Ls, 1.8, 0.03, prec, to_dev(psi), out, b5=b5, c5=c5)
     assert dirac.rel_l2(from_dev(out), op.D(psi)) <= TOL[prec]
-    lat.dwf_apply(Ls, 1.8, 0.03, prec, to_dev(psi), out, dag=True)
+    lat.dwf_apply(Ls, 1.8, 0.03, prec, to_dev(psi), out, dag=True, b5=b5, c5=c5)
     assert dirac.rel_l2(from_dev(out), op.Ddag(psi)) <= TOL[prec]
 
 
@@ -48,20 +50,23 @@ def test_dwf_host_pointers_and_errors():
     assert dirac.rel_l2(out, dwf.DomainWall(U, 1.5, 0.1, Ls).D(psi)) <= 1e-13
     for call in (lambda: lat.dwf_apply(0, 1.5, 0.1, 0, psi, np.zeros_like(psi)),
                  lambda: lat.dwf_apply(Ls, float("inf"), 0.1, 0, psi, np.zeros_like(psi)),
+                 lambda: lat.dwf_apply(Ls, 1.5, 0.1, 0, psi, np.zeros_like(psi), c5=float("nan")),
+                 lambda: lat.dwf_apply(257, 1.5, 0.1, 0, psi, np.zeros_like(psi)),
                  lambda: lat.dwf_apply(Ls, 1.5, 0.1, 2, psi, np.zeros_like(psi))):
         with pytest.raises(lqcd.LqcdError) as e:
             call()
         assert e.value.status == lqcd.EINVAL
 
 
-def test_dwf_solve_matches_oracle():
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_dwf_solve_matches_oracle(b5, c5):
     dims, Ls = (4, 4, 4, 8), 6
     U = fg.gauge_field(dims, 115, "smooth", 0.3)
     b = field5(dims, Ls, 116)
-    op = dwf.DomainWall(U, 1.8, 0.1, Ls)
+    op = dwf.DomainWall(U, 1.8, 0.1, Ls, -1, b5, c5)
     lat = lattice(dims, U, 0.12, 0.0)
     x = to_dev(np.zeros_like(b))
-    st = lat.dwf_solve(Ls, 1.8, 0.1, to_dev(b), x, tol=1e-10)
+    st = lat.dwf_solve(Ls, 1.8, 0.1, to_dev(b), x, tol=1e-10, b5=b5, c5=c5)
     xh = from_dev(x)
     r = np.linalg.norm(b - op.D(xh)) / np.linalg.norm(b)
     assert st.true_rel_resid <= 1e-10 and r <= 1e-10, (st, r)
@@ -71,20 +76,21 @@ def test_dwf_solve_matches_oracle():
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_dwf_native_apply_matches_oracle(prec):
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_dwf_native_apply_matches_oracle(prec, b5, c5):
     """The bench's path: import, D and D^dag on native fields (left
     uninitialised before the import, padding included), export."""
     import torch
     dims, Ls = (4, 6, 8, 10), 5
     U = fg.gauge_field(dims, 117, "haar")
     psi = field5(dims, Ls, 118)
-    op = dwf.DomainWall(U, 1.8, 0.04, Ls)
+    op = dwf.DomainWall(U, 1.8, 0.04, Ls, -1, b5, c5)
     lat = lattice(dims, U, 0.12, 0.0)
     nb = lat.dwf_field_bytes(prec, Ls)
-    src, dst = (torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(2))
+    src, dst, tmp = (torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(3))
     lat.dwf_import(prec, Ls, to_dev(psi), src)
     for dag, want in ((False, op.D(psi)), (True, op.Ddag(psi))):
-        lat.dwf_apply_native_repeat(Ls, 1.8, 0.04, prec, [src], [dst], 1, dag=dag)
+        lat.dwf_apply_native_repeat(Ls, 1.8, 0.04, prec, [src], [dst], 1, dag=dag, b5=b5, c5=c5, tmp=tmp)
         got = to_dev(np.zeros_like(psi))
         lat.dwf_export(prec, Ls, dst, got)
         torch.cuda.synchronize()
