@@ -24,8 +24,11 @@ Modules:
   decomposition, Dirichlet block operator, minimal-residual block solves)
   and flexible BiCGStab.
 * ``staggered`` -- the staggered operator, its even-odd normal system and CG.
-* ``dwf``     -- the domain-wall operator (Shamir form), its adjoint and the
-  normal-equation solve.
+* ``dwf``     -- the Moebius domain-wall operator (Shamir as a special case),
+  its adjoint and the normal-equation solve.
+* ``mg``      -- the two-level aggregation multigrid: chiral aggregation of
+  test vectors, the coarse operator P^dag D P, the SAP-smoothed setup, the
+  two-level preconditioner and its flexible BiCGStab solve.
 
 Parity status: every function here is pinned by a CPU test (``tests/
 test_oracle_*.py``) except the overall sign and trace convention of the clover
