@@ -196,6 +196,59 @@ int lqcd_apply_sap(lqcd_ctx* ctx, const lqcd_sap_params* sap, const double* eta,
 int lqcd_solve_sap(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_params* prm,
                    const lqcd_sap_params* sap, lqcd_solve_stats* stats);
 
+/* Two-level aggregation multigrid (the paper's headline solver, Sec. 3, in
+ * the DD-alpha-AMG style) for the full clover operator D on the gauge field
+ * and clover term already set.
+ *   aggregates: blocks of extents agg[] (each >= 2, an even number of them per
+ *     direction, at most 256 sites each), coarse index a = ax + nax (ay +
+ *     nay (az + naz at));
+ *   chirality: gamma5 of the Dirac-Pauli basis mixes the upper (u) and lower
+ *     (l) spin pairs; the chiral parts are c_+ = (u - l)/sqrt2 and
+ *     c_- = (u + l)/sqrt2;
+ *   P: one column per (a, chi, k), the chiral part chi of test vector k on a,
+ *     the n columns of each (a, chi) orthonormalised in the order k = 0..n-1
+ *     (Gram-Schmidt); coarse vectors are complex128 of mg_coarse_size entries,
+ *     index (a * 2 + chi) * n + k;
+ *   D_c = P^dag D P (a nearest-neighbour stencil on the aggregates), in FP32;
+ *   setup: from nvec start vectors, setup_iters rounds of v_k <- M_SAP v_k for
+ *     every k followed by the orthonormalisation (0 rounds: the start vectors
+ *     themselves);
+ *   preconditioner: x = P D_c^-1 P^dag r with the coarse system solved by
+ *     FP32 BiCGStab to a relative residual coarse_tol (or coarse_max_iter
+ *     iterations), then x += M_SAP (r - D x); all in FP32.
+ * The setup belongs to the context and is dropped by lqcd_set_gauge and
+ * lqcd_set_clover. */
+typedef struct {
+  int agg[4];             /* aggregate extents (x, y, z, t) */
+  int nvec;               /* test vectors per chirality (1 .. 24) */
+  int setup_iters;        /* SAP smoothing rounds in the setup (0 .. 100) */
+  lqcd_sap_params sap;    /* the smoother (setup and post-smoothing) */
+  double coarse_tol;      /* relative residual of the coarse BiCGStab, in (0, 1) */
+  int coarse_max_iter;    /* iteration cap of the coarse BiCGStab (>= 1) */
+} lqcd_mg_params;
+
+/* Set up the test vectors and the coarse operator from nvec canonical spinor
+ * fields at start (back to back, host or device; random vectors in the usual
+ * use). EINVAL for bad parameters or non-finite start vectors, ESTATE before
+ * set_gauge / set_clover, ENOMEM. On failure no setup remains. */
+int lqcd_mg_setup(lqcd_ctx* ctx, const lqcd_mg_params* mg, const double* start, int on_device);
+/* Entries of a coarse vector; 0 without a setup. */
+size_t lqcd_mg_coarse_size(lqcd_ctx* ctx);
+/* coarse = P^dag fine, fine = P coarse, out = D_c in, x = the two-level
+ * preconditioner applied to r (all in FP32 inside; canonical fine fields and
+ * complex128 coarse vectors, host or device). ESTATE without a setup. */
+int lqcd_mg_restrict(lqcd_ctx* ctx, const double* fine, double* coarse, int on_device);
+int lqcd_mg_prolong(lqcd_ctx* ctx, const double* coarse, double* fine, int on_device);
+int lqcd_mg_coarse_apply(lqcd_ctx* ctx, const double* in, double* out, int on_device);
+int lqcd_mg_apply(lqcd_ctx* ctx, const double* r, double* x, int on_device);
+/* Solve D x = b (canonical fields, host or device) by FP64 flexible BiCGStab
+ * with the two-level preconditioner on the right, until the true residual
+ * ||b - D x|| / ||b|| <= prm->tol. stats: outer_iters = flexible BiCGStab
+ * iterations, inner_iters = preconditioner applications. ESTATE without a
+ * setup; ENOCONV / EBREAKDOWN as lqcd_solve. */
+int lqcd_solve_mg(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_params* prm,
+                  lqcd_solve_stats* stats);
+
 /* Staggered fermions (one of the operator kinds the paper lists, Sec. 2), on
  * the gauge field already set: D = m + H with
  *   (H psi)(x) = 1/2 sum_mu eta_mu(x) [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)],

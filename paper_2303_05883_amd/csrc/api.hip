@@ -11,6 +11,7 @@
 #include "sap.h"
 #include "stag.h"
 #include "dwf.h"
+#include "mg.h"
 #include "solver.h"
 #include "tune.h"
 
@@ -172,10 +173,20 @@ int lqcd_create(const int dims[4], int t_bc, void* hip_stream, lqcd_ctx** out) {
   return LQCD_OK;
 }
 
+static void drop_mg(lqcd_ctx* c) {
+  if (c->mg && c->mg_free) {
+    (void)hipStreamSynchronize(c->stream);
+    c->mg_free(c->mg);
+  }
+  c->mg = nullptr;
+  c->mg_free = nullptr;
+}
+
 int lqcd_destroy(lqcd_ctx* c) {
   if (!c) return LQCD_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->batch && c->batch_free) c->batch_free(c->batch);
+  if (c->mg && c->mg_free) c->mg_free(c->mg);
   if (c->ws) {
     c->ws->release();
     delete c->ws;
@@ -204,6 +215,7 @@ int lqcd_set_gauge(lqcd_ctx* c, const double* U, int on_device) {
   c->have_gauge = false;
   c->have_clover = false;
   invalidate_graphs(c);
+  drop_mg(c);
   const size_t bytes = full_sites(c) * 72 * sizeof(double);  // 4 links x 9 complex per site
   void* staging = nullptr;
   const double* dev = U;
@@ -246,6 +258,7 @@ int lqcd_set_clover(lqcd_ctx* c, double kappa, double csw) {
   if (!std::isfinite(kappa) || !std::isfinite(csw)) return set_error(LQCD_EINVAL, "kappa and c_SW must be finite");
   if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
   invalidate_graphs(c);
+  drop_mg(c);
   c->have_clover = false;
   c->kappa = kappa;
   c->csw = csw;
@@ -626,6 +639,163 @@ int lqcd_dwf_apply_native(lqcd_ctx* c, const lqcd_dwf_params* d, int dag, int pr
   if ((prec != 0 && prec != 1) || (dag != 0 && dag != 1)) return set_error(LQCD_EINVAL, "bad precision or dag");
   if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
   return dwf_apply(c, prec, *d, dag, in, out, tmp);
+}
+
+static int validate_mg(const lqcd_ctx* c, const lqcd_mg_params* mp) {
+  if (!mp) return set_error(LQCD_EINVAL, "null multigrid parameters");
+  if (!mg_shape_ok(c->g, mp->agg))
+    return set_error(LQCD_EINVAL, "aggregates must have extents >= 2, tile the lattice with an even number per "
+                                  "direction and hold at most 256 sites");
+  if (mp->nvec < 1 || mp->nvec > 24) return set_error(LQCD_EINVAL, "multigrid needs 1 to 24 test vectors");
+  if (mp->setup_iters < 0 || mp->setup_iters > 100) return set_error(LQCD_EINVAL, "setup_iters must be 0..100");
+  if (!(mp->coarse_tol > 0.0 && mp->coarse_tol < 1.0) || mp->coarse_max_iter < 1)
+    return set_error(LQCD_EINVAL, "coarse_tol must be in (0, 1) and coarse_max_iter >= 1");
+  return validate_sap(c, &mp->sap);
+}
+
+int lqcd_mg_setup(lqcd_ctx* c, const lqcd_mg_params* mp, const double* start, int on_device) {
+  if (!c || !start) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_mg(c, mp));
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  LQ_TRY(ensure_apply_buffers(c, 1));
+  const size_t n = full_sites(c) * 24 * (size_t)mp->nvec;
+  Bufs bf;
+  const double* ds = start;
+  if (!on_device) {
+    void* d = nullptr;
+    LQ_TRY(bf.get(c, n * sizeof(double), &d));
+    LQ_HIP(hipMemcpyAsync(d, start, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    ds = reinterpret_cast<const double*>(d);
+  }
+  LQ_TRY(check_finite(c, ds, n));
+  const int status = mg_setup(c, *mp, ds);
+  if (status != LQCD_OK) drop_mg(c);
+  return status;
+}
+
+size_t lqcd_mg_coarse_size(lqcd_ctx* c) { return c ? mg_coarse_size(c) : 0; }
+
+// canonical fine field (host or device) -> FP32 native halves half_a[1], half_b[1]
+static int mg_stage_fine(lqcd_ctx* c, const double* in, int on_device) {
+  LQ_TRY(ensure_apply_buffers(c, 1));
+  const double* din = nullptr;
+  LQ_TRY(stage_in(c, in, on_device, c->canon_a, full_sites(c) * 192, &din));
+  LQ_TRY(launch_import_spinor(c, 1, 0, din, c->half_a[1]));
+  return launch_import_spinor(c, 1, 1, din, c->half_b[1]);
+}
+
+// FP32 native halves half_c[1], half_d[1] -> canonical fine field (host or device)
+static int mg_unstage_fine(lqcd_ctx* c, double* out, int on_device) {
+  const size_t bytes = full_sites(c) * 192;
+  double* dout = on_device ? out : reinterpret_cast<double*>(c->canon_b);
+  LQ_TRY(launch_export_spinor(c, 1, 0, c->half_c[1], dout));
+  LQ_TRY(launch_export_spinor(c, 1, 1, c->half_d[1], dout));
+  if (!on_device) LQ_HIP(hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  return LQCD_OK;
+}
+
+// a coarse complex128 vector (host or device) -> FP32 complex device vector
+static int mg_stage_coarse(lqcd_ctx* c, Bufs& bf, const double* in, int on_device, void** f32) {
+  const size_t nc = mg_coarse_size(c);
+  LQ_TRY(bf.get(c, nc * 8, f32));
+  const double* din = in;
+  if (!on_device) {
+    void* d = nullptr;
+    LQ_TRY(bf.get(c, nc * 16, &d));
+    LQ_HIP(hipMemcpyAsync(d, in, nc * 16, hipMemcpyHostToDevice, c->stream));
+    din = reinterpret_cast<const double*>(d);
+  }
+  return mg_coarse_convert(c, din, true, *f32, nc);
+}
+
+static int mg_unstage_coarse(lqcd_ctx* c, Bufs& bf, const void* f32, double* out, int on_device) {
+  const size_t nc = mg_coarse_size(c);
+  double* dout = out;
+  if (!on_device) {
+    void* d = nullptr;
+    LQ_TRY(bf.get(c, nc * 16, &d));
+    dout = reinterpret_cast<double*>(d);
+  }
+  LQ_TRY(mg_coarse_convert(c, f32, false, dout, nc));
+  if (!on_device) LQ_HIP(hipMemcpyAsync(out, dout, nc * 16, hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  return LQCD_OK;
+}
+
+int lqcd_mg_restrict(lqcd_ctx* c, const double* fine, double* coarse, int on_device) {
+  if (!c || !fine || !coarse) return set_error(LQCD_EINVAL, "null argument");
+  if (!c->mg) return set_error(LQCD_ESTATE, "lqcd_mg_setup must come first");
+  LQ_TRY(mg_stage_fine(c, fine, on_device));
+  Bufs bf;
+  void* rc = nullptr;
+  LQ_TRY(bf.get(c, mg_coarse_size(c) * 8, &rc));
+  LQ_TRY(mg_restrict(c, c->half_a[1], c->half_b[1], rc));
+  return mg_unstage_coarse(c, bf, rc, coarse, on_device);
+}
+
+int lqcd_mg_prolong(lqcd_ctx* c, const double* coarse, double* fine, int on_device) {
+  if (!c || !fine || !coarse) return set_error(LQCD_EINVAL, "null argument");
+  if (!c->mg) return set_error(LQCD_ESTATE, "lqcd_mg_setup must come first");
+  LQ_TRY(ensure_apply_buffers(c, 1));
+  Bufs bf;
+  void* ec = nullptr;
+  LQ_TRY(mg_stage_coarse(c, bf, coarse, on_device, &ec));
+  LQ_TRY(mg_prolong(c, ec, c->half_c[1], c->half_d[1]));
+  return mg_unstage_fine(c, fine, on_device);
+}
+
+int lqcd_mg_coarse_apply(lqcd_ctx* c, const double* in, double* out, int on_device) {
+  if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
+  if (!c->mg) return set_error(LQCD_ESTATE, "lqcd_mg_setup must come first");
+  Bufs bf;
+  void *x = nullptr, *y = nullptr;
+  LQ_TRY(mg_stage_coarse(c, bf, in, on_device, &x));
+  LQ_TRY(bf.get(c, mg_coarse_size(c) * 8, &y));
+  LQ_TRY(mg_coarse_apply(c, x, y));
+  return mg_unstage_coarse(c, bf, y, out, on_device);
+}
+
+int lqcd_mg_apply(lqcd_ctx* c, const double* r, double* x, int on_device) {
+  if (!c || !r || !x) return set_error(LQCD_EINVAL, "null argument");
+  if (!c->mg) return set_error(LQCD_ESTATE, "lqcd_mg_setup must come first");
+  LQ_TRY(mg_stage_fine(c, r, on_device));
+  LQ_TRY(mg_precond(c, c->half_a[1], c->half_b[1], c->half_c[1], c->half_d[1], nullptr));
+  return mg_unstage_fine(c, x, on_device);
+}
+
+int lqcd_solve_mg(lqcd_ctx* c, const double* b, double* x, const lqcd_solve_params* prm_in, lqcd_solve_stats* stats) {
+  if (!c || !b || !x) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_params(prm_in));
+  if (!c->mg) return set_error(LQCD_ESTATE, "lqcd_mg_setup must come first");
+  lqcd_solve_params prm;
+  if (prm_in) prm = *prm_in;
+  else lqcd_default_params(&prm);
+  LQ_TRY(ensure_apply_buffers(c, 0));
+  const size_t bytes = full_sites(c) * 192;
+  const double* db = nullptr;
+  LQ_TRY(stage_in(c, b, prm.on_device, c->canon_a, bytes, &db));
+  LQ_TRY(check_finite(c, db, full_sites(c) * 24));
+  void *be = c->half_a[0], *bo = c->half_b[0], *xe = c->half_c[0], *xo = c->half_d[0];
+  LQ_TRY(launch_import_spinor(c, 0, 0, db, be));
+  LQ_TRY(launch_import_spinor(c, 0, 1, db, bo));
+  if (prm.x0) {
+    const double* dx0 = nullptr;
+    LQ_TRY(stage_in(c, prm.x0, prm.on_device, c->canon_b, bytes, &dx0));
+    LQ_TRY(launch_import_spinor(c, 0, 0, dx0, xe));
+    LQ_TRY(launch_import_spinor(c, 0, 1, dx0, xo));
+  }
+  lqcd_solve_stats st{};
+  long coarse = 0;
+  const int status = solve_mg(c, prm, be, bo, xe, xo, prm.x0 == nullptr, st, &coarse);
+  if (status != LQCD_OK && status != LQCD_ENOCONV && status != LQCD_EBREAKDOWN) return status;
+  double* dx = prm.on_device ? x : reinterpret_cast<double*>(c->canon_b);
+  LQ_TRY(launch_export_spinor(c, 0, 0, xe, dx));
+  LQ_TRY(launch_export_spinor(c, 0, 1, xo, dx));
+  if (!prm.on_device) LQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  if (stats) *stats = st;
+  return status;
 }
 
 size_t lqcd_stag_field_bytes(lqcd_ctx* c, int prec) {

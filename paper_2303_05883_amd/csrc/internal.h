@@ -146,6 +146,10 @@ struct lqcd_ctx {
   // next batch has the same shape)
   void* batch = nullptr;
   void (*batch_free)(void*) = nullptr;
+  // multigrid setup (test vectors, coarse operator); dropped when the gauge
+  // field or the clover term changes
+  void* mg = nullptr;
+  void (*mg_free)(void*) = nullptr;
 };
 
 namespace lq {

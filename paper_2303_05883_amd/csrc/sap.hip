@@ -417,20 +417,18 @@ inline cx<double> cdivd(cx<double> a, cx<double> b) {
 
 }  // namespace
 
-// D x = b on the full lattice (FP64 native halves), flexible BiCGStab with the
-// FP32 SAP preconditioner on the right; stops on the true residual.
-int solve_sap(lqcd_ctx* c, const lqcd_solve_params& prm, const int blk[4], int ncy, int nmr, const void* b_e,
-              const void* b_o, void* x_e, void* x_o, bool zero_x, lqcd_solve_stats& st) {
+// D x = b on the full lattice (FP64 native halves) by flexible BiCGStab with
+// the preconditioner pre on the right (FP64 halves in, FP64 halves out; it may
+// vary between calls); stops on the true residual. name labels the log lines.
+int solve_flexible(lqcd_ctx* c, const lqcd_solve_params& prm, const FlexPrecond& pre, const char* name,
+                   const void* b_e, const void* b_o, void* x_e, void* x_o, bool zero_x, lqcd_solve_stats& st) {
   using clk = std::chrono::steady_clock;
   const auto t0 = clk::now();
-  if (!sap_shape_ok(c->g, blk)) return set_error(LQCD_EINVAL, "bad SAP block shape");
   FWork w;
-  const size_t b64 = spinor_bytes(0, c->g.vh), b32 = spinor_bytes(1, c->g.vh);
-  Pair r, rh, p, v, s, t, ph, sh, ax, e32, q32;
+  const size_t b64 = spinor_bytes(0, c->g.vh);
+  Pair r, rh, p, v, s, t, ph, sh, ax;
   for (Pair* q : {&r, &rh, &p, &v, &s, &t, &ph, &sh, &ax})
     for (auto& h : q->h) LQ_TRY(w.alloc(b64, &h));
-  for (Pair* q : {&e32, &q32})
-    for (auto& h : q->h) LQ_TRY(w.alloc(b32, &h));
   LQ_HIP(hipMalloc(&w.partials, (size_t)2 * grid_of(c->g.vh) * 3 * sizeof(double)));
   Pair b, x;
   b.h[0] = const_cast<void*>(b_e);
@@ -444,9 +442,7 @@ int solve_sap(lqcd_ctx* c, const lqcd_solve_params& prm, const int blk[4], int n
   auto apply = [&](Pair in, Pair out) -> int { return op_full(c, 0, in.h[0], in.h[1], out.h[0], out.h[1]); };
   int napply = 0;
   auto precond = [&](Pair in, Pair out) -> int {
-    for (int h = 0; h < 2; ++h) LQ_TRY(launch_convert_field(c, 0, in.h[h], 1, e32.h[h]));
-    LQ_TRY(sap_apply(c, blk, ncy, nmr, e32.h[0], e32.h[1], q32.h[0], q32.h[1]));
-    for (int h = 0; h < 2; ++h) LQ_TRY(launch_convert_field(c, 1, q32.h[h], 0, out.h[h]));
+    LQ_TRY(pre(in.h[0], in.h[1], out.h[0], out.h[1]));
     ++napply;
     return LQCD_OK;
   };
@@ -473,15 +469,15 @@ int solve_sap(lqcd_ctx* c, const lqcd_solve_params& prm, const int blk[4], int n
     LQ_TRY(dot(c, w, r, r, nullptr, &rr));
     rnorm = std::sqrt(rr);
     if (log_level() >= 1)
-      std::fprintf(stderr, "[lqcd] SAP-FBiCGStab restart %d: %d iterations, |r|/|b| %.3e\n", restarts, iters,
+      std::fprintf(stderr, "[lqcd] %s-FBiCGStab restart %d: %d iterations, |r|/|b| %.3e\n", name, restarts, iters,
                    rnorm / bnorm);
     if (rnorm <= target) break;
     if (!(rnorm == rnorm)) {
-      status = set_error(LQCD_EBREAKDOWN, "SAP-preconditioned solve produced NaN");
+      status = set_error(LQCD_EBREAKDOWN, "preconditioned flexible BiCGStab produced NaN");
       break;
     }
     if (iters >= prm.max_iter || restarts > prm.max_outer) {
-      status = set_error(LQCD_ENOCONV, "SAP-preconditioned solve did not reach the tolerance");
+      status = set_error(LQCD_ENOCONV, "preconditioned flexible BiCGStab did not reach the tolerance");
       break;
     }
     LQ_TRY(lin3(c, rh, {1, 0}, r));
@@ -518,7 +514,7 @@ int solve_sap(lqcd_ctx* c, const lqcd_solve_params& prm, const int blk[4], int n
       double rn2 = 0.0;
       LQ_TRY(dot(c, w, r, r, nullptr, &rn2));
       if (log_level() >= 2)
-        std::fprintf(stderr, "[lqcd] SAP-FBiCGStab iteration %d: |r|/|b| %.3e\n", iters, std::sqrt(rn2) / bnorm);
+        std::fprintf(stderr, "[lqcd] %s-FBiCGStab iteration %d: |r|/|b| %.3e\n", name, iters, std::sqrt(rn2) / bnorm);
       if (std::sqrt(rn2) <= target || (omega.r == 0.0 && omega.i == 0.0)) break;
     }
     ++restarts;
@@ -529,6 +525,26 @@ int solve_sap(lqcd_ctx* c, const lqcd_solve_params& prm, const int blk[4], int n
   st.true_rel_resid = rnorm / bnorm;
   st.seconds_solve = std::chrono::duration<double>(clk::now() - t1).count();
   return status;
+}
+
+// D x = b with FP64 flexible BiCGStab, the FP32 SAP preconditioner on the right.
+int solve_sap(lqcd_ctx* c, const lqcd_solve_params& prm, const int blk[4], int ncy, int nmr, const void* b_e,
+              const void* b_o, void* x_e, void* x_o, bool zero_x, lqcd_solve_stats& st) {
+  if (!sap_shape_ok(c->g, blk)) return set_error(LQCD_EINVAL, "bad SAP block shape");
+  const size_t b32 = spinor_bytes(1, c->g.vh);
+  FWork w;
+  Pair e32, q32;
+  for (Pair* q : {&e32, &q32})
+    for (auto& h : q->h) LQ_TRY(w.alloc(b32, &h));
+  FlexPrecond pre = [&](const void* ie, const void* io, void* oe, void* oo) -> int {
+    LQ_TRY(launch_convert_field(c, 0, ie, 1, e32.h[0]));
+    LQ_TRY(launch_convert_field(c, 0, io, 1, e32.h[1]));
+    LQ_TRY(sap_apply(c, blk, ncy, nmr, e32.h[0], e32.h[1], q32.h[0], q32.h[1]));
+    LQ_TRY(launch_convert_field(c, 1, q32.h[0], 0, oe));
+    LQ_TRY(launch_convert_field(c, 1, q32.h[1], 0, oo));
+    return LQCD_OK;
+  };
+  return solve_flexible(c, prm, pre, "SAP", b_e, b_o, x_e, x_o, zero_x, st);
 }
 
 }  // namespace lq

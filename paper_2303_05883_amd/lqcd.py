@@ -34,8 +34,8 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
             "lqcd_apply_sap", "lqcd_solve_sap", "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_field_bytes",
             "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_dwf_apply",
             "lqcd_dwf_solve", "lqcd_dwf_field_bytes", "lqcd_dwf_import", "lqcd_dwf_export", "lqcd_dwf_apply_native",
-            "lqcd_strerror",
-            "lqcd_last_error"]
+            "lqcd_mg_setup", "lqcd_mg_coarse_size", "lqcd_mg_restrict", "lqcd_mg_prolong", "lqcd_mg_coarse_apply",
+            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_strerror", "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
 
@@ -55,6 +55,22 @@ def sap_params(block=(4, 4, 4, 4), ncycles: int = 2, nmr: int = 4) -> SapParams:
         sp.block[k] = int(block[k])
     sp.ncycles, sp.nmr = int(ncycles), int(nmr)
     return sp
+
+
+class MgParams(C.Structure):
+    _fields_ = [("agg", C.c_int * 4), ("nvec", C.c_int), ("setup_iters", C.c_int), ("sap", SapParams),
+                ("coarse_tol", C.c_double), ("coarse_max_iter", C.c_int)]
+
+
+def mg_params(agg=(4, 4, 4, 4), nvec: int = 8, setup_iters: int = 3, sap_block=(4, 4, 4, 4), ncycles: int = 2,
+              nmr: int = 4, coarse_tol: float = 0.05, coarse_max_iter: int = 200) -> MgParams:
+    mp = MgParams()
+    for k in range(4):
+        mp.agg[k] = int(agg[k])
+    mp.nvec, mp.setup_iters = int(nvec), int(setup_iters)
+    mp.sap = sap_params(sap_block, ncycles, nmr)
+    mp.coarse_tol, mp.coarse_max_iter = float(coarse_tol), int(coarse_max_iter)
+    return mp
 
 
 class DwfParams(C.Structure):
@@ -134,6 +150,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_dwf_apply_native.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp, vp]
     lib.lqcd_stag_hop_native.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_solve_sap.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SapParams), C.POINTER(SolveStats)]
+    lib.lqcd_mg_setup.argtypes = [vp, C.POINTER(MgParams), vp, ip]
+    lib.lqcd_mg_coarse_size.argtypes = [vp]
+    lib.lqcd_mg_coarse_size.restype = C.c_size_t
+    for name in ("lqcd_mg_restrict", "lqcd_mg_prolong", "lqcd_mg_coarse_apply", "lqcd_mg_apply"):
+        getattr(lib, name).argtypes = [vp, vp, vp, ip]
+    lib.lqcd_solve_mg.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
     lib.lqcd_strerror.argtypes = [ip]
     lib.lqcd_strerror.restype = C.c_char_p
     lib.lqcd_last_error.argtypes = []
@@ -143,7 +165,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "lqcd_set_hop_shape", "lqcd_get_hop_shape", "lqcd_apply_sap", "lqcd_solve_sap",
                  "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_import", "lqcd_stag_export",
                  "lqcd_stag_hop_native", "lqcd_dwf_apply", "lqcd_dwf_solve", "lqcd_dwf_import",
-                 "lqcd_dwf_export", "lqcd_dwf_apply_native"):
+                 "lqcd_dwf_export", "lqcd_dwf_apply_native", "lqcd_mg_setup", "lqcd_mg_restrict", "lqcd_mg_prolong",
+                 "lqcd_mg_coarse_apply", "lqcd_mg_apply", "lqcd_solve_mg"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -371,6 +394,52 @@ class Lattice:
         status = self._call(self.lib.lqcd_solve_sap, self.handle, pb, px, C.byref(prm), C.byref(sp), C.byref(st))
         if raise_on_fail:
             _check(status, "lqcd_solve_sap")
+        return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
+                     st.seconds_setup, status)
+
+    def mg_setup(self, start, **kw):
+        """Multigrid setup from start vectors [nvec, Lt, Lz, Ly, Lx, 4, 3]; kw as mg_params."""
+        ps, ds = _ptr(start)
+        mp = mg_params(**kw)
+        _check(self._call(self.lib.lqcd_mg_setup, self.handle, C.byref(mp), ps, ds), "lqcd_mg_setup")
+
+    def mg_coarse_size(self) -> int:
+        return int(self.lib.lqcd_mg_coarse_size(self.handle))
+
+    def _mg_pair(self, name, a, b):
+        pa, da = _ptr(a)
+        pb, dbv = _ptr(b)
+        if da != dbv:
+            raise ValueError("both arguments must be host or both be device")
+        _check(self._call(getattr(self.lib, name), self.handle, pa, pb, da), name)
+        return b
+
+    def mg_restrict(self, fine, coarse):
+        return self._mg_pair("lqcd_mg_restrict", fine, coarse)
+
+    def mg_prolong(self, coarse, fine):
+        return self._mg_pair("lqcd_mg_prolong", coarse, fine)
+
+    def mg_coarse_apply(self, x, y):
+        return self._mg_pair("lqcd_mg_coarse_apply", x, y)
+
+    def mg_apply(self, r, x):
+        return self._mg_pair("lqcd_mg_apply", r, x)
+
+    def solve_mg(self, b, x, tol=1e-10, max_iter=10000, max_outer=20, x0=None, raise_on_fail=True) -> Stats:
+        """D x = b by FP64 flexible BiCGStab with the two-level multigrid preconditioner."""
+        prm = default_params()
+        pb, db = _ptr(b)
+        px, dx = _ptr(x)
+        if db != dx:
+            raise ValueError("b and x must both be host or both be device")
+        prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
+        if x0 is not None:
+            prm.x0 = _ptr(x0)[0]
+        st = SolveStats()
+        status = self._call(self.lib.lqcd_solve_mg, self.handle, pb, px, C.byref(prm), C.byref(st))
+        if raise_on_fail:
+            _check(status, "lqcd_solve_mg")
         return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
                      st.seconds_setup, status)
 
