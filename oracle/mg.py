@@ -21,9 +21,11 @@ the pieces and prints no steps; the definitions here are the textbook ones:
   k = 1 .. n (the Q of a QR factorisation with a positive real diagonal in R);
   coarse index ``(a * 2 + chi) * n + k`` with chi = 0 for c_+, 1 for c_-;
 * the coarse operator is ``D_c = P^dag D P``;
-* setup: from given start vectors, ``n_iter`` times: ``v_k <- M_SAP v_k`` for
-  every k, then the aggregate-wise orthonormalisation (the test vectors become
-  the orthonormalised basis);
+* setup: from given start vectors, ``n_iter`` times: one SAP-smoothing step
+  of the homogeneous equation ``D v = 0``, ``v_k <- v_k - M_SAP D v_k``, for
+  every k (it damps the modes SAP resolves and keeps the near-null space),
+  then the aggregate-wise orthonormalisation (the test vectors become the
+  orthonormalised basis);
 * the two-level preconditioner: ``x = P D_c^-1 P^dag r`` with the coarse
   system solved by BiCGStab to a relative residual ``coarse_tol``, then one SAP
   post-smoothing ``x <- x + M_SAP (r - D x)``.
@@ -129,12 +131,12 @@ def coarse_operator(D, P: Prolongation) -> np.ndarray:
 
 
 def setup(D, agg: Aggregates, start, sap_blocks: sap.Blocks, n_iter: int, ncy: int, nmr: int) -> Prolongation:
-    """Test vectors by n_iter rounds of SAP smoothing and aggregate-wise
-    orthonormalisation of the given start vectors."""
+    """Test vectors by n_iter rounds of SAP smoothing of D v = 0 and
+    aggregate-wise orthonormalisation of the given start vectors."""
     v = [np.asarray(s, dtype=np.complex128) for s in start]
     P = Prolongation(agg, v)
     for _ in range(n_iter):
-        v = [sap.sap(D, sap_blocks, vk, ncy, nmr) for vk in v]
+        v = [vk - sap.sap(D, sap_blocks, D(vk), ncy, nmr) for vk in v]
         P = Prolongation(agg, v)
         v = P.vectors()
     return P
