@@ -438,6 +438,80 @@ def run_sap(a, torch, lqcd):
     return value, ms_step, config, roof, None, compare, None, lqcd.F32
 
 
+# two-level multigrid on the clover workload; the smoother uses the SAP
+# workload's block shape and MR steps (the same kernel, whose roofline is
+# reported)
+MG = dict(agg=(4, 4, 4, 4), nvec=8, setup_iters=6, sap_block=SAP_BLOCK, ncycles=2, nmr=SAP_NMR, coarse_tol=0.05,
+          coarse_max_iter=200)
+
+
+def mg_fine_flops(vh, st, ncy, nmr):
+    """Fine-lattice flops of one multigrid solve: the FP64 full operator (two
+    hops and two clover terms per application: 2 per flexible BiCGStab
+    iteration and one per restart check), and per preconditioner application
+    one FP32 full operator and 2 ncy SAP block launches over half the sites.
+    The coarse grid, restriction and prolongation are not counted."""
+    full = 2 * (1320 + 504) * vh
+    sap_launch = vh * ((1320 + 504 + 48) + nmr * (1320 + 504 + 96))
+    return full * (2 * st.outer_iters + st.restarts + 2) + st.inner_iters * (full + 2 * ncy * sap_launch)
+
+
+def run_mg(a, torch, lqcd):
+    w = WORKLOADS["clover"]
+    dims = w["dims"]
+    vh = int(np.prod(dims)) // 2
+    lat, U, b = make_lattice(torch, lqcd, dims, w["seed"], w["eps"], w["kappa"], w["csw"])
+    bd = torch.from_numpy(b).cuda()
+    tune(lat, lqcd, a.cached, str(dims))
+    lx, ly, lz, lt = dims
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w["seed"] + 17)
+    shape = (MG["nvec"], lt, lz, ly, lx, 4, 3)
+    start = torch.complex(torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64),
+                          torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64)) / np.sqrt(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.mg_setup(start, **MG)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    del start
+    torch.cuda.empty_cache()
+    log(f"multigrid setup: {setup_s:.3f} s, coarse vectors of {lat.mg_coarse_size()} entries")
+    x = torch.zeros_like(bd)
+    for _ in range(a.warmup):
+        lat.solve_mg(bd, x)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = [lat.solve_mg(bd, x) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    worst = max(s.true_rel_resid for s in stats)
+    if not worst <= 1e-10:
+        log(f"true residual {worst} above 1e-10")
+        sys.exit(1)
+    value = sum(mg_fine_flops(vh, s, MG["ncycles"], MG["nmr"]) for s in stats) / elapsed / 1e9
+    ms_step = 1000 * elapsed / a.steps
+    log(f"timed {a.steps} multigrid solves: {ms_step:.1f} ms each, {stats[-1]}")
+    roof = sap_kernel_roofline(torch, lat, vh)
+    log(f"SAP kernel: {roof}")
+    compare = None
+    if not a.no_compare:
+        compare = compare_solves(torch, lat, lqcd, bd)
+        compare["mg_fbicgstab"] = {"ms": round(ms_step, 2), "outer": stats[-1].outer_iters,
+                                   "preconditioner_applications": stats[-1].inner_iters,
+                                   "setup_s": round(setup_s, 3), "true_rel_resid": stats[-1].true_rel_resid,
+                                   "speedup_vs_f64": round(compare["f64"]["ms"] / ms_step, 3)}
+    config = {"workload": w["text"].replace("even-odd BiCGStab", "full-lattice flexible BiCGStab (FP64)") +
+              f", two-level multigrid preconditioner (FP32): aggregates {'x'.join(map(str, MG['agg']))}, "
+              f"{MG['nvec']} test vectors, {MG['setup_iters']} setup rounds, SAP smoother blocks "
+              f"{'x'.join(map(str, MG['sap_block']))} ({MG['ncycles']} cycles, {MG['nmr']} MR steps), coarse "
+              f"BiCGStab to {MG['coarse_tol']}, to true residual 1e-10; setup timed apart",
+              "lattice": list(dims), "kappa": w["kappa"], "csw": w["csw"], "step": "one whole solve (setup excluded)",
+              "setup_s": round(setup_s, 3), "outer_iters_per_solve": stats[-1].outer_iters,
+              "value_counts": "fine-lattice operator and SAP flops only", "parallelism": "single GPU"}
+    return value, ms_step, config, roof, None, compare, None, lqcd.F32
+
+
 STAG_MASS = 0.05
 STAG_FLOPS = 570            # per output site per staggered hop
 STAG_BYTES = {0: 8 * 96 + 48 + 48, 1: 8 * 48 + 24 + 24}  # 8 links x 12 reals, vector in, vector out
@@ -626,7 +700,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large", "sap", "staggered", "dwf"], default="wilson")
+    ap.add_argument("--workload", choices=["wilson", "clover", "batch", "large", "sap", "mg", "staggered", "dwf"], default="wilson")
     ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-vs-mixed solve comparison")
@@ -650,7 +724,7 @@ def main():
     a.cached = bool(a.tune_cache) and os.path.exists(a.tune_cache)
     if a.tune_cache:
         os.environ["LQCD_TUNE_CACHE"] = os.path.abspath(a.tune_cache)
-    runner = {"batch": run_batch, "sap": run_sap, "staggered": run_staggered, "dwf": run_dwf}.get(a.workload, run_single)
+    runner = {"batch": run_batch, "sap": run_sap, "mg": run_mg, "staggered": run_staggered, "dwf": run_dwf}.get(a.workload, run_single)
     res = runner(a, torch, lqcd)
     if res is None:
         return

@@ -210,9 +210,9 @@ int lqcd_solve_sap(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_p
  *     (Gram-Schmidt); coarse vectors are complex128 of mg_coarse_size entries,
  *     index (a * 2 + chi) * n + k;
  *   D_c = P^dag D P (a nearest-neighbour stencil on the aggregates), in FP32;
- *   setup: from nvec start vectors, setup_iters rounds of v_k <- M_SAP v_k for
- *     every k followed by the orthonormalisation (0 rounds: the start vectors
- *     themselves);
+ *   setup: from nvec start vectors, setup_iters rounds of one SAP-smoothing
+ *     step of D v = 0, v_k <- v_k - M_SAP D v_k, for every k, each followed by
+ *     the orthonormalisation (0 rounds: the start vectors themselves);
  *   preconditioner: x = P D_c^-1 P^dag r with the coarse system solved by
  *     FP32 BiCGStab to a relative residual coarse_tol (or coarse_max_iter
  *     iterations), then x += M_SAP (r - D x); all in FP32.

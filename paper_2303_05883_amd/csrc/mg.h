@@ -9,8 +9,9 @@ namespace lq {
 // even number of aggregates per direction, at most 256 sites per aggregate.
 bool mg_shape_ok(const Geom& g, const int a[4]);
 // Test vectors from prm.nvec canonical FP64 device fields at start (back to
-// back), prm.setup_iters rounds of SAP smoothing and aggregate-wise
-// orthonormalisation, then the coarse operator; replaces any earlier setup.
+// back), prm.setup_iters rounds of SAP smoothing of D v = 0 (v <- v - M D v)
+// and aggregate-wise orthonormalisation, then the coarse operator; replaces
+// any earlier setup.
 int mg_setup(lqcd_ctx* c, const lqcd_mg_params& prm, const double* start);
 // complex entries of a coarse vector (0 without a setup)
 size_t mg_coarse_size(lqcd_ctx* c);

@@ -662,13 +662,15 @@ int mg_setup(lqcd_ctx* c, const lqcd_mg_params& prm, const double* start) {
       LQ_TRY(launch_import_spinor(c, 1, p, start + (size_t)k * vol * 24, V + (size_t)k * fb + (size_t)p * m.hb));
   const dim3 og(m.nagg, 2), ob(agg_block(m));
   if (prm.setup_iters == 0) hipLaunchKernelGGL(k_mg_orth, og, ob, 0, c->stream, m, V, s->B);
+  const dim3 g2(grid1(c->g.vh), 2);
   for (int it = 0; it < prm.setup_iters; ++it) {
-    char *in = s->f32[0], *out = s->f32[1];
+    // one SAP-smoothing step of D v = 0 per vector: v <- v - M_SAP D v
+    char *t = s->f32[0], *u = s->f32[1];
     for (int k = 0; k < m.n; ++k) {
       char* vk = V + (size_t)k * fb;
-      LQ_HIP(hipMemcpyAsync(in, vk, fb, hipMemcpyDeviceToDevice, c->stream));
-      LQ_TRY(sap_apply(c, prm.sap.block, prm.sap.ncycles, prm.sap.nmr, in, in + m.hb, out, out + m.hb));
-      LQ_HIP(hipMemcpyAsync(vk, out, fb, hipMemcpyDeviceToDevice, c->stream));
+      LQ_TRY(op_full(c, 1, vk, vk + m.hb, t, t + m.hb));
+      LQ_TRY(sap_apply(c, prm.sap.block, prm.sap.ncycles, prm.sap.nmr, t, t + m.hb, u, u + m.hb));
+      hipLaunchKernelGGL(k_f32_axpy, g2, dim3(256), 0, c->stream, vk, vk, -1.f, u, m);
     }
     hipLaunchKernelGGL(k_mg_orth, og, ob, 0, c->stream, m, V, s->B);
     hipLaunchKernelGGL(k_mg_to_dp, dim3(grid1(c->g.vh), 2, m.n), dim3(256), 0, c->stream, m, s->B, V);
