@@ -441,7 +441,7 @@ def run_sap(a, torch, lqcd):
 # two-level multigrid on the clover workload; the smoother uses the SAP
 # workload's block shape and MR steps (the same kernel, whose roofline is
 # reported)
-MG = dict(agg=(4, 4, 4, 4), nvec=8, setup_iters=6, sap_block=SAP_BLOCK, ncycles=2, nmr=SAP_NMR, coarse_tol=0.05,
+MG = dict(agg=(4, 4, 4, 4), nvec=8, setup_iters=6, sap_block=SAP_BLOCK, ncycles=4, nmr=SAP_NMR, coarse_tol=0.05,
           coarse_max_iter=200)
 
 
