@@ -143,10 +143,12 @@ def kernel_sources_hash(sources=KERNEL_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec_name, path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
+def measured_traffic(prec_name, path=TRAFFIC_FILE, sources=KERNEL_SOURCES, kernel=None):
     """HBM bytes per launch of a kernel from a committed rocprofv3 counter
     summary (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None
-    when the kernel sources changed since the counters were taken."""
+    when the kernel sources changed since the counters were taken or, with
+    kernel given, when the summary's kernel is another form (the autotuner
+    may pick a different one on another run)."""
     try:
         lines = open(path).read().splitlines()
     except OSError:
@@ -159,6 +161,8 @@ def measured_traffic(prec_name, path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
         return None
     for ln in lines:
         if ln.startswith(prec_name + ":"):
+            if kernel is not None and f"lq::{kernel}<" not in ln and f" {kernel}<" not in ln:
+                return None
             parts = ln.split()
             return int(parts[parts.index("traffic_bytes") + 1])
     return None
@@ -233,7 +237,7 @@ def roofline_of(torch, lat, lqcd, dom, vh):
     shape["nt_links"] = nt
     roof = {"bound": "hbm", "achieved": hop[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": hop[dom]["frac_hbm"],
-            "traffic": measured_traffic(dom) if tuple(lat.dims) == DIMS else None,
+            "traffic": measured_traffic(dom, kernel=kname) if tuple(lat.dims) == DIMS else None,
             "kernel": f"{kname}<{pd},EPI_SCALE> (Dslash, {dom} storage)", "launch_shape": shape,
             "bytes_per_launch": HOP_BYTES[pd] * vh}
     return roof, hop
