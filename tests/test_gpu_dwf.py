@@ -23,8 +23,9 @@ def field5(dims, Ls, seed):
     return (rng.normal(size=shape) + 1j * rng.normal(size=shape)) / np.sqrt(2)
 
 
+# (4, 4, 16, 4): two z planes per XCD slab, as on the benchmarked 64x32x16x8
 @pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 4), ((2, 2, 2, 4), 5), ((4, 6, 8, 10), 3), ((8, 8, 8, 8), 8),
-                                     ((4, 4, 4, 4), 1)])
+                                     ((4, 4, 4, 4), 1), ((4, 4, 16, 4), 8)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("t_bc", [-1, 1])
 @pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5), (1.3, 0.0)])

@@ -66,6 +66,31 @@ def test_restrict_prolong_coarse_apply_match_oracle(n, iters, tol):
     assert dirac.rel_l2(yh, Dc @ e) <= tol
 
 
+def test_full_size_aggregates_match_oracle():
+    """4^4 aggregates (256 sites: four-wave workgroups in the Gram-Schmidt and
+    the restriction, as in the benchmarked configuration)."""
+    dims, adims, sblk, n = (8, 8, 8, 8), (4, 4, 4, 4), (4, 4, 2, 2), 3
+    U = fg.gauge_field(dims, 71, "smooth", 0.3)
+    op = dirac.Operator(U, KAPPA, CSW)
+    start = np.stack([fg.gaussian_spinor(dims, 72 + k) for k in range(n)])
+    lat = lattice(dims, U, KAPPA, CSW)
+    lat.mg_setup(to_dev(start), agg=adims, nvec=n, setup_iters=1, sap_block=sblk, ncycles=1, nmr=2)
+    P = mg.setup(op.D, mg.Aggregates(dims, adims), list(start), sap.Blocks(dims, sblk), 1, 1, 2)
+    nc = lat.mg_coarse_size()
+    assert nc == P.ncoarse == 16 * 2 * n
+    r = fg.gaussian_spinor(dims, 73)
+    rc = to_dev(np.zeros(nc, dtype=np.complex128))
+    lat.mg_restrict(to_dev(r), rc)
+    assert dirac.rel_l2(from_dev(rc), P.restrict(r)) <= 1e-4
+    e = coarse_vec(nc, 74)
+    x = to_dev(np.zeros_like(r))
+    lat.mg_prolong(to_dev(e), x)
+    assert dirac.rel_l2(from_dev(x), P.prolong(e)) <= 1e-4
+    y = to_dev(np.zeros(nc, dtype=np.complex128))
+    lat.mg_coarse_apply(to_dev(e), y)
+    assert dirac.rel_l2(from_dev(y), mg.coarse_operator(op.D, P) @ e) <= 1e-4
+
+
 def test_two_level_preconditioner_matches_oracle():
     U, op, lat, start, kw, P = build(4, 1)
     lat.mg_setup(to_dev(start), coarse_tol=1e-6, coarse_max_iter=2000, **kw)
