@@ -92,6 +92,15 @@ __device__ inline void agg_site(const MgGeom& m, int agg, int l, int c[4], int& 
   i = (int)(full >> 1);
 }
 
+// The aggregate of this workgroup: workgroups are dealt to the 8 XCDs
+// round-robin, so with nagg a multiple of 8 XCD k takes the contiguous range
+// [k nagg/8, (k+1) nagg/8) in order, and aggregates next to each other in x
+// (which share the cache lines of the site-blocked fields) meet in one L2.
+__device__ inline int agg_of_block(const MgGeom& m) {
+  if (m.nagg % 8 != 0) return blockIdx.x;
+  return (blockIdx.x & 7) * (m.nagg >> 3) + (blockIdx.x >> 3);
+}
+
 __device__ inline const char* half_of(const void* f2, int p, size_t hb) {
   return reinterpret_cast<const char*>(f2) + (size_t)p * hb;
 }
@@ -149,7 +158,7 @@ __device__ inline void wg_sum2(double& a, double& b) {
 // two halves) on one aggregate, in the order k = 0 .. n-1, into the basis B
 // (chiral storage). One workgroup per (aggregate, chi), one lane per site.
 __global__ void __launch_bounds__(256) k_mg_orth(MgGeom m, const char* V, char* B) {
-  const int agg = blockIdx.x, chi = blockIdx.y;
+  const int agg = agg_of_block(m), chi = blockIdx.y;
   const bool live = (int)threadIdx.x < m.asz;
   int c[4], p = 0, i = 0;
   if (live) agg_site(m, agg, threadIdx.x, c, p, i);
@@ -308,7 +317,7 @@ __device__ inline void restrict_agg(const MgGeom& m, const char* B, const void* 
 // rc = P^dag r (r: FP32 DP, two halves)
 template <int NC>
 __global__ void __launch_bounds__(256) k_mg_restrict(MgGeom m, const char* B, const void* r2, float2* rc) {
-  const int agg = blockIdx.x;
+  const int agg = agg_of_block(m);
   restrict_agg<NC>(m, B, r2, agg, -1, 0, rc + (size_t)agg * 2 * m.n, 1);
 }
 
@@ -317,7 +326,7 @@ __global__ void __launch_bounds__(256) k_mg_restrict(MgGeom m, const char* B, co
 template <int NC>
 __global__ void __launch_bounds__(256) k_mg_collect(MgGeom m, const char* B, const void* y2, int cls, int col,
                                                     float2* M) {
-  const int agg = blockIdx.x;
+  const int agg = agg_of_block(m);
   const int d = class_of(m, agg) ^ cls;
   const int n2 = 2 * m.n;
   float2* base = M + (size_t)agg * 9 * n2 * n2 + col;
