@@ -27,11 +27,11 @@ SBLK = (4, 2, 2, 4)
 KAPPA, CSW = 0.13, 1.0
 
 
-def build(n, iters, seed=51, ncy=2, nmr=3):
+def build(n, iters, seed=51, ncy=2, nmr=3, csw=CSW):
     U = fg.gauge_field(DIMS, seed, "smooth", 0.3)
-    op = dirac.Operator(U, KAPPA, CSW)
+    op = dirac.Operator(U, KAPPA, csw)
     start = np.stack([fg.gaussian_spinor(DIMS, seed + 1 + k) for k in range(n)])
-    lat = lattice(DIMS, U, KAPPA, CSW)
+    lat = lattice(DIMS, U, KAPPA, csw)
     kw = dict(agg=ADIMS, nvec=n, setup_iters=iters, sap_block=SBLK, ncycles=ncy, nmr=nmr)
     P = mg.setup(op.D, mg.Aggregates(DIMS, ADIMS), list(start), sap.Blocks(DIMS, SBLK), iters, ncy, nmr)
     return U, op, lat, start, kw, P
@@ -103,9 +103,9 @@ def test_two_level_preconditioner_matches_oracle():
     assert dirac.rel_l2(from_dev(x), pre(r)) <= 1e-3
 
 
-@pytest.mark.parametrize("iters", [0, 2])
-def test_solve_mg_matches_oracle(iters):
-    U, op, lat, start, kw, P = build(4, iters)
+@pytest.mark.parametrize("iters,csw", [(0, CSW), (2, CSW), (2, 0.0)])
+def test_solve_mg_matches_oracle(iters, csw):
+    U, op, lat, start, kw, P = build(4, iters, csw=csw)
     lat.mg_setup(to_dev(start), **kw)
     b = fg.gaussian_spinor(DIMS, 63)
     x = to_dev(np.zeros_like(b))
