@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size (32^3 x 64), in the launch configuration
 bench.py times (autotuned shapes): outputs at sampled sites are compared with
-the oracle evaluated site by site (oracle.sampled), and solves are judged by
+the oracle evaluated site by site (oracle.sampled), and solves are checked by
 their true residual. Sites include the time boundary (antiperiodic hops) and
 both ends of every direction.
 """

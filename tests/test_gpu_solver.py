@@ -1,4 +1,4 @@
-"""GPU solvers, judged by the oracle: the returned x must satisfy
+"""GPU solvers, checked against the oracle: the returned x must satisfy
 ||b - D x|| / ||b|| <= 1e-10 with the oracle's FP64 operator, for the plain
 FP64 BiCGStab and for the FP32 and FP16 inner solvers inside the FP64 outer
 loop. Solutions are also compared with LAPACK's dense solve on a tiny lattice.
