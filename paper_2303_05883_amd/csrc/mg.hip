@@ -372,37 +372,48 @@ __global__ void __launch_bounds__(256) k_mg_prolong(MgGeom m, const char* B, con
 }
 
 // ------------------------------------------------------------------ coarse operator
-// y = D_c x: one lane per (aggregate, row)
+// y = D_c x: four lanes per (aggregate, row), lane j of the four taking the
+// stencil blocks j, j + 4 and j + 8, their sums added by lane exchanges (the
+// coarse lattice is small: this quadruples the waves in flight)
 __global__ void __launch_bounds__(256) k_mg_capply(MgGeom m, const float2* M, const float2* x, float2* y) {
   const int n2 = 2 * m.n;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (size_t)m.nagg * n2) return;
-  const int agg = (int)(q / n2), row = (int)(q % n2);
-  int ac[4];
-  int r = agg;
-  for (int d = 0; d < 3; ++d) {
-    ac[d] = r % m.na[d];
-    r /= m.na[d];
-  }
-  ac[3] = r;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t q = t >> 2;
+  const int sub = (int)(t & 3);
+  const bool live = q < (size_t)m.nagg * n2;
   float re = 0.f, im = 0.f;
-  for (int dir = 0; dir < 9; ++dir) {
-    int nb = agg;
-    if (dir > 0) {
-      const int mu = (dir - 1) >> 1, s = (dir & 1) ? 1 : -1;
-      int cc[4] = {ac[0], ac[1], ac[2], ac[3]};
-      cc[mu] = (cc[mu] + s + m.na[mu]) % m.na[mu];
-      nb = cc[0] + m.na[0] * (cc[1] + m.na[1] * (cc[2] + m.na[2] * cc[3]));
+  if (live) {
+    const int agg = (int)(q / n2), row = (int)(q % n2);
+    int ac[4];
+    int r = agg;
+    for (int d = 0; d < 3; ++d) {
+      ac[d] = r % m.na[d];
+      r /= m.na[d];
     }
-    const float2* Mr = M + (((size_t)agg * 9 + dir) * n2 + row) * n2;
-    const float2* xv = x + (size_t)nb * n2;
-    for (int c = 0; c < n2; ++c) {
-      const float2 a = Mr[c], b = xv[c];
-      re += a.x * b.x - a.y * b.y;
-      im += a.x * b.y + a.y * b.x;
+    ac[3] = r;
+    for (int dir = sub; dir < 9; dir += 4) {
+      int nb = agg;
+      if (dir > 0) {
+        const int mu = (dir - 1) >> 1, sg = (dir & 1) ? 1 : -1;
+        int cc[4] = {ac[0], ac[1], ac[2], ac[3]};
+        cc[mu] = (cc[mu] + sg + m.na[mu]) % m.na[mu];
+        nb = cc[0] + m.na[0] * (cc[1] + m.na[1] * (cc[2] + m.na[2] * cc[3]));
+      }
+      // n2 is even: rows and vectors start on 16-byte boundaries, two entries per load
+      const float4* Mr = reinterpret_cast<const float4*>(M + (((size_t)agg * 9 + dir) * n2 + row) * n2);
+      const float4* xv = reinterpret_cast<const float4*>(x + (size_t)nb * n2);
+      for (int c = 0; c < n2 / 2; ++c) {
+        const float4 a = Mr[c], b = xv[c];
+        re += a.x * b.x - a.y * b.y + a.z * b.z - a.w * b.w;
+        im += a.x * b.y + a.y * b.x + a.z * b.w + a.w * b.z;
+      }
     }
   }
-  y[q] = make_float2(re, im);
+  re += __shfl_xor(re, 1, 64);
+  im += __shfl_xor(im, 1, 64);
+  re += __shfl_xor(re, 2, 64);
+  im += __shfl_xor(im, 2, 64);
+  if (live && sub == 0) y[q] = make_float2(re, im);
 }
 
 // coarse vectors: out = ca a + cb b + cc c (b, c may be null)
@@ -516,7 +527,7 @@ int prolong_to(lqcd_ctx* c, MgState& s, const float2* e, void* x2) {
 }
 
 int capply(lqcd_ctx* c, MgState& s, const float2* x, float2* y) {
-  hipLaunchKernelGGL(k_mg_capply, dim3(grid1(s.nc())), dim3(256), 0, c->stream, s.m, s.M, x, y);
+  hipLaunchKernelGGL(k_mg_capply, dim3(grid1(4 * s.nc())), dim3(256), 0, c->stream, s.m, s.M, x, y);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }
