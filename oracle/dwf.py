@@ -19,6 +19,10 @@ i.e. D_W is the 4-d Wilson operator with mass -M5 on every slice, applied to
 (b5 + c5 S) psi. b5 = 1, c5 = 0 gives the Shamir operator
 (5 - M5) psi_s - 1/2 H psi_s - (S psi)_s. D is not positive definite (its
 Wilson kernel has mass -M5), so the solver is CG on the normal equations.
+
+The paper implements the even-odd forms of every operator (Sec. 2, Eq. (1));
+``EvenOdd`` is the even-odd Schur complement of D over the 4-d parity of the
+sites, with its adjoint and solve.
 """
 
 from __future__ import annotations
@@ -90,3 +94,89 @@ class DomainWall:
 def solve(op: DomainWall, b: np.ndarray, tol: float = 1e-10):
     """D x = b through the normal equations D^dag D x = D^dag b and CG."""
     return solvers.cg(op.normal, op.Ddag(b), tol=tol)
+
+
+# ---------------------------------------------------------------- even-odd form
+# With the 4-d parity of the sites (s does not enter it), D splits into the
+# site-local part M5op = (4 - M5)(b5 + c5 S) + 1 - S, which acts on s and spin
+# only, and the hopping part Dhop = -1/2 H (b5 + c5 S), which couples the two
+# parities. The even-odd Schur complement on the even sites is
+#   S_ee = M5op - Dhop_eo M5op^-1 Dhop_oe,
+# D x = b is S_ee x_e = b_e - Dhop_eo M5op^-1 b_o, x_o = M5op^-1 (b_o - Dhop_oe x_e).
+
+def parity5(op: DomainWall, psi: np.ndarray, parity: int) -> np.ndarray:
+    par = dirac.parity_field(dirac.dims_of(op.U))[None, ..., None, None]
+    return np.where(par == parity, psi, 0)
+
+
+def m5op(op: DomainWall, psi):
+    return (4.0 - op.M5) * (op.b5 * psi + op.c5 * op.S(psi)) + psi - op.S(psi)
+
+
+def m5op_dag(op: DomainWall, psi):
+    return (4.0 - op.M5) * (op.b5 * psi + op.c5 * op.Sdag(psi)) + psi - op.Sdag(psi)
+
+
+def dhop(op: DomainWall, psi):
+    return np.stack([-0.5 * dirac.hop(op.U, v, op.t_bc) for v in op.b5 * psi + op.c5 * op.S(psi)])
+
+
+def dhop_dag(op: DomainWall, psi):
+    h = np.stack([-0.5 * op._hd.hop_dag(v) for v in psi])
+    return op.b5 * h + op.c5 * op.Sdag(h)
+
+
+def local_matrix(op: DomainWall, fn) -> np.ndarray:
+    """The (Ls 4) x (Ls 4) matrix over (s, spin) of a site-local map fn (the
+    same at every site and colour), from its action on unit vectors."""
+    Ls = op.Ls
+    cols = []
+    for s in range(Ls):
+        for a in range(4):
+            e = np.zeros((Ls, 1, 1, 1, 1, 4, 3), dtype=np.complex128)
+            e[s, 0, 0, 0, 0, a, 0] = 1.0
+            cols.append(fn(e)[:, 0, 0, 0, 0, :, 0].reshape(-1))
+    return np.array(cols).T
+
+
+def apply_local(K: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    Ls = psi.shape[0]
+    Kr = K.reshape(Ls, 4, Ls, 4)
+    return np.einsum("sarb,rtzyxbc->stzyxac", Kr, psi)
+
+
+class EvenOdd:
+    def __init__(self, op: DomainWall):
+        self.op = op
+        # M5op does not involve the links: its matrix is built on one site
+        self.Kinv = np.linalg.inv(local_matrix(op, lambda e: m5op(op, e)))
+
+    def m5inv(self, psi):
+        return apply_local(self.Kinv, psi)
+
+    def m5inv_dag(self, psi):
+        return apply_local(self.Kinv.conj().T, psi)
+
+    def schur(self, xe):
+        op = self.op
+        xe = parity5(op, xe, 0)
+        t = parity5(op, dhop(op, xe), 1)
+        t = parity5(op, dhop(op, self.m5inv(t)), 0)
+        return m5op(op, xe) - t
+
+    def schur_dag(self, xe):
+        op = self.op
+        xe = parity5(op, xe, 0)
+        t = parity5(op, dhop_dag(op, xe), 1)
+        t = parity5(op, dhop_dag(op, self.m5inv_dag(t)), 0)
+        return m5op_dag(op, xe) - t
+
+    def solve(self, b, tol: float = 1e-10):
+        """D x = b through the even-odd Schur complement and CG on its normal
+        equations, then the odd sites."""
+        op = self.op
+        be, bo = parity5(op, b, 0), parity5(op, b, 1)
+        bp = be - parity5(op, dhop(op, self.m5inv(bo)), 0)
+        xe, info = solvers.cg(lambda v: self.schur_dag(self.schur(v)), self.schur_dag(bp), tol=0.1 * tol)
+        xo = self.m5inv(bo - parity5(op, dhop(op, xe), 1))
+        return parity5(op, xe, 0) + parity5(op, xo, 1), info

@@ -199,3 +199,40 @@ def test_adjoint_and_normal_solve_match_lapack(b5, c5):
     want = np.linalg.solve(dense_dwf(U, 1.8, 0.1, Ls, -1, b5, c5), vec5(b))
     assert np.linalg.norm(vec5(x) - want) <= 1e-8 * np.linalg.norm(want)
     assert np.linalg.norm(vec5(b - op.D(x))) <= 1e-10 * np.linalg.norm(vec5(b))
+
+
+def parity_index(dims, Ls, parity):
+    """vec5 indices of the components on 4-d sites of one parity."""
+    par = dirac.parity_field(dims)  # [t, z, y, x]
+    per_site = np.repeat((par == parity).reshape(-1), 12)
+    n4 = per_site.size
+    return np.concatenate([s * n4 + np.nonzero(per_site)[0] for s in range(Ls)])
+
+
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_even_odd_schur_is_dense_schur_complement(b5, c5):
+    dims, Ls = (2, 2, 2, 4), 4
+    U = fg.gauge_field(dims, 105, "haar")
+    op = dwf.DomainWall(U, 1.8, 0.07, Ls, -1, b5, c5)
+    eo = dwf.EvenOdd(op)
+    D = dense_dwf(U, 1.8, 0.07, Ls, -1, b5, c5)
+    e, o = parity_index(dims, Ls, 0), parity_index(dims, Ls, 1)
+    S = D[np.ix_(e, e)] - D[np.ix_(e, o)] @ np.linalg.solve(D[np.ix_(o, o)], D[np.ix_(o, e)])
+    psi = dwf.parity5(op, field5(dims, Ls, 106), 0)
+    got = vec5(eo.schur(psi))
+    assert np.abs(got[e] - S @ vec5(psi)[e]).max() <= 1e-12
+    assert np.abs(got[o]).max() == 0.0
+    got = vec5(eo.schur_dag(psi))
+    assert np.abs(got[e] - S.conj().T @ vec5(psi)[e]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_even_odd_solve_matches_lapack(b5, c5):
+    dims, Ls = (2, 2, 2, 4), 4
+    U = fg.gauge_field(dims, 107, "smooth", 0.3)
+    op = dwf.DomainWall(U, 1.8, 0.1, Ls, -1, b5, c5)
+    b = field5(dims, Ls, 108)
+    x, info = dwf.EvenOdd(op).solve(b, tol=1e-12)
+    assert info.converged
+    want = np.linalg.solve(dense_dwf(U, 1.8, 0.1, Ls, -1, b5, c5), vec5(b))
+    assert np.linalg.norm(vec5(x) - want) <= 1e-9 * np.linalg.norm(want)
