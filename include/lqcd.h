@@ -305,6 +305,22 @@ int lqcd_dwf_apply(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec,
 int lqcd_dwf_solve(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, const double* b, double* x,
                    const lqcd_solve_params* prm, lqcd_solve_stats* stats);
 
+/* Even-odd form over the 4-d parity of the sites (the paper's even-odd
+ * decomposition, Sec. 2, Eq. (1)): D = M5op + Dhop with the site-local
+ * M5op = (4 - M5)(b5 + c5 S) + 1 - S and Dhop = -1/2 H (b5 + c5 S).
+ * out = S_ee in (dag 0) or S_ee^dag in (dag 1) with
+ * S_ee = M5op - Dhop_eo M5op^-1 Dhop_oe on the even sites of canonical 5-d
+ * fields (host or device); the odd sites of in are ignored and those of out
+ * are set to zero. ESINGULAR if M5op is singular; otherwise as lqcd_dwf_apply. */
+int lqcd_dwf_apply_schur(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const double* in, double* out,
+                         int on_device);
+/* Solve D x = b through S_ee x_e = b_e - Dhop_eo M5op^-1 b_o, solved by FP64 CG
+ * on its normal equations, and x_o = M5op^-1 (b_o - Dhop_oe x_e), restarted
+ * from the true residual until ||b - D x|| / ||b|| <= prm->tol. Parameters
+ * and stats as lqcd_dwf_solve. */
+int lqcd_dwf_solve_eo(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, const double* b, double* x,
+                      const lqcd_solve_params* prm, lqcd_solve_stats* stats);
+
 /* Native domain-wall fields (benchmarks), on the device: the fifth coordinate
  * is the fastest index of a site (5-d index i Ls + s, i the 4-d checkerboard
  * index of the library's spinor layout), two parity halves in the

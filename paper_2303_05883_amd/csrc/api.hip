@@ -613,6 +613,71 @@ int lqcd_dwf_solve(lqcd_ctx* c, const lqcd_dwf_params* d, const double* b, doubl
   return status;
 }
 
+int lqcd_dwf_apply_schur(lqcd_ctx* c, const lqcd_dwf_params* d, int dag, int prec, const double* in, double* out,
+                         int on_device) {
+  if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_dwf(d));
+  if (prec != 0 && prec != 1) return set_error(LQCD_EINVAL, "domain-wall operator: precision must be F64 or F32");
+  if (dag != 0 && dag != 1) return set_error(LQCD_EINVAL, "dag must be 0 or 1");
+  if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
+  const size_t cbytes = full_sites(c) * 192 * (size_t)d->Ls;
+  const size_t fb = dwf_field_bytes(prec, c->g.vh, d->Ls);
+  Bufs b;
+  void *cin = nullptr, *cout = nullptr, *f[4];
+  const double* din = in;
+  double* dout = out;
+  if (!on_device) {
+    LQ_TRY(b.get(c, cbytes, &cin));
+    LQ_TRY(b.get(c, cbytes, &cout));
+    LQ_HIP(hipMemcpyAsync(cin, in, cbytes, hipMemcpyHostToDevice, c->stream));
+    din = reinterpret_cast<const double*>(cin);
+    dout = reinterpret_cast<double*>(cout);
+  }
+  for (auto& q : f) LQ_TRY(b.get(c, fb, &q));  // zeroed: the odd half of the result stays zero
+  LQ_TRY(dwf_import(c, prec, d->Ls, din, f[0]));
+  LQ_TRY(dwf_schur_apply(c, prec, *d, dag, f[0], f[1], f[2], f[3]));
+  LQ_TRY(dwf_export(c, prec, d->Ls, f[1], dout));
+  if (!on_device) LQ_HIP(hipMemcpyAsync(out, dout, cbytes, hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  return LQCD_OK;
+}
+
+int lqcd_dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params* d, const double* b, double* x,
+                      const lqcd_solve_params* prm_in, lqcd_solve_stats* stats) {
+  if (!c || !b || !x) return set_error(LQCD_EINVAL, "null argument");
+  LQ_TRY(validate_dwf(d));
+  LQ_TRY(validate_params(prm_in));
+  lqcd_solve_params prm;
+  if (prm_in) prm = *prm_in;
+  else lqcd_default_params(&prm);
+  if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
+  const size_t cbytes = full_sites(c) * 192 * (size_t)d->Ls;
+  const size_t fb = dwf_field_bytes(0, c->g.vh, d->Ls);
+  Bufs bf;
+  void *cb = nullptr, *cx_ = nullptr, *fbn, *fx;
+  const double* db = b;
+  double* dx = x;
+  if (!prm.on_device) {
+    LQ_TRY(bf.get(c, cbytes, &cb));
+    LQ_TRY(bf.get(c, cbytes, &cx_));
+    LQ_HIP(hipMemcpyAsync(cb, b, cbytes, hipMemcpyHostToDevice, c->stream));
+    db = reinterpret_cast<const double*>(cb);
+    dx = reinterpret_cast<double*>(cx_);
+  }
+  LQ_TRY(check_finite(c, db, full_sites(c) * 24 * (size_t)d->Ls));
+  LQ_TRY(bf.get(c, fb, &fbn));
+  LQ_TRY(bf.get(c, fb, &fx));
+  LQ_TRY(dwf_import(c, 0, d->Ls, db, fbn));
+  lqcd_solve_stats st{};
+  const int status = dwf_solve_eo(c, *d, prm, fbn, fx, st);
+  if (status != LQCD_OK && status != LQCD_ENOCONV && status != LQCD_EBREAKDOWN) return status;
+  LQ_TRY(dwf_export(c, 0, d->Ls, fx, dx));
+  if (!prm.on_device) LQ_HIP(hipMemcpyAsync(x, dx, cbytes, hipMemcpyDeviceToHost, c->stream));
+  LQ_HIP(hipStreamSynchronize(c->stream));
+  if (stats) *stats = st;
+  return status;
+}
+
 size_t lqcd_dwf_field_bytes(lqcd_ctx* c, int prec, int Ls) {
   if (!c || (prec != 0 && prec != 1) || Ls < 1 || Ls > 256) return 0;
   return dwf_field_bytes(prec, c->g.vh, Ls);

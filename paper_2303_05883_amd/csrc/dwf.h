@@ -14,6 +14,15 @@ int dwf_export(lqcd_ctx* c, int prec, int Ls, const void* f5, double* canon);
 // out = D in (dag 0) or D^dag in (dag 1); in != out; 1 <= Ls <= 256; tmp: a
 // third 5-d field, needed (phi) by D with c5 != 0 only
 int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tmp);
+// Even-odd form (4-d parity): out_e = S_ee in_e (dag 0) or S_ee^dag in_e (dag
+// 1), S_ee = M5op - Dhop_eo M5op^-1 Dhop_oe; only the even halves of in and
+// out are used; tA, tB: scratch 5-d fields
+int dwf_schur_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tA,
+                    void* tB);
+// D x = b (FP64 native 5-d fields) through S_ee and CG on its normal
+// equations, x_o rebuilt, stopping on the true residual of D
+int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& prm, const void* b, void* x,
+                 lqcd_solve_stats& st);
 // D x = b (FP64 native 5-d fields, padding zero) by CG on D^dag D x = D^dag b
 int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& prm, const void* b, void* x,
               lqcd_solve_stats& st);

@@ -263,6 +263,77 @@ __global__ void __launch_bounds__(DWB) k_dwf_phi(DwfArgs a) {
   IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, v);
 }
 
+// ---------------------------------------------------------------- even-odd form
+// D = M5op + Dhop with the site-local M5op = (4 - M5)(b5 + c5 S) + 1 - S and
+// Dhop = -1/2 H (b5 + c5 S). Every site-local operator here has the form
+// A_+ (x) P_+ + A_- (x) P_-, A_+- real Ls x Ls matrices over s (S: A_+ the
+// lower shift with -m_f in the corner, A_- the upper shift with -m_f in the
+// corner; adjoints are transposes).
+
+// out_s = sum_s' (A_+ P_+ x + A_- P_- x)_s' [+ (C_+ P_+ y + C_- P_- y)_s'] on the
+// parity-p half of 5-d fields; mats = {A_+, A_-, C_+, C_-}, each Ls x Ls row-major
+template <int P>
+__global__ void __launch_bounds__(DWB) k_dwf_sop(DwfArgs a, int p, const char* x5, const char* y5,
+                                                 const double* mats) {
+  using T = typename IO<P>::T;
+  __shared__ cx<T> lp[6][DWB], lm[6][DWB];
+  const int Ls = a.Ls;
+  size_t j = 0;
+  const bool live = dwf_site(a, j);
+  const int s = live ? (int)(j % (size_t)Ls) : 0;
+  const int base = (int)threadIdx.x - s;
+  cx<T> o[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o[k] = {T(0), T(0)};
+  for (int pass = 0; pass < 2; ++pass) {
+    const char* f = pass == 0 ? x5 : y5;
+    if (!f) break;
+    const double* Ap = mats + (size_t)(2 * pass) * Ls * Ls + (size_t)s * Ls;
+    const double* Am = Ap + (size_t)Ls * Ls;
+    cx<T> v[12];
+    if (live) {
+      IO<P>::load_spinor(f + (size_t)p * a.hb, j, v);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = {T(0), T(0)};
+    }
+    if (pass == 1) __syncthreads();  // the x pass has read its halves
+    put_halves(lp, lm, v);
+    __syncthreads();
+    if (live) {
+      for (int t = 0; t < Ls; ++t) {
+        const T cp = (T)Ap[t], cm = (T)Am[t];
+        if (cp == T(0) && cm == T(0)) continue;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const cx<T> up = cp * lp[k][base + t], um = cm * lm[k][base + t];
+          o[k] = o[k] + up + um;
+          o[6 + k] = o[6 + k] - up + um;
+        }
+      }
+    }
+  }
+  if (live) IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, o);
+}
+
+// out = scale H in (DAG: scale gamma5 H gamma5 in) on the parity-p half, from
+// the other half of in
+template <int P, bool DAG>
+__global__ void __launch_bounds__(DWB) k_dwf_hop1(DwfArgs a, int p, double scale) {
+  using T = typename IO<P>::T;
+  size_t j = 0;
+  if (!dwf_site(a, j)) return;
+  const int i = (int)(j / a.Ls), s = (int)(j - (size_t)i * a.Ls);
+  cx<T> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+  dwf_hop<P, DAG>(a, a.in, p, i, s, acc);
+  const T sc = (T)scale;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
+  IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, acc);
+}
+
 // canonical [s][t][z][y][x][spin][colour] complex128 <-> native 5-d field
 template <int P>
 __global__ void __launch_bounds__(256) k_dwf_import(Geom g, int Ls, size_t hb, const double* canon, char* f5) {
@@ -520,6 +591,292 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
       rr = rn;
     }
     // the next pass iterates on the recomputed residual to a tighter normal target if needed
+    target *= 0.5;
+  }
+  st.outer_iters = passes;
+  st.inner_iters = iters;
+  st.restarts = passes > 0 ? passes - 1 : 0;
+  st.true_rel_resid = true_rel;
+  st.seconds_solve = std::chrono::duration<double>(clk::now() - ts).count();
+  return status;
+}
+
+// ---------------------------------------------------------------- even-odd host side
+namespace {
+
+// pairs (A_+, A_-) of real Ls x Ls matrices, in this order in the device buffer
+enum EoPair { EP_B, EP_BMINV, EP_M5, EP_MINUS_I, EP_BMINV_T, EP_M5_T, EP_MINUS_B_T, EP_MINV, EP_MINUS_MINV, EP_I,
+              EP_MINUS_I2, EP_COUNT };
+
+using Mat = std::vector<double>;
+
+Mat matmul(const Mat& a, const Mat& b, int n) {
+  Mat c((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j) c[(size_t)i * n + j] += a[(size_t)i * n + k] * b[(size_t)k * n + j];
+  return c;
+}
+
+Mat transpose(const Mat& a, int n) {
+  Mat t((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) t[(size_t)j * n + i] = a[(size_t)i * n + j];
+  return t;
+}
+
+// Gauss-Jordan with partial pivoting; false if singular
+bool invert(Mat a, int n, Mat& inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + col]) > std::fabs(a[(size_t)piv * n + col])) piv = r;
+    const double pv = a[(size_t)piv * n + col];
+    if (!(std::fabs(pv) > 1e-300)) return false;
+    if (piv != col)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[(size_t)piv * n + j], a[(size_t)col * n + j]);
+        std::swap(inv[(size_t)piv * n + j], inv[(size_t)col * n + j]);
+      }
+    const double ip = 1.0 / a[(size_t)col * n + col];
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)col * n + j] *= ip;
+      inv[(size_t)col * n + j] *= ip;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = a[(size_t)r * n + col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)r * n + j] -= f * a[(size_t)col * n + j];
+        inv[(size_t)r * n + j] -= f * inv[(size_t)col * n + j];
+      }
+    }
+  }
+  return true;
+}
+
+// the pairs of the even-odd operators, for chirality + (h = 0) and - (h = 1)
+int eo_matrices(const lqcd_dwf_params& d, std::vector<double>& out) {
+  const int n = d.Ls;
+  const size_t nn = (size_t)n * n;
+  out.assign((size_t)EP_COUNT * 2 * nn, 0.0);
+  for (int h = 0; h < 2; ++h) {
+    Mat S(nn, 0.0), I(nn, 0.0);
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    for (int i = 0; i < n; ++i) {
+      if (h == 0) {  // P_+ psi_{s-1}, wall -m_f psi_{Ls-1} at s = 0
+        if (i > 0) S[(size_t)i * n + i - 1] += 1.0;
+        else S[(size_t)i * n + n - 1] += -d.mf;
+      } else {       // P_- psi_{s+1}, wall -m_f psi_0 at s = Ls-1
+        if (i + 1 < n) S[(size_t)i * n + i + 1] += 1.0;
+        else S[(size_t)i * n] += -d.mf;
+      }
+    }
+    Mat B(nn), M(nn), Minv;
+    for (size_t k = 0; k < nn; ++k) {
+      B[k] = d.b5 * I[k] + d.c5 * S[k];
+      M[k] = (4.0 - d.M5) * B[k] + I[k] - S[k];
+    }
+    if (!invert(M, n, Minv)) return set_error(LQCD_ESINGULAR, "domain-wall even-odd: the site-local part is singular");
+    const Mat BM = matmul(B, Minv, n);
+    const Mat set[EP_COUNT] = {B, BM, M, I, transpose(BM, n), transpose(M, n), transpose(B, n), Minv, Minv, I, I};
+    const double sign[EP_COUNT] = {1, 1, 1, -1, 1, 1, -1, 1, -1, 1, -1};
+    for (int e = 0; e < EP_COUNT; ++e)
+      for (size_t k = 0; k < nn; ++k) out[((size_t)e * 2 + h) * nn + k] = sign[e] * set[e][k];
+  }
+  return LQCD_OK;
+}
+
+struct EoCtx {
+  lqcd_ctx* c;
+  int prec;
+  lqcd_dwf_params d;
+  DwfArgs a;
+  dim3 grid, block;
+  const double* mats;
+  const double* pair(int e) const { return mats + (size_t)e * 2 * d.Ls * d.Ls; }
+
+  int sop(int p, const void* x, const void* y, int e, void* out) const {
+    DwfArgs b = a;
+    b.out = reinterpret_cast<char*>(out);
+    const char* xs = reinterpret_cast<const char*>(x);
+    const char* ys = reinterpret_cast<const char*>(y);
+    if (prec == 0) hipLaunchKernelGGL(k_dwf_sop<0>, grid, block, 0, c->stream, b, p, xs, ys, pair(e));
+    else hipLaunchKernelGGL(k_dwf_sop<1>, grid, block, 0, c->stream, b, p, xs, ys, pair(e));
+    LQ_HIP(hipGetLastError());
+    return LQCD_OK;
+  }
+  int hop(int p, const void* in, void* out, bool dag) const {
+    DwfArgs b = a;
+    b.in = reinterpret_cast<const char*>(in);
+    b.out = reinterpret_cast<char*>(out);
+    if (prec == 0) {
+      if (dag) hipLaunchKernelGGL((k_dwf_hop1<0, true>), grid, block, 0, c->stream, b, p, -0.5);
+      else hipLaunchKernelGGL((k_dwf_hop1<0, false>), grid, block, 0, c->stream, b, p, -0.5);
+    } else {
+      if (dag) hipLaunchKernelGGL((k_dwf_hop1<1, true>), grid, block, 0, c->stream, b, p, -0.5);
+      else hipLaunchKernelGGL((k_dwf_hop1<1, false>), grid, block, 0, c->stream, b, p, -0.5);
+    }
+    LQ_HIP(hipGetLastError());
+    return LQCD_OK;
+  }
+  // out_e = S_ee x_e (dag 0) or S_ee^dag x_e (dag 1); tA, tB: scratch 5-d fields
+  int schur(int dag, const void* x, void* out, void* tA, void* tB) const {
+    if (!dag) {
+      LQ_TRY(sop(0, x, nullptr, EP_B, tA));           // B x
+      LQ_TRY(hop(1, tA, tB, false));                  // Dhop_oe x
+      LQ_TRY(sop(1, tB, nullptr, EP_BMINV, tA));      // B M5^-1 ...
+      LQ_TRY(hop(0, tA, tB, false));                  // Dhop_eo M5^-1 Dhop_oe x
+      return sop(0, x, tB, EP_M5, out);               // M5 x - that
+    }
+    LQ_TRY(hop(1, x, tA, true));                      // -1/2 H^dag_oe x
+    LQ_TRY(sop(1, tA, nullptr, EP_BMINV_T, tB));      // M5^-dag B^dag ...
+    LQ_TRY(hop(0, tB, tA, true));                     // -1/2 H^dag_eo ...
+    return sop(0, x, tA, EP_M5_T, out);               // M5^dag x - B^dag that
+  }
+};
+
+int eo_setup(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, const double* mats, EoCtx& e) {
+  if (!c->gauge[prec]) return set_error(LQCD_ESTATE, "gauge field not set");
+  if (d.Ls < 1 || d.Ls > DWB) return set_error(LQCD_EINVAL, "domain-wall operator: Ls must be in [1, 256]");
+  if (prec != 0 && prec != 1) return set_error(LQCD_EINVAL, "domain-wall operator: precision must be F64 or F32");
+  e.c = c;
+  e.prec = prec;
+  e.d = d;
+  e.mats = mats;
+  DwfArgs& a = e.a;
+  a = DwfArgs{};
+  a.gauge = reinterpret_cast<const char*>(c->gauge[prec]);
+  a.link_stride = link_bytes(prec, c->g.vh);
+  a.g = c->g;
+  a.hb = half_bytes(prec, c->g.vh, d.Ls);
+  a.Ls = d.Ls;
+  a.spb = (DWB / d.Ls) * d.Ls;
+  a.hz = c->g.lz % 8 == 0 ? c->g.lz / 8 : 0;
+  a.d4 = 4.0 - d.M5;
+  a.b5 = d.b5;
+  a.c5 = d.c5;
+  a.mf = d.mf;
+  const size_t n = (size_t)c->g.vh * d.Ls;
+  e.grid = dim3(a.hz ? 8u * (unsigned)((n / 8 + a.spb - 1) / a.spb) : (unsigned)((n + a.spb - 1) / a.spb));
+  e.block = dim3((a.spb + 63) / 64 * 64);
+  return LQCD_OK;
+}
+
+struct DevMats {
+  double* p = nullptr;
+  ~DevMats() { (void)hipFree(p); }
+  int upload(lqcd_ctx* c, const lqcd_dwf_params& d) {
+    std::vector<double> h;
+    LQ_TRY(eo_matrices(d, h));
+    if (hipMalloc(reinterpret_cast<void**>(&p), h.size() * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(LQCD_ENOMEM, "domain-wall even-odd matrices");
+    }
+    LQ_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    LQ_HIP(hipStreamSynchronize(c->stream));
+    return LQCD_OK;
+  }
+};
+
+}  // namespace
+
+int dwf_schur_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tA,
+                    void* tB) {
+  DevMats m;
+  LQ_TRY(m.upload(c, d));
+  EoCtx e;
+  LQ_TRY(eo_setup(c, prec, d, m.p, e));
+  LQ_TRY(e.schur(dag, in, out, tA, tB));
+  LQ_HIP(hipStreamSynchronize(c->stream));  // m is freed on return
+  return LQCD_OK;
+}
+
+int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& prm, const void* b, void* x,
+                 lqcd_solve_stats& st) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  DevMats m;
+  LQ_TRY(m.upload(c, d));
+  EoCtx e;
+  LQ_TRY(eo_setup(c, 0, d, m.p, e));
+  DWork w;
+  const size_t bytes = dwf_field_bytes(0, c->g.vh, d.Ls);
+  const size_t nh = padded_sites((size_t)c->g.vh * d.Ls), nf = 2 * nh;
+  void *bp, *r, *pv, *q, *sx, *tA, *tB, *res;
+  for (void** f : {&bp, &r, &pv, &q, &sx, &tA, &tB, &res}) LQ_TRY(w.alloc(c, bytes, f));
+  LQ_HIP(hipMalloc(&w.partials, (size_t)((nf + 255) / 256) * 2 * sizeof(double)));
+  auto ev = [](void* f) { return f; };  // even half = start of the field
+  double bb = 0.0;
+  LQ_TRY(dot(c, w, nf, b, b, nullptr, &bb));
+  const double bnorm = std::sqrt(bb);
+  st = lqcd_solve_stats{};
+  const auto ts = clk::now();
+  st.seconds_setup = std::chrono::duration<double>(ts - t0).count();
+  LQ_HIP(hipMemsetAsync(x, 0, bytes, c->stream));
+  if (bnorm == 0.0) return LQCD_OK;
+  // b' = b_e - Dhop_eo M5^-1 b_o
+  LQ_TRY(e.sop(1, b, nullptr, EP_BMINV, tA));
+  LQ_TRY(e.hop(0, tA, tB, false));
+  LQ_TRY(e.sop(0, b, tB, EP_I, bp));
+  LQ_TRY(e.schur(1, bp, sx, tA, tB));  // S^dag b'
+  double sbb = 0.0;
+  LQ_TRY(dot(c, w, nh, ev(sx), ev(sx), nullptr, &sbb));
+  int iters = 0, passes = 0, status = LQCD_OK;
+  double true_rel = 1.0, target = 0.1 * prm.tol * std::sqrt(sbb);
+  auto normal = [&](void* in, void* out) -> int {  // out_e = S^dag S in_e
+    LQ_TRY(e.schur(0, in, sx, tA, tB));
+    return e.schur(1, sx, out, tA, tB);
+  };
+  for (;;) {
+    // x_o from x_e, then the true residual with the full operator
+    LQ_TRY(e.sop(0, x, nullptr, EP_B, tA));
+    LQ_TRY(e.hop(1, tA, tB, false));
+    LQ_TRY(e.sop(1, b, tB, EP_MINV, x));
+    LQ_TRY(dwf_apply(c, 0, d, 0, x, q, tA));
+    LQ_TRY(axpy(c, nf, res, b, q, -1.0));
+    double tt = 0.0;
+    LQ_TRY(dot(c, w, nf, res, res, nullptr, &tt));
+    true_rel = std::sqrt(tt) / bnorm;
+    if (log_level() >= 1)
+      std::fprintf(stderr, "[lqcd] domain-wall even-odd CG pass %d: %d iterations, |b - D x|/|b| %.3e\n", passes, iters,
+                   true_rel);
+    if (true_rel <= prm.tol) break;
+    if (!(true_rel == true_rel)) {
+      status = set_error(LQCD_EBREAKDOWN, "domain-wall even-odd CG produced NaN");
+      break;
+    }
+    if (iters >= prm.max_iter || passes >= prm.max_outer) {
+      status = set_error(LQCD_ENOCONV, "domain-wall even-odd CG did not reach the tolerance");
+      break;
+    }
+    ++passes;
+    // r = S^dag (b' - S x_e) on the even half
+    LQ_TRY(e.schur(0, x, q, tA, tB));
+    LQ_TRY(axpy(c, nh, ev(res), ev(bp), ev(q), -1.0));
+    LQ_TRY(e.schur(1, res, r, tA, tB));
+    double rr = 0.0;
+    LQ_TRY(dot(c, w, nh, ev(r), ev(r), nullptr, &rr));
+    LQ_TRY(axpy(c, nh, ev(pv), ev(r), ev(r), 0.0));
+    const double tgt = std::min(target, 0.5 * std::sqrt(rr));
+    while (iters < prm.max_iter) {
+      LQ_TRY(normal(pv, q));
+      double pq = 0.0;
+      LQ_TRY(dot(c, w, nh, ev(pv), ev(q), &pq, nullptr));
+      if (!(pq > 0.0)) break;
+      const double alpha = rr / pq;
+      LQ_TRY(axpy(c, nh, ev(x), ev(x), ev(pv), alpha));
+      LQ_TRY(axpy(c, nh, ev(r), ev(r), ev(q), -alpha));
+      double rn = 0.0;
+      LQ_TRY(dot(c, w, nh, ev(r), ev(r), nullptr, &rn));
+      ++iters;
+      if (std::sqrt(rn) <= tgt) break;
+      LQ_TRY(axpy(c, nh, ev(pv), ev(r), ev(pv), rn / rr));
+      rr = rn;
+    }
     target *= 0.5;
   }
   st.outer_iters = passes;

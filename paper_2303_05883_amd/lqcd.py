@@ -35,7 +35,8 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
             "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_dwf_apply",
             "lqcd_dwf_solve", "lqcd_dwf_field_bytes", "lqcd_dwf_import", "lqcd_dwf_export", "lqcd_dwf_apply_native",
             "lqcd_mg_setup", "lqcd_mg_coarse_size", "lqcd_mg_restrict", "lqcd_mg_prolong", "lqcd_mg_coarse_apply",
-            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_strerror", "lqcd_last_error"]
+            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur", "lqcd_dwf_solve_eo", "lqcd_strerror",
+            "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
 
@@ -143,6 +144,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_stag_export.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_dwf_apply.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp, ip]
     lib.lqcd_dwf_solve.argtypes = [vp, C.POINTER(DwfParams), vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
+    lib.lqcd_dwf_apply_schur.argtypes = [vp, C.POINTER(DwfParams), ip, ip, vp, vp, ip]
+    lib.lqcd_dwf_solve_eo.argtypes = [vp, C.POINTER(DwfParams), vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
     lib.lqcd_dwf_field_bytes.argtypes = [vp, ip, ip]
     lib.lqcd_dwf_field_bytes.restype = C.c_size_t
     lib.lqcd_dwf_import.argtypes = [vp, ip, ip, vp, vp]
@@ -166,7 +169,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "lqcd_stag_apply", "lqcd_stag_solve", "lqcd_stag_import", "lqcd_stag_export",
                  "lqcd_stag_hop_native", "lqcd_dwf_apply", "lqcd_dwf_solve", "lqcd_dwf_import",
                  "lqcd_dwf_export", "lqcd_dwf_apply_native", "lqcd_mg_setup", "lqcd_mg_restrict", "lqcd_mg_prolong",
-                 "lqcd_mg_coarse_apply", "lqcd_mg_apply", "lqcd_solve_mg"):
+                 "lqcd_mg_coarse_apply", "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur",
+                 "lqcd_dwf_solve_eo"):
         getattr(lib, name).restype = ip
     _lib = lib
     return lib
@@ -479,6 +483,34 @@ class Lattice:
         status = self._call(self.lib.lqcd_dwf_solve, self.handle, C.byref(d), pb, px, C.byref(prm), C.byref(st))
         if raise_on_fail:
             _check(status, "lqcd_dwf_solve")
+        return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
+                     st.seconds_setup, status)
+
+    def dwf_apply_schur(self, Ls, M5, mf, prec, x, out, dag=False, b5=1.0, c5=0.0):
+        """The even-odd Schur complement S_ee (or its adjoint) on the even sites of canonical 5-d fields."""
+        pi, di = _ptr(x)
+        po, do = _ptr(out)
+        if di != do:
+            raise ValueError("in and out must both be host or both be device")
+        d = dwf_params(Ls, M5, mf, b5, c5)
+        _check(self._call(self.lib.lqcd_dwf_apply_schur, self.handle, C.byref(d), int(bool(dag)), int(prec), pi, po,
+                          di), "lqcd_dwf_apply_schur")
+        return out
+
+    def dwf_solve_eo(self, Ls, M5, mf, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True, b5=1.0,
+                     c5=0.0) -> Stats:
+        """Moebius domain-wall D x = b through the even-odd Schur complement and FP64 CG."""
+        prm = default_params()
+        pb, db = _ptr(b)
+        px, dx = _ptr(x)
+        if db != dx:
+            raise ValueError("b and x must both be host or both be device")
+        prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
+        d = dwf_params(Ls, M5, mf, b5, c5)
+        st = SolveStats()
+        status = self._call(self.lib.lqcd_dwf_solve_eo, self.handle, C.byref(d), pb, px, C.byref(prm), C.byref(st))
+        if raise_on_fail:
+            _check(status, "lqcd_dwf_solve_eo")
         return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
                      st.seconds_setup, status)
 

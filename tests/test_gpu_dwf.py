@@ -96,3 +96,38 @@ def test_dwf_native_apply_matches_oracle(prec, b5, c5):
         lat.dwf_export(prec, Ls, dst, got)
         torch.cuda.synchronize()
         assert dirac.rel_l2(from_dev(got), want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 4), ((4, 6, 8, 10), 3), ((4, 4, 16, 4), 8), ((2, 2, 2, 4), 1)])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_dwf_schur_matches_oracle(dims, Ls, prec, b5, c5):
+    U = fg.gauge_field(dims, 119, "haar")
+    op = dwf.DomainWall(U, 1.8, 0.05, Ls, -1, b5, c5)
+    eo = dwf.EvenOdd(op)
+    psi = field5(dims, Ls, 120)
+    lat = lattice(dims, U, 0.12, 0.0)
+    for dag, want in ((False, eo.schur(psi)), (True, eo.schur_dag(psi))):
+        out = to_dev(np.ones_like(psi))
+        lat.dwf_apply_schur(Ls, 1.8, 0.05, prec, to_dev(psi), out, dag=dag, b5=b5, c5=c5)
+        assert dirac.rel_l2(from_dev(out), want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+def test_dwf_solve_eo_matches_oracle(b5, c5):
+    dims, Ls = (4, 4, 4, 8), 6
+    U = fg.gauge_field(dims, 121, "smooth", 0.3)
+    b = field5(dims, Ls, 122)
+    op = dwf.DomainWall(U, 1.8, 0.1, Ls, -1, b5, c5)
+    lat = lattice(dims, U, 0.12, 0.0)
+    x = to_dev(np.zeros_like(b))
+    st = lat.dwf_solve_eo(Ls, 1.8, 0.1, to_dev(b), x, tol=1e-10, b5=b5, c5=c5)
+    xh = from_dev(x)
+    r = np.linalg.norm(b - op.D(xh)) / np.linalg.norm(b)
+    assert st.true_rel_resid <= 1e-10 and r <= 1e-10, (st, r)
+    xo, info = dwf.EvenOdd(op).solve(b, tol=1e-12)
+    assert info.converged
+    assert dirac.rel_l2(xh, xo) <= 1e-8
+    # the even-odd system needs fewer iterations than the full normal equations
+    st_full = lat.dwf_solve(Ls, 1.8, 0.1, to_dev(b), to_dev(np.zeros_like(b)), tol=1e-10, b5=b5, c5=c5)
+    assert st.inner_iters < st_full.inner_iters, (st, st_full)
