@@ -675,7 +675,21 @@ def run_dwf(a, torch, lqcd):
     value = DWF_FLOPS * vol5 * sum(dwf_applications(s) for s in stats) / elapsed / 1e9
     ms_step = 1000 * elapsed / a.steps
     log(f"timed {a.steps} domain-wall CG solves: {ms_step:.1f} ms each, {stats[-1]}")
-    del b, x
+    # the even-odd Schur complement and CG on its normal equations, same system
+    xe = torch.zeros_like(b)
+    lat.dwf_solve_eo(Ls, d["M5"], d["mf"], b, xe, **mob)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st_eo = lat.dwf_solve_eo(Ls, d["M5"], d["mf"], b, xe, **mob)
+    torch.cuda.synchronize()
+    ms_eo = 1000 * (time.perf_counter() - t1)
+    compare = {"full_cg": {"ms": round(ms_step, 2), "cg_iters": stats[-1].inner_iters,
+                           "true_rel_resid": stats[-1].true_rel_resid},
+               "even_odd_cg": {"ms": round(ms_eo, 2), "cg_iters": st_eo.inner_iters,
+                               "true_rel_resid": st_eo.true_rel_resid,
+                               "speedup_vs_full": round(ms_step / ms_eo, 3)}}
+    log(f"domain-wall solves: {compare}")
+    del b, x, xe
     torch.cuda.empty_cache()
     ops = {}
     for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32")):
@@ -696,7 +710,7 @@ def run_dwf(a, torch, lqcd):
               "lattice": list(dims), "Ls": Ls, "M5": d["M5"], "mf": d["mf"], "b5": d["b5"], "c5": d["c5"],
               "step": "one whole solve",
               "cg_iters_per_solve": stats[-1].inner_iters, "parallelism": "single GPU"}
-    return value, ms_step, config, roof, ops, None, None, lqcd.F64
+    return value, ms_step, config, roof, ops, compare, None, lqcd.F64
 
 
 def main():
