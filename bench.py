@@ -729,8 +729,8 @@ def main():
                          "(the short program the hardware-counter profiles are taken on)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the lattice is not sharded across GPUs in this build "
-              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library does not shard the lattice across GPUs "
+              "(the halo-exchange design is described but not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
