@@ -131,3 +131,31 @@ def test_dwf_solve_eo_matches_oracle(b5, c5):
     # the even-odd system needs fewer iterations than the full normal equations
     st_full = lat.dwf_solve(Ls, 1.8, 0.1, to_dev(b), to_dev(np.zeros_like(b)), tol=1e-10, b5=b5, c5=c5)
     assert st.inner_iters < st_full.inner_iters, (st, st_full)
+
+
+def test_dwf_adjoint_at_benchmark_size():
+    """<a, D b> = <D^dag a, b> and the same for S_ee at the benchmarked size
+    (64x32x16x8, Ls 8, Moebius), where the oracle would be slow: a property
+    that holds at any size, FP64."""
+    import torch
+    dims, Ls, M5, mf, b5, c5 = (64, 32, 16, 8), 8, 1.8, 0.05, 1.5, 0.5
+    U = fg.gauge_field(dims, 123, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    lx, ly, lz, lt = dims
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(124)
+    shape = (Ls, lt, lz, ly, lx, 4, 3)
+
+    def rnd():
+        return torch.complex(torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64),
+                             torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64))
+
+    a, b = rnd(), rnd()
+    out = torch.empty_like(a)
+    for apply in (lat.dwf_apply, lat.dwf_apply_schur):
+        apply(Ls, M5, mf, 0, b, out, b5=b5, c5=c5)
+        lhs = torch.vdot(a.flatten(), out.flatten()).item()
+        apply(Ls, M5, mf, 0, a, out, dag=True, b5=b5, c5=c5)
+        rhs = torch.vdot(out.flatten(), b.flatten()).item()
+        # (S_ee: both outputs vanish on the odd sites, so only the even sites of a and b enter)
+        assert abs(lhs - rhs) <= 1e-11 * abs(lhs), (apply, lhs, rhs)
