@@ -99,3 +99,21 @@ def test_stag_native_hop_matches_oracle():
             torch.cuda.synchronize()
             want = op.hop_pq(out_parity, 1 - out_parity, psi)
             assert dirac.rel_l2(from_dev(got), want) <= TOL[prec]
+
+
+def test_stag_antihermitian_at_benchmark_size():
+    """H = D - m is anti-Hermitian: <a, H b> = -<H a, b>, checked on the
+    benchmarked 32^3x64 lattice (a property that holds at any size), FP64."""
+    import torch
+    dims, mass = (32, 32, 32, 64), 0.05
+    U = fg.gauge_field(dims, 90, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    a, b = (to_dev(colour_field(dims, s)) for s in (91, 92))
+    ha, hb = torch.empty_like(a), torch.empty_like(b)
+    lat.stag_apply("D", 0, mass, a, ha)
+    lat.stag_apply("D", 0, mass, b, hb)
+    ha -= mass * a
+    hb -= mass * b
+    lhs = torch.vdot(a.flatten(), hb.flatten()).item()
+    rhs = -torch.vdot(ha.flatten(), b.flatten()).item()
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs), (lhs, rhs)
