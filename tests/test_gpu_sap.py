@@ -96,3 +96,22 @@ def test_solve_sap_agrees_with_even_odd_solver():
     s2 = lat.solve(to_dev(b), x2, tol=1e-10)
     assert s1.true_rel_resid <= 1e-10 and s2.true_rel_resid <= 1e-10
     assert dirac.rel_l2(from_dev(x1), from_dev(x2)) <= 1e-8
+
+
+def test_sap_properties_at_benchmark_size():
+    """On the benchmarked 32^3x64 clover system with 16x4x2x2 blocks: M is
+    homogeneous (M(2 eta) = 2 M(eta), bit for bit, as scaling by 2 is exact
+    and the kernel's sums run in a fixed order), and one application reduces
+    the residual of D x = eta."""
+    import torch
+    dims, kappa = (32, 32, 32, 64), 0.137
+    U = fg.gauge_field(dims, 47, "smooth", 0.3)
+    lat = lattice(dims, U, kappa, 1.0)
+    eta = to_dev(fg.gaussian_spinor(dims, 48))
+    m1, m2 = torch.empty_like(eta), torch.empty_like(eta)
+    lat.apply_sap(eta, m1, (16, 4, 2, 2), 2, 6)
+    lat.apply_sap(2 * eta, m2, (16, 4, 2, 2), 2, 6)
+    assert torch.equal(m2, 2 * m1)
+    dm = torch.empty_like(eta)
+    lat.apply("D", 0, m1, dm)
+    assert torch.linalg.vector_norm(eta - dm) < 0.5 * torch.linalg.vector_norm(eta)
