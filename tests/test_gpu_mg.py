@@ -141,3 +141,37 @@ def test_mg_errors_and_state():
     with pytest.raises(lqcd.LqcdError) as e:
         lat.solve_mg(r, np.zeros_like(r))
     assert e.value.status == lqcd.ESTATE
+
+
+def test_mg_properties_at_benchmark_size():
+    """On the benchmarked 32^3x64 clover system with 4^4 aggregates: P^dag P = 1
+    and the coarse operator is Gamma5-hermitian (<x, G D_c y> = <G D_c x, y>,
+    G = +1 on the c_+ and -1 on the c_- coarse entries), to FP32 rounding."""
+    import torch
+    dims, n = (32, 32, 32, 64), 4
+    U = fg.gauge_field(dims, 75, "smooth", 0.3)
+    lat = lattice(dims, U, 0.137, 1.0)
+    lx, ly, lz, lt = dims
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(76)
+    shape = (n, lt, lz, ly, lx, 4, 3)
+    start = torch.complex(torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64),
+                          torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64))
+    lat.mg_setup(start, agg=(4, 4, 4, 4), nvec=n, setup_iters=1, sap_block=(16, 4, 2, 2), ncycles=1, nmr=2)
+    del start
+    nc = lat.mg_coarse_size()
+    assert nc == 8 * 8 * 8 * 16 * 2 * n
+    e = to_dev(coarse_vec(nc, 77))
+    fine = torch.empty((lt, lz, ly, lx, 4, 3), dtype=torch.complex128, device="cuda")
+    lat.mg_prolong(e, fine)
+    back = torch.empty_like(e)
+    lat.mg_restrict(fine, back)
+    assert (torch.linalg.vector_norm(back - e) / torch.linalg.vector_norm(e)).item() <= 1e-5
+    g = torch.tensor([1.0] * n + [-1.0] * n, dtype=torch.float64, device="cuda").repeat(nc // (2 * n))
+    x, y = to_dev(coarse_vec(nc, 78)), to_dev(coarse_vec(nc, 79))
+    dx, dy = torch.empty_like(x), torch.empty_like(y)
+    lat.mg_coarse_apply(x, dx)
+    lat.mg_coarse_apply(y, dy)
+    lhs = torch.vdot(x, g * dy).item()
+    rhs = torch.vdot(g * dx, y).item()
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs), (lhs, rhs)
