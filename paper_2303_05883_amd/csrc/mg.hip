@@ -576,9 +576,10 @@ int coarse_solve(lqcd_ctx* c, MgState& s, int& iters) {
   LQ_HIP(hipMemsetAsync(p, 0, s.nc() * sizeof(float2), c->stream));
   LQ_HIP(hipMemsetAsync(v, 0, s.nc() * sizeof(float2), c->stream));
   cx<double> rho_old{1, 0}, alpha{1, 0}, omega{1, 0};
+  // rho = <rhat, r>; later iterations take it from the residual-norm pass
+  cx<double> rho;
+  LQ_TRY(cdot(c, s, rh, r, &rho, nullptr));
   while (iters < s.prm.coarse_max_iter) {
-    cx<double> rho;
-    LQ_TRY(cdot(c, s, rh, r, &rho, nullptr));
     if (rho.r == 0.0 && rho.i == 0.0) break;
     const cx<double> beta = cdiv(rho, rho_old) * cdiv(alpha, omega);
     LQ_TRY(clin(c, s, p, {1, 0}, r, f2(beta), p, f2({-(beta * omega).r, -(beta * omega).i}), v));
@@ -589,18 +590,18 @@ int coarse_solve(lqcd_ctx* c, MgState& s, int& iters) {
     alpha = cdiv(rho, rv);
     LQ_TRY(clin(c, s, q, {1, 0}, r, f2({-alpha.r, -alpha.i}), v));  // s
     LQ_TRY(capply(c, s, q, t));
-    cx<double> ts;
+    // one pass: <s, t> (its conjugate is <t, s>) and <t, t>
+    cx<double> st;
     double tt = 0.0;
-    LQ_TRY(cdot(c, s, t, q, &ts, &tt));
-    // cdot returns <t, q> and |q|^2; |t|^2 needs its own pass
-    LQ_TRY(cdot(c, s, t, t, nullptr, &tt));
-    omega = tt != 0.0 ? cx<double>{ts.r / tt, ts.i / tt} : cx<double>{0, 0};
+    LQ_TRY(cdot(c, s, q, t, &st, &tt));
+    omega = tt != 0.0 ? cx<double>{st.r / tt, -st.i / tt} : cx<double>{0, 0};
     LQ_TRY(clin(c, s, x, {1, 0}, x, f2(alpha), p, f2(omega), q));
     LQ_TRY(clin(c, s, r, {1, 0}, q, f2({-omega.r, -omega.i}), t));
     rho_old = rho;
     ++iters;
+    // one pass: the next rho = <rhat, r> and |r|^2
     double rr = 0.0;
-    LQ_TRY(cdot(c, s, r, r, nullptr, &rr));
+    LQ_TRY(cdot(c, s, rh, r, &rho, &rr));
     if (std::sqrt(rr) <= target || (omega.r == 0.0 && omega.i == 0.0)) break;
   }
   return LQCD_OK;
