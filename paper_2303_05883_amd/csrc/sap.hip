@@ -486,9 +486,10 @@ int solve_flexible(lqcd_ctx* c, const lqcd_solve_params& prm, const FlexPrecond&
     LQ_TRY(blas_zero(c, 0, v.h[1]));
     LQ_TRY(blas_zero(c, 0, p.h[0]));
     LQ_TRY(blas_zero(c, 0, p.h[1]));
+    // rho = <rhat, r>; later iterations take it from the residual-norm pass
+    cx<double> rho;
+    LQ_TRY(dot(c, w, rh, r, &rho, nullptr));
     while (iters < prm.max_iter) {
-      cx<double> rho;
-      LQ_TRY(dot(c, w, rh, r, &rho, nullptr));
       if (rho.r == 0.0 && rho.i == 0.0) break;
       const cx<double> beta = cdivd(rho, rho_old) * cdivd(alpha, omega);
       // p = r + beta (p - omega v)
@@ -502,17 +503,18 @@ int solve_flexible(lqcd_ctx* c, const lqcd_solve_params& prm, const FlexPrecond&
       LQ_TRY(lin3(c, s, {1, 0}, r, {-alpha.r, -alpha.i}, &v));
       LQ_TRY(precond(s, sh));
       LQ_TRY(apply(sh, t));
-      cx<double> ts;
+      // one pass: <s, t> (its conjugate is <t, s>) and <t, t>
+      cx<double> st;
       double tt = 0.0;
-      LQ_TRY(dot(c, w, t, s, &ts, nullptr));
-      LQ_TRY(dot(c, w, t, t, nullptr, &tt));
-      omega = tt != 0.0 ? cx<double>{ts.r / tt, ts.i / tt} : cx<double>{0, 0};
+      LQ_TRY(dot(c, w, s, t, &st, &tt));
+      omega = tt != 0.0 ? cx<double>{st.r / tt, -st.i / tt} : cx<double>{0, 0};
       LQ_TRY(lin3(c, x, {1, 0}, x, alpha, &ph, omega, &sh));
       LQ_TRY(lin3(c, r, {1, 0}, s, {-omega.r, -omega.i}, &t));
       rho_old = rho;
       ++iters;
+      // one pass: the next rho = <rhat, r> and |r|^2
       double rn2 = 0.0;
-      LQ_TRY(dot(c, w, r, r, nullptr, &rn2));
+      LQ_TRY(dot(c, w, rh, r, &rho, &rn2));
       if (log_level() >= 2)
         std::fprintf(stderr, "[lqcd] %s-FBiCGStab iteration %d: |r|/|b| %.3e\n", name, iters, std::sqrt(rn2) / bnorm);
       if (std::sqrt(rn2) <= target || (omega.r == 0.0 && omega.i == 0.0)) break;
