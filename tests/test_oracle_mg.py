@@ -157,3 +157,41 @@ def test_multigrid_solve_matches_lapack(n_iter):
     assert info.converged
     want = np.linalg.solve(dense.dense_dirac(U, 0.13, 1.0), dense.to_vector(b))
     assert np.linalg.norm(dense.to_vector(x) - want) <= 1e-9 * np.linalg.norm(want)
+
+
+def _null_space_system():
+    """Unit links, periodic in t, kappa = 1/8, no clover term: every constant
+    spinor is an exact zero mode of D (the free operator at zero momentum is
+    1 - 8 kappa)."""
+    U = fg.gauge_field(DIMS, 0, "unit")
+    op = dirac.Operator(U, 0.125, 0.0, t_bc=+1)
+    c = np.random.default_rng(8).normal(size=(4, 3, 2)) @ np.array([1.0, 1j])
+    v0 = np.broadcast_to(c, DIMS[::-1] + (4, 3)).copy()
+    assert np.abs(op.D(v0)).max() <= 1e-14 * np.abs(v0).max()
+    agg = mg.Aggregates(DIMS, ADIMS)
+    start = [v0] + [fg.gaussian_spinor(DIMS, 50 + k) for k in range(2)]
+    return op, agg, start, v0
+
+
+@pytest.mark.parametrize("n_iter", [1, 3])
+def test_setup_keeps_exact_zero_mode(n_iter):
+    """The setup smooths the homogeneous equation D v = 0 (Sec. 3: SAP smoothing
+    of the test vectors), which leaves an exact zero mode of D where it is, so
+    the coarse space still holds it after every round: P P^dag v0 = v0."""
+    op, agg, start, v0 = _null_space_system()
+    blocks = sap.Blocks(DIMS, (2, 2, 2, 2))
+    P = mg.setup(op.D, agg, start, blocks, n_iter, 2, 3)
+    assert np.abs(P.prolong(P.restrict(v0)) - v0).max() <= 1e-12 * np.abs(v0).max()
+
+
+def test_setup_reading_v_from_sap_of_v_is_caught():
+    """A planted mistake, the setup round v <- M_SAP v instead of
+    v <- v - M_SAP D v, moves the zero mode out of the coarse space."""
+    op, agg, start, v0 = _null_space_system()
+    blocks = sap.Blocks(DIMS, (2, 2, 2, 2))
+    v = [np.asarray(s) for s in start]
+    for _ in range(3):
+        v = [sap.sap(op.D, blocks, vk, 2, 3) for vk in v]
+        v = mg.Prolongation(agg, v).vectors()
+    P = mg.Prolongation(agg, v)
+    assert np.abs(P.prolong(P.restrict(v0)) - v0).max() > 1e-3 * np.abs(v0).max()

@@ -49,6 +49,49 @@ def test_generated_links_are_su3():
         assert np.abs(np.conj(np.cross(u[:, 0], u[:, 1])) - u[:, 2]).max() < 1e-14
 
 
+def _plaquette(U):
+    """Average Re tr / 3 of the 1x1 loops U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag."""
+    tot = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            umu, unu = U[..., mu, :, :], U[..., nu, :, :]
+            loop = (umu @ np.roll(unu, -1, axis=3 - mu)
+                    @ np.conj(np.swapaxes(np.roll(umu, -1, axis=3 - nu), -1, -2))
+                    @ np.conj(np.swapaxes(unu, -1, -2)))
+            tot += np.trace(loop, axis1=-2, axis2=-1).real.mean() / 3
+    return tot / 6
+
+
+@pytest.mark.parametrize("eps,scale", [(0.3, 1.0), (0.25, 2 ** 0.5)])
+def test_smooth_link_normalisation(eps, scale):
+    """U = exp(i eps H) with H traceless Hermitian and E tr H^2 = 8 scale^2:
+    H is recovered from the eigenphases of each link (theta = eps lambda), so
+    the check does not repeat the generator's construction. The 5-sigma window
+    excludes a dropped trace subtraction (E tr H^2 = 9 scale^2)."""
+    u = fg.gauge_field((8, 8, 8, 8), 1003, "smooth", eps, scale).reshape(-1, 3, 3)
+    theta = np.angle(np.linalg.eigvals(u))
+    assert np.abs(theta).max() < 3.0  # no phase wrapped past pi
+    lam = theta / eps
+    assert np.abs(lam.sum(axis=-1)).max() <= 1e-12  # traceless
+    tr = (lam ** 2).sum(axis=-1)
+    sigma = tr.std() / np.sqrt(tr.size)
+    assert 5 * sigma < 0.5 * scale ** 2
+    assert abs(tr.mean() - 8 * scale ** 2) <= 5 * sigma
+
+
+def test_smooth_link_plaquettes():
+    """Links drawn independently with a conjugation-invariant law have
+    E[U] = c 1, so the average plaquette is c^4 with c = E[Re tr U] / 3; and
+    the recorded plaquettes of the two smooth ensembles (0.611 at eps 0.3,
+    0.713 at eps 0.25)."""
+    for eps, want in ((0.3, 0.611), (0.25, 0.713)):
+        U = fg.gauge_field((8, 8, 8, 8), 1003, "smooth", eps)
+        c = np.trace(U, axis1=-2, axis2=-1).real.mean() / 3
+        p = _plaquette(U)
+        assert abs(p - c ** 4) <= 3e-3
+        assert abs(p - want) <= 3e-3
+
+
 def test_generator_slicewise_equals_whole():
     dims = (4, 4, 2, 6)
     whole = fg.gauge_field(dims, 9, "smooth", 0.3)

@@ -127,3 +127,69 @@ def test_fbicgstab_sap_matches_lapack(csw):
     assert np.linalg.norm(dense.to_vector(x) - want) <= 1e-8 * np.linalg.norm(want)
     _, plain = solvers.bicgstab(op.D, b, tol=1e-10)
     assert info.iterations < plain.iterations
+
+
+def dense_block_mr(M, blocks, colour, rho_vec, n_mr):
+    """n_mr minimal-residual steps on each block of one colour separately, with
+    the block matrix M[B, B] cut out of the brute-force dense matrix and one
+    coefficient per block, written without the oracle's block machinery."""
+    delta = np.zeros_like(rho_vec)
+    lx, ly, lz, lt = DIMS
+    for blk in range(blocks.count):
+        idx = []
+        for t in range(lt):
+            for z in range(lz):
+                for y in range(ly):
+                    for x in range(lx):
+                        if blocks.block_id[t, z, y, x] == blk and blocks.colour[t, z, y, x] == colour:
+                            s = dense.site_index(DIMS, x, y, z, t)
+                            idx.extend(range(12 * s, 12 * s + 12))
+        if not idx:
+            continue
+        idx = np.array(idx)
+        MB = M[np.ix_(idx, idx)]
+        r = rho_vec[idx].copy()
+        d = np.zeros_like(r)
+        for _ in range(n_mr):
+            q = MB @ r
+            a = np.vdot(q, r) / np.vdot(q, q).real
+            d += a * r
+            r -= a * q
+        delta[idx] = d
+    return delta
+
+
+@pytest.mark.parametrize("n_mr", [1, 2, 5])
+def test_mr_steps_equal_blockwise_dense_mr(n_mr):
+    """A few MR steps (far from converged) equal the same steps taken block by
+    block on the dense block matrices, each block with its own coefficient
+    (Sec. 3: the SAP smoother solves every block approximately on its own)."""
+    U, op = setup(0.13, 1.0)
+    blocks = sap.Blocks(DIMS, BDIMS)
+    M = dense.dense_dirac(U, 0.13, 1.0)
+    rho = fg.gaussian_spinor(DIMS, 14)
+    for colour in (0, 1):
+        rho_c = np.where(blocks.mask(colour), rho, 0)
+        want = dense_block_mr(M, blocks, colour, dense.to_vector(rho_c), n_mr)
+        got = dense.to_vector(sap.mr_blocks(op.D, blocks, colour, rho_c, n_mr))
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_mr_one_coefficient_per_colour_is_caught():
+    """A planted mistake, one MR coefficient for all blocks of a colour instead
+    of one per block, fails the blockwise dense MR pin."""
+    U, op = setup(0.13, 1.0)
+    blocks = sap.Blocks(DIMS, BDIMS)
+    M = dense.dense_dirac(U, 0.13, 1.0)
+    rho = fg.gaussian_spinor(DIMS, 14)
+    colour = 0
+    m = blocks.mask(colour)
+    r = np.where(m, rho, 0)
+    delta = np.zeros_like(rho)
+    for _ in range(2):
+        q = sap.block_apply(op.D, blocks, colour, r)
+        a = np.vdot(q, r) / np.vdot(q, q).real
+        delta = delta + np.where(m, a * r, 0)
+        r = r - np.where(m, a * q, 0)
+    want = dense_block_mr(M, blocks, colour, dense.to_vector(np.where(m, rho, 0)), 2)
+    assert np.abs(dense.to_vector(delta) - want).max() > 1e-3 * np.abs(want).max()
