@@ -185,19 +185,91 @@ def hop_applications(st):
     return 4 * st.inner_iters + 2 * (st.outer_iters + 1) + 1 + 1 + 2
 
 
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+_HOST_HOP = None  # (U, psi, sites) shared with forked workers
+
+
+def _host_hop_chunk(span):
+    from oracle import sampled
+    U, psi, sites = _HOST_HOP
+    out = sampled.hop_at(U, sampled.full_lookup(psi), -1, sites[span[0]:span[1]])
+    return float(np.vdot(out, out).real)
+
+
+def _host_ready(_):
+    return os.getpid()
+
+
+def cpu_all_cores(U, b, dims, workers):
+    """The oracle's site-list hop (oracle.sampled, pinned to the whole-field
+    hop) over every site of the lattice, the sites split evenly among worker
+    processes: one full-lattice application on all usable host cores."""
+    import multiprocessing as mp
+    global _HOST_HOP
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx), indexing="ij")
+    sites = np.stack([x.ravel(), y.ravel(), z.ravel(), t.ravel()], axis=1)
+    _HOST_HOP = (U, b, sites)
+    n = len(sites)
+    pieces = 4 * workers
+    spans = [(k * n // pieces, (k + 1) * n // pieces) for k in range(pieces)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(_host_ready, range(workers))
+        t0 = time.perf_counter()
+        pool.map(_host_hop_chunk, spans, chunksize=1)
+        dt = time.perf_counter() - t0
+    _HOST_HOP = None
+    return dt
+
+
 def cpu_baseline(U, b, dims):
-    """The CPU oracle's hopping term on the same field (one full-lattice
-    application = 1320 flop x V), timed on the host."""
-    from oracle import dirac
+    """The CPU oracle timed on the host: its hopping term on the benchmark's
+    own field (one full-lattice application = 1320 flop x V) on one thread and
+    on all usable cores, and the 8^4 Haar Wilson system (kappa 0.12) applied
+    and solved by its unpreconditioned BiCGStab."""
+    from oracle import dirac, solvers
+    host = host_info()
     reps = 2
     t0 = time.perf_counter()
     for _ in range(reps):
         dirac.hop(U, b, -1)
     dt = (time.perf_counter() - t0) / reps
     v = int(np.prod(dims))
+    workers = max(1, min(16, host["usable_cpus"]))
+    dt_all = cpu_all_cores(U, b, dims, workers)
+    c1_dims = (8, 8, 8, 8)
+    U1 = fg.gauge_field(c1_dims, 1001, "haar")
+    b1 = fg.gaussian_spinor(c1_dims, 1001)
+    op = dirac.Operator(U1, 0.12, 0.0)
+    t0 = time.perf_counter()
+    op.D(b1)
+    dt_apply = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x1, info = solvers.bicgstab(op.D, b1, tol=1e-10)
+    dt_solve = time.perf_counter() - t0
     return {"value": round(HOP_FLOPS * v / dt / 1e9, 4), "unit": "GFlop/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} oracle hopping-term applications H psi on the full {dims[0]}^3x{dims[3]} lattice "
-                      f"(1320 flop/site x {v} sites each, NumPy float64, one thread), {dt:.1f} s each"}
+                      f"(1320 flop/site x {v} sites each, NumPy float64, one thread), {dt:.1f} s each",
+            "host": host,
+            "all_cores": {"value": round(HOP_FLOPS * v / dt_all / 1e9, 4), "unit": "GFlop/s", "cores": workers,
+                          "sample": f"one application of the oracle's site-list hop over all {v} sites, "
+                                    f"split among {workers} worker processes, {dt_all:.2f} s"},
+            "c1_8x8x8x8": {"apply_ms": round(1000 * dt_apply, 2), "solve_s": round(dt_solve, 3),
+                           "iterations": info.iterations, "rel_resid": info.residual,
+                           "sample": "oracle D apply and unpreconditioned FP64 BiCGStab to 1e-10, Haar links, "
+                                     "kappa 0.12, one thread"}}
 
 
 def make_lattice(torch, lqcd, dims, seed, eps, kappa, csw, stream=None, source=True, scale=1.0):
@@ -260,6 +332,42 @@ def compare_solves(torch, lat, lqcd, bd):
     return out
 
 
+def c1_gpu(torch, lqcd):
+    """C1: the 8^4 Haar Wilson system (kappa 0.12) solved by BiCGStab on the
+    full operator (no preconditioning) and by the even-odd FP64 solve."""
+    dims = (8, 8, 8, 8)
+    U = fg.gauge_field(dims, 1001, "haar")
+    b = torch.from_numpy(fg.gaussian_spinor(dims, 1001)).cuda()
+    lat = lqcd.Lattice(dims, -1)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    lat.set_clover(0.12, 0.0)
+    out = {}
+    for name, eo in (("unpreconditioned_f64", False), ("even_odd_f64", True)):
+        x = torch.zeros_like(b)
+        lat.solve(b, x, even_odd=eo)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = lat.solve(b, x, even_odd=eo)
+        torch.cuda.synchronize()
+        out[name] = {"ms": round(1000 * (time.perf_counter() - t0), 3), "iterations": st.inner_iters,
+                     "true_rel_resid": st.true_rel_resid}
+    lat.close()
+    log(f"C1 8^4 solves: {out}")
+    return out
+
+
+def clover_compare(a, torch, lqcd):
+    """C3: the 32^3x64 clover system solved in FP64 and mixed FP32 / FP16."""
+    w = WORKLOADS["clover"]
+    lat, U, b = make_lattice(torch, lqcd, w["dims"], w["seed"], w["eps"], w["kappa"], w["csw"])
+    del U
+    tune(lat, lqcd, a.cached, "clover " + str(w["dims"]))
+    bd = torch.from_numpy(b).cuda()
+    out = compare_solves(torch, lat, lqcd, bd)
+    lat.close()
+    return out
+
+
 def run_single(a, torch, lqcd):
     w = WORKLOADS[a.workload]
     dims = w["dims"]
@@ -301,6 +409,13 @@ def run_single(a, torch, lqcd):
     cpu = None if (a.no_cpu or a.workload != "wilson") else cpu_baseline(U, b, dims)
     if cpu:
         log(f"cpu baseline: {cpu}")
+    if a.workload == "wilson" and not a.no_compare and not a.no_extra:
+        # the other two targets of the metric, timed in the same run: C3 clover
+        # mixed vs FP64, C4 batched vs sequential FP64, and C1
+        del U, b, bd, x
+        lat.close()
+        compare = {"wilson": compare, "clover": clover_compare(a, torch, lqcd),
+                   "batch": batch_compare(a, torch, lqcd), "c1": c1_gpu(torch, lqcd)}
     config = {"workload": w["text"] + f", {a.inner} inner / f64 outer to true residual 1e-10",
               "lattice": list(dims), "kappa": w["kappa"], "csw": w["csw"], "step": "one whole solve",
               "inner_iters_per_solve": stats[-1].inner_iters, "outer_iters_per_solve": stats[-1].outer_iters,
@@ -308,10 +423,10 @@ def run_single(a, torch, lqcd):
     return value, ms_step, config, roof, hop, compare, cpu, inner
 
 
-def run_batch(a, torch, lqcd):
+def batch_setup(a, torch, lqcd):
+    """The three clover lattices of the batched workload with 12 point sources each."""
     stream = torch.cuda.Stream()
-    lats, bs, xs = [], [], []
-    vhs = []
+    lats, bs, xs, vhs = [], [], [], []
     for dims, seed in BATCH:
         lat, U, _ = make_lattice(torch, lqcd, dims, seed, 0.3, 0.1370, 1.0, stream=stream, source=False)
         del U
@@ -321,13 +436,16 @@ def run_batch(a, torch, lqcd):
         bs.append(torch.from_numpy(src).cuda())
         xs.append(torch.zeros_like(bs[-1]))
         vhs.append(int(np.prod(dims)) // 2)
-    inner = lqcd.F32 if a.inner == "f32" else lqcd.F16
-    for _ in range(a.warmup):
+    return lats, bs, xs, vhs
+
+
+def time_batched(torch, lqcd, lats, bs, xs, inner, steps, warmup):
+    for _ in range(warmup):
         lqcd.solve_batch(lats, bs, xs, inner_prec=inner)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     stats = None
-    for _ in range(a.steps):
+    for _ in range(steps):
         stats = lqcd.solve_batch(lats, bs, xs, inner_prec=inner)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -335,6 +453,51 @@ def run_batch(a, torch, lqcd):
     if not worst <= 1e-10:
         log(f"true residual {worst} above 1e-10")
         sys.exit(1)
+    return elapsed, stats
+
+
+def time_sequential_f64(torch, lqcd, lats, bs, xs):
+    """The same 36 right-hand sides one after another, plain FP64 BiCGStab
+    (one warm-up solve per lattice first)."""
+    for lat, b, x in zip(lats, bs, xs):
+        lat.solve(b[0], x[0], inner_prec=lqcd.F64)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    worst = 0.0
+    for lat, b, x in zip(lats, bs, xs):
+        for r in range(12):
+            worst = max(worst, lat.solve(b[r], x[r], inner_prec=lqcd.F64).true_rel_resid)
+    torch.cuda.synchronize()
+    if not worst <= 1e-10:
+        log(f"true residual {worst} above 1e-10")
+        sys.exit(1)
+    return time.perf_counter() - t1
+
+
+def batch_compare(a, torch, lqcd):
+    """C4: one batched solve of the 36 right-hand sides with FP32 and with FP16
+    inner iterations against 36 sequential FP64 solves."""
+    lats, bs, xs, _ = batch_setup(a, torch, lqcd)
+    out = {}
+    for name, inner in (("batched_f32", lqcd.F32), ("batched_f16", lqcd.F16)):
+        el, stats = time_batched(torch, lqcd, lats, bs, xs, inner, 1, 1)
+        out[name] = {"ms": round(1000 * el, 1), "propagators_per_s": round(3 / el, 3),
+                     "inner_iters_max": max(s.inner_iters for s in stats),
+                     "true_rel_resid_max": max(s.true_rel_resid for s in stats)}
+    seq = time_sequential_f64(torch, lqcd, lats, bs, xs)
+    out["sequential_f64"] = {"ms": round(1000 * seq, 1), "propagators_per_s": round(3 / seq, 3)}
+    for name in ("batched_f32", "batched_f16"):
+        out[name]["speedup_vs_sequential_f64"] = round(seq * 1000 / out[name]["ms"], 3)
+    for lat in lats:
+        lat.close()
+    log(f"batch vs sequential FP64: {out}")
+    return out
+
+
+def run_batch(a, torch, lqcd):
+    lats, bs, xs, vhs = batch_setup(a, torch, lqcd)
+    inner = lqcd.F32 if a.inner == "f32" else lqcd.F16
+    elapsed, stats = time_batched(torch, lqcd, lats, bs, xs, inner, a.steps, a.warmup)
     seg_vh = [vh for vh in vhs for _ in range(12)]
     flops = sum(HOP_FLOPS * vh * hop_applications(s) for vh, s in zip(seg_vh, stats)) * a.steps
     value = flops / elapsed / 1e9
@@ -343,14 +506,7 @@ def run_batch(a, torch, lqcd):
     log(f"timed {a.steps} batched solves of 36 RHS: {ms_step:.1f} ms each, {props:.2f} propagators/s")
     compare = None
     if not a.no_compare:
-        # the same 36 right-hand sides one after another, plain FP64 BiCGStab
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for lat, b, x in zip(lats, bs, xs):
-            for r in range(12):
-                lat.solve(b[r], x[r], inner_prec=lqcd.F64)
-        torch.cuda.synchronize()
-        seq = time.perf_counter() - t1
+        seq = time_sequential_f64(torch, lqcd, lats, bs, xs)
         compare = {"batched_ms": round(ms_step, 2), "sequential_f64_ms": round(1000 * seq, 2),
                    "propagators_per_s_batched": round(props, 3),
                    "propagators_per_s_sequential_f64": round(3 / seq, 3),
@@ -722,6 +878,8 @@ def main():
     ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-vs-mixed solve comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="wilson workload: skip the clover (C3), batched (C4) and 8^4 (C1) comparisons")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON launch-shape cache: read if present (no tuning sweep), written after tuning otherwise")
     ap.add_argument("--kernels-only", action="store_true",

@@ -130,6 +130,9 @@ typedef struct {
                            space, the FP64 true residual re-injected each time the
                            iterated one drops 10x); 0 = defect correction (restart
                            the inner solve from each FP64 residual) */
+  int even_odd;         /* lqcd_solve only: 1 = even-odd preconditioned (Eq. (1));
+                           0 = BiCGStab on the full operator D, FP64 only
+                           (inner_prec must be LQCD_F64, else EINVAL) */
 } lqcd_solve_params;
 
 typedef struct {
@@ -143,20 +146,29 @@ typedef struct {
 
 /* Fill *p with the defaults (tol 1e-10, max_iter 100000, max_outer 100,
  * inner_prec LQCD_F64, inner_tol 1e-6 for F32 / 1e-2 for F16 when 0,
- * check_every 8, use_graph 1, x0 NULL, on_device 0, reliable_update 0). */
+ * check_every 8, use_graph 1, x0 NULL, on_device 0, reliable_update 0,
+ * even_odd 1). */
 void lqcd_default_params(lqcd_solve_params* p);
 
-/* Solve D x = b (canonical full-lattice vectors) by even-odd preconditioning:
+/* Solve D x = b (canonical full-lattice vectors), the propagator solve the
+ * paper benchmarks (Sec. 3: BiCGStab for the clover operator and its
+ * mixed-precision variant), by even-odd preconditioning (Eq. (1)):
  * b_e' = b_e - D_eo D_oo^-1 b_o, S x_e = b_e' by BiCGStab (FP64, or FP32/FP16
  * iterations with FP64 reliable updates or an FP64 defect-correction loop), then
- * x_o = D_oo^-1 (b_o - D_oe x_e). Returns after the stream is synchronised.
- * ENOCONV if the caps are hit (x holds the last iterate, stats are filled). */
+ * x_o = D_oo^-1 (b_o - D_oe x_e). With prm->even_odd = 0, FP64 BiCGStab on the
+ * full operator D instead (stats: inner_iters = iterations, outer_iters =
+ * passes restarted from the true residual). Returns after the stream is
+ * synchronised. ENOCONV if the caps are hit (x holds the last iterate, stats
+ * are filled). */
 int lqcd_solve(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_params* prm,
                lqcd_solve_stats* stats);
 
-/* Batched solve: for each lattice k < nlattices, nrhs[k] right-hand sides
+/* Batched solve (Sec. 3: many equations on one gauge configuration, e.g. the
+ * 12 spin-colour sources of a propagator, solved together to share the
+ * operator's data): for each lattice k < nlattices, nrhs[k] right-hand sides
  * b[k] (nrhs[k] canonical vectors back to back) on context ctxs[k]; solutions
- * to x[k]. All contexts must share one stream. Each RHS runs its own
+ * to x[k], by the even-odd preconditioned (mixed-precision) BiCGStab of
+ * lqcd_solve (even_odd = 0 is EINVAL here). All contexts must share one stream. Each RHS runs its own
  * BiCGStab (own alpha, beta, omega; not block Krylov) but every operator step
  * of every unconverged RHS of every lattice is one persistent kernel launch that
  * loads each link once per site for all RHS of that lattice. Converged RHS are

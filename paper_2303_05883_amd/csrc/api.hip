@@ -125,6 +125,7 @@ void lqcd_default_params(lqcd_solve_params* p) {
   p->x0 = nullptr;
   p->on_device = 0;
   p->reliable_update = 0;
+  p->even_odd = 1;
 }
 
 int lqcd_create(const int dims[4], int t_bc, void* hip_stream, lqcd_ctx** out) {
@@ -327,7 +328,7 @@ int lqcd_apply(lqcd_ctx* c, int op, int prec, const double* in, double* out, int
 static int validate_params(const lqcd_solve_params* p) {
   if (!p) return LQCD_OK;
   if (!(p->tol > 0) || p->inner_prec < 0 || p->inner_prec > 2 || p->max_iter < 1 || p->max_outer < 1 ||
-      p->inner_tol < 0 || !(p->inner_tol < 1))
+      p->inner_tol < 0 || !(p->inner_tol < 1) || p->even_odd < 0 || p->even_odd > 1)
     return set_error(LQCD_EINVAL, "bad solver parameters");
   return LQCD_OK;
 }
@@ -339,6 +340,8 @@ int lqcd_solve(lqcd_ctx* c, const double* b, double* x, const lqcd_solve_params*
   if (prm_in) prm = *prm_in;
   else lqcd_default_params(&prm);
   if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
+  if (!prm.even_odd && prm.inner_prec != LQCD_F64)
+    return set_error(LQCD_EINVAL, "the unpreconditioned solve (even_odd = 0) runs in FP64 only");
   LQ_TRY(ensure_apply_buffers(c, 0));
   LQ_TRY(ensure_workspace(c, prm.inner_prec));
   Workspace* w = c->ws;
@@ -352,11 +355,21 @@ int lqcd_solve(lqcd_ctx* c, const double* b, double* x, const lqcd_solve_params*
     const double* dx0 = nullptr;
     LQ_TRY(stage_in(c, prm.x0, prm.on_device, c->canon_b, bytes, &dx0));
     LQ_TRY(launch_import_spinor(c, 0, 0, dx0, w->x_e));
+    if (!prm.even_odd) LQ_TRY(launch_import_spinor(c, 0, 1, dx0, w->x_o));
   } else {
     LQ_TRY(blas_zero(c, 0, w->x_e));
   }
   lqcd_solve_stats st{};
-  const int status = solve_native(c, prm, st);
+  int status;
+  if (prm.even_odd) {
+    status = solve_native(c, prm, st);
+  } else {
+    // BiCGStab on the full operator D: the flexible BiCGStab without a
+    // preconditioner; its counts mapped to lqcd_solve's (iterations, passes)
+    status = solve_flexible(c, prm, FlexPrecond(), "plain", w->b_e, w->b_o, w->x_e, w->x_o, !prm.x0, st);
+    st.inner_iters = st.outer_iters;
+    st.outer_iters = st.restarts + 1;
+  }
   if (status != LQCD_OK && status != LQCD_ENOCONV && status != LQCD_EBREAKDOWN) return status;
   double* dx = prm.on_device ? x : reinterpret_cast<double*>(c->canon_b);
   LQ_TRY(launch_export_spinor(c, 0, 0, w->x_e, dx));

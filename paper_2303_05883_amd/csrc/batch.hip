@@ -410,6 +410,7 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   if (!(prm.tol > 0) || prm.inner_prec < 0 || prm.inner_prec > 2 || prm.max_iter < 1 || prm.max_outer < 1)
     return set_error(LQCD_EINVAL, "bad solver parameters");
   if (prm.x0) return set_error(LQCD_EINVAL, "batched solves start from x = 0");
+  if (prm.even_odd != 1) return set_error(LQCD_EINVAL, "batched solves are even-odd preconditioned");
   hipStream_t stream = ctxs[0] ? ctxs[0]->stream : nullptr;
   bool clover = false;
   for (int l = 0; l < nlattices; ++l) {

@@ -16,8 +16,9 @@ int sap_apply(lqcd_ctx* c, const int b[4], int ncy, int nmr, const void* eta_e, 
               void* psi_o);
 // A right preconditioner for solve_flexible: FP64 native halves in and out.
 using FlexPrecond = std::function<int(const void* in_e, const void* in_o, void* out_e, void* out_o)>;
-// D x = b on the full lattice with FP64 flexible BiCGStab, pre on the right;
-// x starts at zero if zero_x; stops on the true residual.
+// D x = b on the full lattice with FP64 flexible BiCGStab, pre on the right
+// (an empty pre: plain BiCGStab on D); x starts at zero if zero_x; stops on the
+// true residual.
 int solve_flexible(lqcd_ctx* c, const lqcd_solve_params& prm, const FlexPrecond& pre, const char* name,
                    const void* b_e, const void* b_o, void* x_e, void* x_o, bool zero_x, lqcd_solve_stats& st);
 // D x = b with FP64 flexible BiCGStab, SAP on the right; x starts at zero if zero_x.

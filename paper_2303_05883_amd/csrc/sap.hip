@@ -427,8 +427,18 @@ int solve_flexible(lqcd_ctx* c, const lqcd_solve_params& prm, const FlexPrecond&
   FWork w;
   const size_t b64 = spinor_bytes(0, c->g.vh);
   Pair r, rh, p, v, s, t, ph, sh, ax;
-  for (Pair* q : {&r, &rh, &p, &v, &s, &t, &ph, &sh, &ax})
+  for (Pair* q : {&r, &rh, &p, &v, &s, &t, &ax})
     for (auto& h : q->h) LQ_TRY(w.alloc(b64, &h));
+  // without a preconditioner (plain BiCGStab) the preconditioned vectors are
+  // the vectors themselves: p_hat aliases p and s_hat aliases s
+  const bool ident = !pre;
+  if (ident) {
+    ph = p;
+    sh = s;
+  } else {
+    for (Pair* q : {&ph, &sh})
+      for (auto& h : q->h) LQ_TRY(w.alloc(b64, &h));
+  }
   LQ_HIP(hipMalloc(&w.partials, (size_t)2 * grid_of(c->g.vh) * 3 * sizeof(double)));
   Pair b, x;
   b.h[0] = const_cast<void*>(b_e);
@@ -442,6 +452,7 @@ int solve_flexible(lqcd_ctx* c, const lqcd_solve_params& prm, const FlexPrecond&
   auto apply = [&](Pair in, Pair out) -> int { return op_full(c, 0, in.h[0], in.h[1], out.h[0], out.h[1]); };
   int napply = 0;
   auto precond = [&](Pair in, Pair out) -> int {
+    if (ident) return LQCD_OK;
     LQ_TRY(pre(in.h[0], in.h[1], out.h[0], out.h[1]));
     ++napply;
     return LQCD_OK;

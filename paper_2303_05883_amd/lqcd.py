@@ -43,7 +43,7 @@ STAG_OPS = {"D": 0, "SCHUR": 1}
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("max_outer", C.c_int), ("inner_prec", C.c_int),
                 ("inner_tol", C.c_double), ("check_every", C.c_int), ("use_graph", C.c_int),
-                ("x0", C.c_void_p), ("on_device", C.c_int), ("reliable_update", C.c_int)]
+                ("x0", C.c_void_p), ("on_device", C.c_int), ("reliable_update", C.c_int), ("even_odd", C.c_int)]
 
 
 class SapParams(C.Structure):
@@ -353,7 +353,9 @@ class Lattice:
 
     # solver ----------------------------------------------------------------
     def solve(self, b, x, tol=1e-10, inner_prec=F64, inner_tol=0.0, max_iter=100000, max_outer=100,
-              check_every=8, use_graph=True, x0=None, raise_on_fail=True, reliable_update=False) -> Stats:
+              check_every=8, use_graph=True, x0=None, raise_on_fail=True, reliable_update=False,
+              even_odd=True) -> Stats:
+        """D x = b; even_odd=False: FP64 BiCGStab on the full operator (no preconditioning)."""
         prm = default_params()
         pb, db = _ptr(b)
         px, dx = _ptr(x)
@@ -363,6 +365,7 @@ class Lattice:
         prm.max_iter, prm.max_outer, prm.check_every = int(max_iter), int(max_outer), int(check_every)
         prm.use_graph, prm.on_device = int(bool(use_graph)), db
         prm.reliable_update = int(bool(reliable_update))
+        prm.even_odd = int(bool(even_odd))
         if x0 is not None:
             prm.x0 = _ptr(x0)[0]
         st = SolveStats()

@@ -112,3 +112,43 @@ def test_iteration_cap_reports_noconv():
     x = np.zeros_like(b)
     st = lat.solve(b, x, max_iter=3, raise_on_fail=False)
     assert st.status == lqcd.ENOCONV and st.inner_iters <= 3 + 8 and st.true_rel_resid > 1e-10
+
+
+def test_unpreconditioned_c1():
+    """BiCGStab on the full operator (no even-odd preconditioning) for the 8^4
+    Haar Wilson system at kappa 0.12: the oracle's FP64 residual of the
+    returned x is at most 1e-10, and so is the library's own."""
+    dims = (8, 8, 8, 8)
+    U = fg.gauge_field(dims, 1001, "haar")
+    b = fg.gaussian_spinor(dims, 1001)
+    lat = lattice(dims, U, 0.12, 0.0)
+    x = to_dev(np.zeros_like(b))
+    st = lat.solve(to_dev(b), x, even_odd=False)
+    r = true_residual(dirac.Operator(U, 0.12, 0.0), from_dev(x), b)
+    assert st.true_rel_resid <= 1e-10 and r <= 1e-10, (st, r)
+    assert st.inner_iters > 0 and st.outer_iters >= 1
+
+
+def test_unpreconditioned_matches_dense_solve():
+    dims = (4, 4, 4, 4)
+    U = fg.gauge_field(dims, 5, "smooth", 0.3)
+    b = fg.gaussian_spinor(dims, 6)
+    lat = lattice(dims, U, 0.13, 1.0)
+    x = np.zeros_like(b)
+    lat.solve(b, x, tol=1e-12, even_odd=False)
+    xd = np.linalg.solve(dense.dense_dirac(U, 0.13, 1.0), dense.to_vector(b)).reshape(b.shape)
+    assert dirac.rel_l2(x, xd) <= 1e-9
+    # an initial guess is used: starting from the solution needs no iteration
+    x2 = np.zeros_like(b)
+    st = lat.solve(b, x2, tol=1e-10, even_odd=False, x0=x)
+    assert st.inner_iters == 0 and st.true_rel_resid <= 1e-10
+
+
+def test_unpreconditioned_rejects_mixed_precision():
+    dims = (4, 4, 4, 4)
+    U = fg.gauge_field(dims, 5, "smooth", 0.3)
+    lat = lattice(dims, U, 0.13, 1.0)
+    b = fg.gaussian_spinor(dims, 6)
+    with pytest.raises(lqcd.LqcdError) as e:
+        lat.solve(b, np.zeros_like(b), inner_prec=lqcd.F32, even_odd=False)
+    assert e.value.status == lqcd.EINVAL
