@@ -423,6 +423,35 @@ def run_single(a, torch, lqcd):
     return value, ms_step, config, roof, hop, compare, cpu, inner
 
 
+# algorithmic bytes per site of the batched A_oo^-1 H_oe hop: links (8 x 12
+# reals) and the clover block (72 reals) once per site, the input and output
+# spinor once per site and right-hand side (FP16: 24 codes + the FP32 scale)
+BHOP_SITE = {0: (8 * 96, 576, 192), 1: (8 * 48, 288, 96), 2: (8 * 24, 144, 52)}
+BHOP_FLOPS = HOP_FLOPS + 504  # per site and right-hand side: hop + clover term
+
+
+def batched_hop_roofline(lqcd, lats, nrhs, vhs, prec):
+    """The batched hop's launch shape (autotuned or from the cache) and its
+    roofline: algorithmic bytes per launch over the average launch time, HIP
+    events on the batch's stream (inside the library, 20 launches)."""
+    shape, us = lqcd.batch_autotune(lats, nrhs, prec)
+    links, clov, spin = BHOP_SITE[prec]
+    nbytes = sum(vh * (links + clov + n * 2 * spin) for vh, n in zip(vhs, nrhs))
+    site_rhs = sum(vh * n for vh, n in zip(vhs, nrhs))
+    gbs = nbytes / (us * 1e-6) / 1e9
+    name = {0: "f64", 1: "f32", 2: "f16"}[prec]
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+           "kernel": f"k_bhop<{prec},EPI_SCALE_CLOV> (batched A_oo^-1 H_oe hop, {name} storage, all right-hand "
+                     "sides of all lattices in one launch)",
+           "launch_shape": {"rhs_per_lane": shape[0], "waves_per_workgroup": shape[1], "workgroups_per_xcd": shape[2],
+                            "walk": ["linear", "slab"][shape[3]], "nt_links_clover": shape[4]},
+           "us": round(us, 2), "bytes_per_launch": nbytes,
+           "gflops": round(BHOP_FLOPS * site_rhs / (us * 1e-6) / 1e9, 1)}
+    log(f"batched hop ({name}): {out}")
+    return out
+
+
 def batch_setup(a, torch, lqcd):
     """The three clover lattices of the batched workload with 12 point sources each."""
     stream = torch.cuda.Stream()
@@ -477,13 +506,14 @@ def time_sequential_f64(torch, lqcd, lats, bs, xs):
 def batch_compare(a, torch, lqcd):
     """C4: one batched solve of the 36 right-hand sides with FP32 and with FP16
     inner iterations against 36 sequential FP64 solves."""
-    lats, bs, xs, _ = batch_setup(a, torch, lqcd)
+    lats, bs, xs, vhs = batch_setup(a, torch, lqcd)
     out = {}
     for name, inner in (("batched_f32", lqcd.F32), ("batched_f16", lqcd.F16)):
+        roof = batched_hop_roofline(lqcd, lats, [12] * len(lats), vhs, inner)
         el, stats = time_batched(torch, lqcd, lats, bs, xs, inner, 1, 1)
         out[name] = {"ms": round(1000 * el, 1), "propagators_per_s": round(3 / el, 3),
                      "inner_iters_max": max(s.inner_iters for s in stats),
-                     "true_rel_resid_max": max(s.true_rel_resid for s in stats)}
+                     "true_rel_resid_max": max(s.true_rel_resid for s in stats), "batched_hop": roof}
     seq = time_sequential_f64(torch, lqcd, lats, bs, xs)
     out["sequential_f64"] = {"ms": round(1000 * seq, 1), "propagators_per_s": round(3 / seq, 3)}
     for name in ("batched_f32", "batched_f16"):
@@ -497,6 +527,7 @@ def batch_compare(a, torch, lqcd):
 def run_batch(a, torch, lqcd):
     lats, bs, xs, vhs = batch_setup(a, torch, lqcd)
     inner = lqcd.F32 if a.inner == "f32" else lqcd.F16
+    broof = batched_hop_roofline(lqcd, lats, [12] * len(lats), vhs, inner)
     elapsed, stats = time_batched(torch, lqcd, lats, bs, xs, inner, a.steps, a.warmup)
     seg_vh = [vh for vh in vhs for _ in range(12)]
     flops = sum(HOP_FLOPS * vh * hop_applications(s) for vh, s in zip(seg_vh, stats)) * a.steps
@@ -512,7 +543,8 @@ def run_batch(a, torch, lqcd):
                    "propagators_per_s_sequential_f64": round(3 / seq, 3),
                    "speedup": round(seq / (ms_step / 1000), 3)}
         log(f"batch vs sequential FP64: {compare}")
-    roof, hop = roofline_of(torch, lats[0], lqcd, "f32" if inner == lqcd.F32 else "f16", vhs[0])
+    _, hop = roofline_of(torch, lats[0], lqcd, "f32" if inner == lqcd.F32 else "f16", vhs[0])
+    roof = broof
     config = {"workload": "12 point sources on each of 32^3x64, 24^3x48, 16^3x32 clover lattices (c_SW=1.0, "
                           f"kappa=0.1370, eps=0.3), one batched solve of 36 RHS, {a.inner} inner / f64 outer to 1e-10",
               "step": "one batched solve", "propagators_per_s": round(props, 3), "parallelism": "single GPU"}

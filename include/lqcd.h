@@ -177,6 +177,37 @@ int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const
                      double* const* x, int nlattices, const lqcd_solve_params* prm,
                      lqcd_solve_stats* stats);
 
+/* Launch shape of the batched hop for a batch (the same contexts and nrhs
+ * as a later lqcd_solve_batch call) at inner precision prec, chosen by a
+ * project-written autotuner (the counterpart of the paper's tiling sweep,
+ * Sec. 3): shape = {right-hand sides per lane (1..4; 1..2 in FP64),
+ * wavefronts per workgroup (1..8, one group of right-hand sides each),
+ * workgroups per XCD, tile walk (0: linear in the site index, 1: every XCD
+ * walks its range of blocks of each time slice, slice after slice), 1 for
+ * non-temporal loads of links and clover blocks}. With shape NULL or
+ * shape[0] <= 0 the shape comes from the tune cache (LQCD_TUNE_CACHE) or,
+ * without an entry, from timing every candidate with HIP events on the
+ * batch's own fields (the choice is then written to the cache); otherwise the
+ * given shape is used as is. The batch keeps the shape for the next
+ * lqcd_solve_batch of the same contexts, nrhs and precision (which tunes by
+ * itself when no shape was set). On return shape (if not NULL) holds the
+ * shape in use and *us (if not NULL) the average duration in microseconds of
+ * its A_oo^-1 H_oe hop over all right-hand sides of all lattices, timed with
+ * HIP events on the contexts' stream over 20 launches. Allocates the batch's
+ * fields; EINVAL for a bad shape or precision, otherwise as lqcd_solve_batch. */
+int lqcd_batch_autotune(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, int prec, int shape[5], double* us);
+
+/* out = S in for every right-hand side of a batch, through the batched hop
+ * kernels of lqcd_solve_batch in precision prec (S = D_ee - D_eo D_oo^-1 D_oe
+ * as LQCD_DPREC_SCHUR; Eq. (1)): in[k] and out[k] hold nrhs[k] canonical
+ * full-lattice vectors of lattice k back to back, in device memory; the odd
+ * sites of in are ignored and those of out set to zero. Uses the batch's launch
+ * shape (tuned as in lqcd_solve_batch if none is set). For checking the batched
+ * kernels against single-field applies and the oracle; returns after the
+ * stream is synchronised. EINVAL / ESTATE as lqcd_solve_batch. */
+int lqcd_batch_apply_schur(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, int prec,
+                           const double* const* in, double* const* out);
+
 /* Schwarz alternating procedure (SAP) preconditioner, the smoother of the
  * paper's multigrid solver (Sec. 3): the lattice is cut into blocks of
  * block[0] x block[1] x block[2] x block[3] sites (x, y, z, t), every extent

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblqcd.so")
 SOURCES = ["api.hip", "layout.hip", "hop.hip", "clover.hip", "blas.hip", "ops.hip", "solver.hip", "tune.hip",
-           "batch.hip", "sap.hip", "stag.hip", "dwf.hip", "mg.hip"]
+           "batch.hip", "bhop_f64.hip", "bhop_f32.hip", "bhop_f16.hip", "sap.hip", "stag.hip", "dwf.hip", "mg.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

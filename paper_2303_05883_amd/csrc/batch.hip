@@ -4,16 +4,18 @@
 // rho, alpha, omega; not block Krylov), but every operator step of every
 // unconverged segment of every lattice is ONE persistent kernel launch:
 //
-//  * the hop walks a tile list of (lattice, site block, group of right-hand
-//    sides); a thread computes its site for every right-hand side of its
-//    group, loading each link and clover block once for all of them, and the
-//    groups of one site block are consecutive tiles in one of 8 contiguous
-//    chunks, one per XCD (blocks reach the XCDs round-robin), so links are
-//    reused from that XCD's L2 across groups too (the paper's motivation:
-//    many equations on one gauge field, Sec. 3);
+//  * the hop (bhop.h) walks a tile list of (lattice, 64-site block); the
+//    wavefronts of a workgroup take the groups of right-hand sides of its tile
+//    and a lane computes its site for the nb right-hand sides of its group,
+//    so links and clover blocks come from HBM once per site for all
+//    right-hand sides of the lattice (the paper's motivation: many equations
+//    on one gauge field, Sec. 3);
+//  * its launch shape (right-hand sides per lane, wavefronts per workgroup,
+//    workgroups per XCD) is picked by timing the candidates on the batch
+//    itself the first time a batch shape is seen, and kept in the tune cache;
 //  * vector updates and the fused reductions are batched the same way, with
 //    per-segment partial sums and per-segment finalize blocks;
-//  * converged segments are masked: their tiles return at once;
+//  * converged segments are masked: their waves skip the work;
 //  * check_every iterations of the whole batch are replayed from one captured
 //    hipGraph.
 // The FP64 defect-correction outer loop, the even-odd source preparation and
@@ -25,134 +27,23 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <sstream>
+#include <string>
 #include <vector>
 
+#include "bhop.h"
 #include "blascore.h"
-#include "hopcore.h"
 #include "internal.h"
 #include "ops.h"
 #include "solver.h"
+#include "tune.h"
 
 namespace lq {
 
 namespace {
 
-enum Fld { F_R = 0, F_RHAT, F_P, F_V, F_S, F_T, F_Y, F_X, F_COUNT };
-
-struct BLat {
-  Geom g;
-  const char* gauge;  // links of the inner precision
-  size_t link_stride;
-  const void* clov_e;     // A_ee (slot 0) or null
-  const void* clov_oinv;  // A_oo^-1 (slot 3) or null
-  double kappa;
-  int tile0;   // first hop tile of this lattice
-  int ntile;   // hop tiles: nsb * ceil(nrhs / NB)
-  int nsb;     // hop site blocks
-  int btile0;  // first blas tile
-  int nbb;     // blas blocks
-  int nrhs;
-  int seg0;
-};
-
-struct BSeg {
-  void* f[F_COUNT];
-  Scal* sc;
-  double* partials;
-  int lat;
-};
-
 constexpr int MAXLAT = 16;
-constexpr int BS = 256;
-// right-hand sides per thread in the batched hop (links shared between them)
-template <int P>
-struct RhsBlock {
-  static constexpr int NB = P == 0 ? 2 : 4;
-};
-
-struct BHopArgs {
-  const BLat* lat;
-  const BSeg* seg;
-  int nlat;
-  int in_sel, out_sel, own_sel, w_sel;
-  int out_parity;
-  int clov_slot;      // 0: A_ee, 3: A_oo^-1
-  int scale_mode;     // 0: 1, 1: -kappa^2
-  int bound[9];       // XCD chunk boundaries of the hop tile list
-};
-
-__device__ inline int find_lat(const BLat* lat, int nlat, int tile, bool blas) {
-  int l = 0;
-  for (int k = 1; k < nlat; ++k)
-    if (tile >= (blas ? lat[k].btile0 : lat[k].tile0)) l = k;
-  return l;
-}
-
-// Tiles are (lattice, site block, group of NB right-hand sides), groups
-// fastest; each thread computes one site for the NB right-hand sides of its
-// group (link and clover loads shared).
-template <int P, int EPI, bool CLOV, int RED, bool NT, int NB>
-__global__ void __launch_bounds__(BS) k_bhop(BHopArgs b) {
-  constexpr int NR = RED == RED_DOT ? 2 : (RED == RED_TS ? 3 : 0);
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, nslot = gridDim.x >> 3;
-  for (int t = b.bound[xcd] + slot; t < b.bound[xcd + 1]; t += nslot) {
-    const int l = find_lat(b.lat, b.nlat, t, false);
-    const BLat& L = b.lat[l];
-    const int ngroup = (L.nrhs + NB - 1) / NB;
-    const int local = t - L.tile0;
-    const int sb = local / ngroup, grp = local % ngroup;
-    MultiPtrs<NB> m;
-    m.act = 0u;
-    int segs[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int r = grp * NB + q;
-      segs[q] = -1;
-      m.in[q] = nullptr;
-      m.out[q] = nullptr;
-      m.own[q] = nullptr;
-      m.w[q] = nullptr;
-      if (r < L.nrhs) {
-        const BSeg& S = b.seg[L.seg0 + r];
-        segs[q] = L.seg0 + r;
-        if (!S.sc->done) m.act |= 1u << q;  // uniform over the block
-        m.in[q] = S.f[b.in_sel];
-        m.out[q] = S.f[b.out_sel];
-        m.own[q] = b.own_sel >= 0 ? S.f[b.own_sel] : nullptr;
-        m.w[q] = b.w_sel >= 0 ? S.f[b.w_sel] : nullptr;
-      }
-    }
-    if (m.act == 0u) continue;
-    HopArgs a;
-    a.in = nullptr;
-    a.out = nullptr;
-    a.gauge = L.gauge;
-    a.link_stride = L.link_stride;
-    a.clov = b.clov_slot == 0 ? L.clov_e : L.clov_oinv;
-    a.xown = nullptr;
-    a.w = nullptr;
-    a.partials = nullptr;
-    a.skip = nullptr;
-    a.scale = b.scale_mode == 0 ? 1.0 : -L.kappa * L.kappa;
-    a.g = L.g;
-    a.p = b.out_parity;
-    a.remap = 0;
-    a.hz = 0;
-    const size_t i = (size_t)sb * BS + threadIdx.x;
-    double red[NB][3];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) red[q][0] = red[q][1] = red[q][2] = 0.0;
-    if (i < (size_t)L.g.vh) hop_site_multi<P, EPI, CLOV, RED, NT, NB>(a, m, i, red);
-    if constexpr (NR > 0) {
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        if (!((m.act >> q) & 1u)) continue;
-        block_reduce<NR>(red[q], b.seg[segs[q]].partials + (size_t)sb * NR);
-        __syncthreads();
-      }
-    }
-  }
-}
+constexpr int BS = 256;  // sites per workgroup of the batched vector updates
 
 enum BOp { B_P_UPDATE = 0, B_S_UPDATE, B_XR_UPDATE, B_START };
 
@@ -254,6 +145,13 @@ struct Batch {
   std::vector<std::pair<int, int>> key;
   Scal* dscal_all = nullptr;
   bool ready = false;  // every buffer allocated
+  BShape shape;        // launch shape of the batched hop
+  bool tuned = false;  // shape chosen for this batch
+  int2* dtiles = nullptr;  // device tile list of the current shape
+  size_t tile_cap = 0;     // its capacity (tiles of the largest shape)
+  std::vector<int2> htiles;
+  double hop_us = 0;   // its average duration when timed (microseconds)
+  int max_rhs = 1;
 
   ~Batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -278,6 +176,7 @@ int batch_hop(Batch& B, hipStream_t s, int in_sel, int out_sel, int own_sel, int
   BHopArgs a;
   a.lat = B.dlat;
   a.seg = B.dseg;
+  a.tiles = B.dtiles;
   a.nlat = (int)B.hlat.size();
   a.in_sel = in_sel;
   a.out_sel = out_sel;
@@ -287,29 +186,9 @@ int batch_hop(Batch& B, hipStream_t s, int in_sel, int out_sel, int own_sel, int
   a.clov_slot = clov_slot;
   a.scale_mode = scale_mode;
   for (int k = 0; k < 9; ++k) a.bound[k] = B.bound[k];
-  const int grid = 8 * 256;  // persistent: 256 blocks per XCD
-  const bool cl = B.clover;
-#define LQ_BHOP(P)                                                                                       \
-  if (epi == EPI_SCALE_CLOV) {                                                                           \
-    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_SCALE_CLOV, true, RED_NONE, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a); \
-    else hipLaunchKernelGGL((k_bhop<P, EPI_SCALE, false, RED_NONE, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);      \
-  } else if (red == RED_DOT) {                                                                           \
-    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, true, RED_DOT, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);        \
-    else hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, false, RED_DOT, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);          \
-  } else {                                                                                               \
-    if (cl) hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, true, RED_TS, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);         \
-    else hipLaunchKernelGGL((k_bhop<P, EPI_XPAY, false, RED_TS, true, RhsBlock<P>::NB>), dim3(grid), dim3(BS), 0, s, a);           \
-  }
-  if (B.prec == 1) {
-    LQ_BHOP(1)
-  } else if (B.prec == 2) {
-    LQ_BHOP(2)
-  } else {
-    LQ_BHOP(0)
-  }
-#undef LQ_BHOP
-  LQ_HIP(hipGetLastError());
-  return LQCD_OK;
+  if (B.prec == 1) return launch_bhop<1>(a, B.shape, epi, red, B.clover, s);
+  if (B.prec == 2) return launch_bhop<2>(a, B.shape, epi, red, B.clover, s);
+  return launch_bhop<0>(a, B.shape, epi, red, B.clover, s);
 }
 
 template <int OP>
@@ -392,40 +271,81 @@ int seg_norm(lqcd_ctx* c, const void* a, double* dst) {
 
 void free_batch(void* p) { delete reinterpret_cast<Batch*>(p); }
 
-}  // namespace
+// Make sh the batch's launch shape: the tile list of its walk and group sets,
+// dealt to the XCDs in 8 contiguous chunks, uploaded (on the batch's stream)
+// and a captured iteration graph dropped (its launches hold the old shape).
+int set_shape(Batch& B, const BShape& sh) {
+  std::vector<int2>& tl = B.htiles;
+  tl.clear();
+  for (int k = 0; k < 8; ++k) {
+    B.bound[k] = (int)tl.size();
+    for (size_t l = 0; l < B.hlat.size(); ++l) {
+      const BLat& L = B.hlat[l];
+      const int ngroup = (L.nrhs + sh.nb - 1) / sh.nb;
+      const int nset = (ngroup + sh.nw - 1) / sh.nw;
+      const size_t vh = L.g.vh;
+      const size_t per_t = vh / (size_t)L.g.lt;  // sites of one parity in a time slice
+      auto push = [&](int blk) {
+        for (int gs = 0; gs < nset; ++gs) tl.push_back(make_int2((int)l | (gs << 8), blk));
+      };
+      if (sh.walk == 1 && per_t % SB == 0) {
+        // slab walk: this XCD's range of blocks in every time slice, slices in order
+        const int nbt = (int)(per_t / SB);
+        const int lo = (int)((long long)nbt * k / 8), hi = (int)((long long)nbt * (k + 1) / 8);
+        for (int t = 0; t < L.g.lt; ++t)
+          for (int bb = lo; bb < hi; ++bb) push(t * nbt + bb);
+      } else {
+        const int lo = (int)((long long)L.nsb * k / 8), hi = (int)((long long)L.nsb * (k + 1) / 8);
+        for (int bb = lo; bb < hi; ++bb) push(bb);
+      }
+    }
+  }
+  B.bound[8] = (int)tl.size();
+  if (tl.size() > B.tile_cap) return set_error(LQCD_EINVAL, "batched hop tile list exceeds its buffer");
+  LQ_HIP(hipMemcpyAsync(B.dtiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, B.stream));
+  B.shape = sh;
+  if (B.exec) {
+    (void)hipStreamSynchronize(B.stream);
+    (void)hipGraphExecDestroy(B.exec);
+    B.exec = nullptr;
+  }
+  if (B.graph) {
+    (void)hipGraphDestroy(B.graph);
+    B.graph = nullptr;
+  }
+  return LQCD_OK;
+}
 
-}  // namespace lq
-
-using namespace lq;
-
-extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const* b, double* const* x,
-                                int nlattices, const lqcd_solve_params* prm_in, lqcd_solve_stats* stats) {
-  using clk = std::chrono::steady_clock;
-  const auto t0 = clk::now();
-  if (!ctxs || !nrhs || !b || !x || nlattices < 1 || nlattices > MAXLAT)
+// Check a batch's contexts (one stream, all clover or all Wilson, gauge and
+// clover set, no context twice).
+int batch_check(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, bool* clover) {
+  if (!ctxs || !nrhs || nlattices < 1 || nlattices > MAXLAT)
     return set_error(LQCD_EINVAL, "bad batch arguments (1 to 16 lattices)");
-  lqcd_solve_params prm;
-  if (prm_in) prm = *prm_in;
-  else lqcd_default_params(&prm);
-  if (!(prm.tol > 0) || prm.inner_prec < 0 || prm.inner_prec > 2 || prm.max_iter < 1 || prm.max_outer < 1)
-    return set_error(LQCD_EINVAL, "bad solver parameters");
-  if (prm.x0) return set_error(LQCD_EINVAL, "batched solves start from x = 0");
-  if (prm.even_odd != 1) return set_error(LQCD_EINVAL, "batched solves are even-odd preconditioned");
   hipStream_t stream = ctxs[0] ? ctxs[0]->stream : nullptr;
-  bool clover = false;
   for (int l = 0; l < nlattices; ++l) {
     lqcd_ctx* c = ctxs[l];
-    if (!c || !b[l] || !x[l] || nrhs[l] < 1) return set_error(LQCD_EINVAL, "null context, vector or nrhs < 1");
+    if (!c || nrhs[l] < 1) return set_error(LQCD_EINVAL, "null context or nrhs < 1");
     if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
     if (c->stream != stream) return set_error(LQCD_EINVAL, "all contexts of a batch must share one stream");
-    if (l == 0) clover = !c->is_wilson;
-    else if (clover != !c->is_wilson) return set_error(LQCD_EINVAL, "a batch is all clover or all Wilson");
+    if (l == 0) *clover = !c->is_wilson;
+    else if (*clover != !c->is_wilson) return set_error(LQCD_EINVAL, "a batch is all clover or all Wilson");
     for (int m = 0; m < l; ++m)
       if (ctxs[m] == c) return set_error(LQCD_EINVAL, "a context appears twice in the batch");
   }
-  const int IP = prm.inner_prec;
+  return LQCD_OK;
+}
+
+// The batch of these contexts at inner precision IP: descriptors rebuilt from
+// the current contexts, buffers allocated when the batch shape is new (kept
+// on the first context for the next call with the same shape).
+int batch_prepare(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, int IP, bool clover, Batch** out) {
+  hipStream_t stream = ctxs[0]->stream;
   std::vector<std::pair<int, int>> key;
-  for (int l = 0; l < nlattices; ++l) key.push_back({ctxs[l]->g.vh, nrhs[l]});
+  for (int l = 0; l < nlattices; ++l) {
+    const Geom& g = ctxs[l]->g;
+    key.push_back({g.lx | (g.ly << 16), g.lz | (g.lt << 16)});
+    key.push_back({g.vh, nrhs[l]});
+  }
   key.push_back({IP, clover ? 1 : 0});
   lqcd_ctx* lead = ctxs[0];
   Batch* cached = reinterpret_cast<Batch*>(lead->batch);
@@ -445,20 +365,15 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   B.prec = IP;
   B.xprec = IP == 2 ? 1 : IP;
   B.clover = clover;
-  const int check = prm.check_every > 0 ? prm.check_every : 8;
-  const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : (IP == 2 ? 1e-2 : 1e-10));
-
-  // descriptors (rebuilt every call from the current contexts) and buffers
-  // (allocated when the batch shape is new)
   int total_seg = 0;
   for (int l = 0; l < nlattices; ++l) total_seg += nrhs[l];
   if (!reuse) {
     B.key = key;
     LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dscal_all), (size_t)total_seg * sizeof(Scal)));
   }
-  Scal* dscal_all = B.dscal_all;
   B.hlat.clear();
   B.ctx.clear();
+  B.max_rhs = 1;
   int tile = 0, btile = 0, seg = 0;
   for (int l = 0; l < nlattices; ++l) {
     lqcd_ctx* c = ctxs[l];
@@ -470,18 +385,15 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
     L.clov_e = clover ? c->clov[IP][0] : nullptr;
     L.clov_oinv = clover ? c->clov[IP][3] : nullptr;
     L.kappa = c->kappa;
-    L.nsb = (c->g.vh + BS - 1) / BS;
-    L.nbb = L.nsb;
+    L.nsb = (int)(padded_sites(c->g.vh) / SB);
+    L.nbb = (c->g.vh + BS - 1) / BS;
     L.nrhs = nrhs[l];
     L.tile0 = tile;
-    {
-      const int nbk = IP == 0 ? RhsBlock<0>::NB : RhsBlock<1>::NB;
-      L.ntile = L.nsb * ((L.nrhs + nbk - 1) / nbk);
-    }
     L.btile0 = btile;
     L.seg0 = seg;
-    tile += L.ntile;
+    tile += L.nsb;
     btile += L.nbb * L.nrhs;
+    B.max_rhs = std::max(B.max_rhs, L.nrhs);
     B.hlat.push_back(L);
     B.ctx.push_back(c);
     for (int r = 0; r < nrhs[l]; ++r, ++seg) {
@@ -490,7 +402,8 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
       const size_t vh = c->g.vh;
       for (int f = 0; f < F_COUNT; ++f)
         LQ_TRY(B.dev_alloc(&S.f[f], spinor_bytes(f == F_X ? B.xprec : IP, vh)));
-      S.sc = dscal_all + seg;
+      S.sc = B.dscal_all + seg;
+      // partial sums: 3 per 64-site hop block (more than per BS-site vector block)
       LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&S.partials), (size_t)L.nsb * 3 * sizeof(double)));
       S.lat = l;
       B.hseg.push_back(S);
@@ -503,8 +416,11 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   const int nseg = seg;
   B.hop_tiles = tile;
   B.blas_tiles = btile;
-  for (int k = 0; k <= 8; ++k) B.bound[k] = (int)((long long)tile * k / 8);
   if (!reuse) {
+    size_t cap = 0;
+    for (const BLat& L : B.hlat) cap += (size_t)L.nsb * L.nrhs;
+    B.tile_cap = cap;
+    LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dtiles), cap * sizeof(int2)));
     LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dlat), B.hlat.size() * sizeof(BLat)));
     LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dseg), B.hseg.size() * sizeof(BSeg)));
     LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.snorm), (size_t)nseg * 16 * sizeof(double)));
@@ -516,6 +432,161 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   }
   LQ_HIP(hipMemcpyAsync(B.dlat, B.hlat.data(), B.hlat.size() * sizeof(BLat), hipMemcpyHostToDevice, stream));
   LQ_HIP(hipMemcpyAsync(B.dseg, B.hseg.data(), B.hseg.size() * sizeof(BSeg), hipMemcpyHostToDevice, stream));
+  *out = &B;
+  return LQCD_OK;
+}
+
+
+std::string batch_key(const Batch& B) {
+  std::ostringstream o;
+  o << "batch:" << B.prec << ":" << (B.clover ? 1 : 0) << ":";
+  for (size_t l = 0; l < B.hlat.size(); ++l) {
+    const Geom& g = B.hlat[l].g;
+    o << (l ? "," : "") << g.lx << "." << g.ly << "." << g.lz << "." << g.lt << "x" << B.hlat[l].nrhs;
+  }
+  return o.str();
+}
+
+bool shape_ok(const Batch& B, const BShape& sh) {
+  const int max_nb = B.prec == 0 ? 2 : 4;
+  return sh.nb >= 1 && sh.nb <= max_nb && sh.nw >= 1 && sh.nw <= BHOP_MAX_WAVES && sh.nslot >= 1 &&
+         sh.nslot <= 4096 && (sh.walk == 0 || sh.walk == 1) && (sh.nt == 0 || sh.nt == 1);
+}
+
+// Average duration (us) of the batched A_oo^-1 H_oe hop (the first hop of the
+// Schur operator, input F_P, output F_Y) with shape sh, HIP events on the
+// batch's stream, reps launches after two warm-up launches.
+int time_bhop(Batch& B, const BShape& sh, int reps, double* us) {
+  LQ_TRY(set_shape(B, sh));
+  hipEvent_t e0, e1;
+  LQ_HIP(hipEventCreate(&e0));
+  LQ_HIP(hipEventCreate(&e1));
+  int st = LQCD_OK;
+  for (int k = 0; k < 2 && st == LQCD_OK; ++k) st = batch_hop(B, B.stream, F_P, F_Y, -1, -1, 1, EPI_SCALE_CLOV, RED_NONE, 3, 0);
+  (void)hipEventRecord(e0, B.stream);
+  for (int k = 0; k < reps && st == LQCD_OK; ++k)
+    st = batch_hop(B, B.stream, F_P, F_Y, -1, -1, 1, EPI_SCALE_CLOV, RED_NONE, 3, 0);
+  (void)hipEventRecord(e1, B.stream);
+  (void)hipEventSynchronize(e1);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  LQ_TRY(st);
+  *us = 1000.0 * ms / reps;
+  return LQCD_OK;
+}
+
+// Pick the batched hop's launch shape for this batch (right-hand sides per
+// lane x wavefronts per workgroup x workgroups per XCD) by timing every
+// candidate on the batch's own fields; a forced shape (nb > 0) is only timed.
+// The choice is read from and written to the tune cache (LQCD_TUNE_CACHE).
+int batch_tune(Batch& B, bool sweep, const BShape* forced = nullptr) {
+  const std::string key = batch_key(B);
+  if (!sweep && !forced) {
+    int v[4];
+    if (tune_cache_get(key, v)) {
+      BShape sh;
+      sh.nw = v[0] / 64;
+      sh.nb = v[1];
+      sh.nslot = v[2];
+      sh.walk = v[3] & 1;
+      sh.nt = (v[3] >> 1) & 1;
+      if (shape_ok(B, sh)) {
+        LQ_TRY(set_shape(B, sh));
+        B.tuned = true;
+        return LQCD_OK;
+      }
+    }
+  }
+  // the timed launches read zeroed fields of every segment, none masked
+  for (size_t s = 0; s < B.hseg.size(); ++s) {
+    lqcd_ctx* c = B.ctx[B.seg_lat[s]];
+    LQ_TRY(blas_zero(c, B.prec, B.hseg[s].f[F_P]));
+  }
+  LQ_HIP(hipMemsetAsync(B.dscal_all, 0, B.hseg.size() * sizeof(Scal), B.stream));
+  std::vector<BShape> cand;
+  if (forced) {
+    if (!shape_ok(B, *forced)) return set_error(LQCD_EINVAL, "bad batched hop launch shape");
+    cand.push_back(*forced);
+  } else {
+    for (int nb = 1; nb <= (B.prec == 0 ? 2 : 4); ++nb) {
+      const int ngroup = (B.max_rhs + nb - 1) / nb;
+      for (int nw : {1, std::min(BHOP_MAX_WAVES, ngroup)})
+        for (int nslot : {128, 256})
+          for (int walk = 0; walk < 2; ++walk)
+            for (int nt = 0; nt < 2; ++nt) {
+              BShape sh;
+              sh.nb = nb;
+              sh.nw = nw;
+              sh.nslot = nslot;
+              sh.walk = walk;
+              sh.nt = nt;
+              bool dup = false;
+              for (const BShape& c : cand)
+                dup = dup || (c.nb == sh.nb && c.nw == sh.nw && c.nslot == sh.nslot && c.walk == sh.walk &&
+                              c.nt == sh.nt);
+              if (!dup) cand.push_back(sh);
+            }
+    }
+  }
+  const bool verbose = std::getenv("LQCD_TUNE_VERBOSE") != nullptr;
+  BShape best = cand[0];
+  double best_us = 1e30;
+  for (const BShape& sh : cand) {
+    double us = 0;
+    LQ_TRY(time_bhop(B, sh, 5, &us));
+    if (verbose)
+      std::fprintf(stderr, "[lqcd tune] %s nb %d nw %d nslot %d walk %d nt %d: %.1f us\n", key.c_str(), sh.nb,
+                   sh.nw, sh.nslot, sh.walk, sh.nt, us);
+    if (us < best_us) {
+      best_us = us;
+      best = sh;
+    }
+  }
+  LQ_TRY(set_shape(B, best));
+  B.hop_us = best_us;
+  B.tuned = true;
+  if (!forced) {
+    const int v[4] = {64 * best.nw, best.nb, best.nslot, best.walk | (best.nt << 1)};
+    LQ_TRY(tune_cache_put(key, v, best_us));
+  }
+  return LQCD_OK;
+}
+
+}  // namespace
+
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const* b, double* const* x,
+                                int nlattices, const lqcd_solve_params* prm_in, lqcd_solve_stats* stats) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  if (!ctxs || !nrhs || !b || !x || nlattices < 1 || nlattices > MAXLAT)
+    return set_error(LQCD_EINVAL, "bad batch arguments (1 to 16 lattices)");
+  lqcd_solve_params prm;
+  if (prm_in) prm = *prm_in;
+  else lqcd_default_params(&prm);
+  if (!(prm.tol > 0) || prm.inner_prec < 0 || prm.inner_prec > 2 || prm.max_iter < 1 || prm.max_outer < 1)
+    return set_error(LQCD_EINVAL, "bad solver parameters");
+  if (prm.x0) return set_error(LQCD_EINVAL, "batched solves start from x = 0");
+  if (prm.even_odd != 1) return set_error(LQCD_EINVAL, "batched solves are even-odd preconditioned");
+  for (int l = 0; l < nlattices; ++l)
+    if (!b[l] || !x[l]) return set_error(LQCD_EINVAL, "null vector");
+  bool clover = false;
+  LQ_TRY(batch_check(ctxs, nrhs, nlattices, &clover));
+  hipStream_t stream = ctxs[0]->stream;
+  const int IP = prm.inner_prec;
+  Batch* Bp = nullptr;
+  LQ_TRY(batch_prepare(ctxs, nrhs, nlattices, IP, clover, &Bp));
+  Batch& B = *Bp;
+  if (!B.tuned) LQ_TRY(batch_tune(B, false));
+  Scal* dscal_all = B.dscal_all;
+  const int nseg = (int)B.hseg.size();
+  const int check = prm.check_every > 0 ? prm.check_every : 8;
+  const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : (IP == 2 ? 1e-2 : 1e-10));
 
   // import and prepare every segment: b', |b|^2, x = 0, r = b'
   for (int s = 0; s < nseg; ++s) {
@@ -684,4 +755,75 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
       st.seconds_setup = setup_s;
     }
   return status;
+}
+
+extern "C" int lqcd_batch_autotune(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, int prec, int shape[5],
+                                   double* us) {
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  bool clover = false;
+  LQ_TRY(batch_check(ctxs, nrhs, nlattices, &clover));
+  Batch* Bp = nullptr;
+  LQ_TRY(batch_prepare(ctxs, nrhs, nlattices, prec, clover, &Bp));
+  Batch& B = *Bp;
+  if (shape && shape[0] > 0) {
+    BShape sh;
+    sh.nb = shape[0];
+    sh.nw = shape[1];
+    sh.nslot = shape[2];
+    sh.walk = shape[3];
+    sh.nt = shape[4];
+    LQ_TRY(batch_tune(B, false, &sh));
+  } else {
+    B.tuned = false;
+    LQ_TRY(batch_tune(B, false));
+  }
+  // time the chosen shape on its own (also after a cache hit)
+  double t = 0;
+  LQ_TRY(time_bhop(B, B.shape, 20, &t));
+  B.hop_us = t;
+  if (us) *us = t;
+  if (shape) {
+    shape[0] = B.shape.nb;
+    shape[1] = B.shape.nw;
+    shape[2] = B.shape.nslot;
+    shape[3] = B.shape.walk;
+    shape[4] = B.shape.nt;
+  }
+  LQ_HIP(hipStreamSynchronize(B.stream));
+  return LQCD_OK;
+}
+
+extern "C" int lqcd_batch_apply_schur(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, int prec,
+                                      const double* const* in, double* const* out) {
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  if (!in || !out) return set_error(LQCD_EINVAL, "null vector list");
+  bool clover = false;
+  LQ_TRY(batch_check(ctxs, nrhs, nlattices, &clover));
+  for (int l = 0; l < nlattices; ++l)
+    if (!in[l] || !out[l]) return set_error(LQCD_EINVAL, "null vector");
+  Batch* Bp = nullptr;
+  LQ_TRY(batch_prepare(ctxs, nrhs, nlattices, prec, clover, &Bp));
+  Batch& B = *Bp;
+  if (!B.tuned) LQ_TRY(batch_tune(B, false));
+  // every segment active: S in -> out through the two batched hops of the solver
+  LQ_HIP(hipMemsetAsync(B.dscal_all, 0, B.hseg.size() * sizeof(Scal), B.stream));
+  for (size_t s = 0; s < B.hseg.size(); ++s) {
+    const int l = B.seg_lat[s];
+    lqcd_ctx* c = B.ctx[l];
+    const size_t n = (size_t)c->g.vh * 2 * 24;
+    const double* src = in[l] + (size_t)(s - B.hlat[l].seg0) * n;
+    LQ_TRY(launch_import_spinor(c, prec, 0, src, B.hseg[s].f[F_P]));
+  }
+  LQ_TRY(batch_hop(B, B.stream, F_P, F_Y, -1, -1, 1, EPI_SCALE_CLOV, RED_NONE, 3, 0));
+  LQ_TRY(batch_hop(B, B.stream, F_Y, F_T, F_P, -1, 0, EPI_XPAY, RED_TS, 0, 1));
+  for (size_t s = 0; s < B.hseg.size(); ++s) {
+    const int l = B.seg_lat[s];
+    lqcd_ctx* c = B.ctx[l];
+    const size_t n = (size_t)c->g.vh * 2 * 24;
+    double* dst = out[l] + (size_t)(s - B.hlat[l].seg0) * n;
+    LQ_HIP(hipMemsetAsync(dst, 0, n * sizeof(double), B.stream));
+    LQ_TRY(launch_export_spinor(c, prec, 0, B.hseg[s].f[F_T], dst));
+  }
+  LQ_HIP(hipStreamSynchronize(B.stream));
+  return LQCD_OK;
 }

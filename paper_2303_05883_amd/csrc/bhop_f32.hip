@@ -1,0 +1,15 @@
+// Batched hop kernels with FP32 fields (see bhop.h).
+#include "bhop.h"
+
+namespace lq {
+
+template <>
+int launch_bhop<1>(const BHopArgs& a, const BShape& sh, int epi, int red, bool clov, hipStream_t s) {
+  LQ_BHOP_LAUNCH_NB(1, 1)
+  LQ_BHOP_LAUNCH_NB(1, 2)
+  LQ_BHOP_LAUNCH_NB(1, 3)
+  LQ_BHOP_LAUNCH_NB(1, 4)
+  return set_error(LQCD_EINVAL, "unsupported right-hand sides per lane in the batched hop");
+}
+
+}  // namespace lq

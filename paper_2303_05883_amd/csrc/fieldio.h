@@ -83,6 +83,15 @@ struct IO<0> {
       s[k] = {v.x, v.y};
     }
   }
+  // the spinor as stored and its scale (1 here; FP16 fields store codes and a scale)
+  __device__ static inline void load_spinor_codes(const void* f, size_t i, cx<T> s[12], T& scale) {
+    load_spinor(f, i, s);
+    scale = T(1);
+  }
+  __device__ static inline void load_half_codes(const void* f, size_t i, bool upper, cx<T> s[6], T& scale) {
+    load_half(f, i, upper, s);
+    scale = T(1);
+  }
   __device__ static inline void store_spinor(void* f, size_t i, const cx<T> s[12]) {
     double2* b = reinterpret_cast<double2*>(f);
 #pragma unroll
@@ -105,11 +114,12 @@ struct IO<0> {
     }
   }
   // 18 complex slots of one chiral block (blk = 0: +, 1: -)
+  template <bool NT = false>
   __device__ static inline void load_clover_block(const void* c, size_t i, int blk, cx<T> m[18]) {
     const double2* b = reinterpret_cast<const double2*>(c);
 #pragma unroll
     for (int k = 0; k < 18; ++k) {
-      double2 v = b[widx(i, blk * 18 + k, 36)];
+      double2 v = ld16<NT>(b + widx(i, blk * 18 + k, 36));
       m[k] = {v.x, v.y};
     }
   }
@@ -149,6 +159,14 @@ struct IO<1> {
       s[2 * k + 1] = {v.z, v.w};
     }
   }
+  __device__ static inline void load_spinor_codes(const void* f, size_t i, cx<T> s[12], T& scale) {
+    load_spinor(f, i, s);
+    scale = T(1);
+  }
+  __device__ static inline void load_half_codes(const void* f, size_t i, bool upper, cx<T> s[6], T& scale) {
+    load_half(f, i, upper, s);
+    scale = T(1);
+  }
   __device__ static inline void store_spinor(void* f, size_t i, const cx<T> s[12]) {
     float4* b = reinterpret_cast<float4*>(f);
 #pragma unroll
@@ -171,11 +189,12 @@ struct IO<1> {
       u[2 * k + 1] = {v.z, v.w};
     }
   }
+  template <bool NT = false>
   __device__ static inline void load_clover_block(const void* c, size_t i, int blk, cx<T> m[18]) {
     const float4* b = reinterpret_cast<const float4*>(c);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      float4 v = b[widx(i, blk * 9 + k, 18)];
+      float4 v = ld16<NT>(b + widx(i, blk * 9 + k, 18));
       m[2 * k] = {v.x, v.y};
       m[2 * k + 1] = {v.z, v.w};
     }
@@ -208,6 +227,33 @@ struct IO<2> {
       half8 v = b[k * SB];
 #pragma unroll
       for (int j = 0; j < 4; ++j) s[4 * k + j] = {n * (float)v[2 * j], n * (float)v[2 * j + 1]};
+    }
+  }
+  // the codes (the spinor in units of its scale) and the scale
+  __device__ static inline void load_spinor_codes(const void* f, size_t i, cx<T> s[12], T& sc) {
+    const half8* b = words(f, i);
+    sc = *scale(f, i);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      half8 v = b[k * SB];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[4 * k + j] = {(float)v[2 * j], (float)v[2 * j + 1]};
+    }
+  }
+  // spins 0,1 (complex 0..5: word 0, first half of word 1) or spins 2,3
+  // (second half of word 1, word 2), converting only those
+  __device__ static inline void load_half_codes(const void* f, size_t i, bool upper, cx<T> s[6], T& sc) {
+    const half8* b = words(f, i);
+    sc = *scale(f, i);
+    const half8 w1 = b[SB];
+    const half8 w02 = b[upper ? 0 : 2 * SB];
+    const int o = upper ? 0 : 2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[o + j] = {(float)w02[2 * j], (float)w02[2 * j + 1]};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int jj = upper ? j : j + 2;
+      s[(upper ? 4 : 0) + j] = {(float)w1[2 * jj], (float)w1[2 * jj + 1]};
     }
   }
   // the FP16 words mix spins 1 and 2, so every selection loads the whole spinor
@@ -252,12 +298,14 @@ struct IO<2> {
     }
   }
   // block + is complex 0..17 (words 0..4), block - is complex 18..35 (words 4..8)
+  template <bool NT = false>
   __device__ static inline void load_clover_block(const void* c, size_t i, int blk, cx<T> m[18]) {
     const half8* b = reinterpret_cast<const half8*>(c);
     cx<T> part[20];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      half8 v = b[widx(i, blk * 4 + k, 9)];
+      const half8* q = b + widx(i, blk * 4 + k, 9);
+      half8 v = NT ? __builtin_nontemporal_load(q) : *q;
 #pragma unroll
       for (int j = 0; j < 4; ++j) part[4 * k + j] = {(float)v[2 * j], (float)v[2 * j + 1]};
     }
@@ -304,9 +352,9 @@ __device__ inline void clover_apply(const void* clov, size_t i, const cx<typenam
     chp[k] = in[k] - in[k + 6];
     chm[k] = in[k] + in[k + 6];
   }
-  IO<P>::load_clover_block(clov, i, 0, m);
+  IO<P>::template load_clover_block<false>(clov, i, 0, m);
   herm6_mul(m, chp, yp);
-  IO<P>::load_clover_block(clov, i, 1, m);
+  IO<P>::template load_clover_block<false>(clov, i, 1, m);
   herm6_mul(m, chm, ym);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {

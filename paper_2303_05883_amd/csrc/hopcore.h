@@ -259,7 +259,10 @@ __device__ inline void hop_site(const HopArgs& a, size_t i, double red[3]) {
 // NB right-hand sides of one lattice at one site: each link (and its rebuilt
 // third row) is loaded once per direction and applied to every right-hand
 // side, so the link traffic per site-RHS falls by NB. act has bit r set for
-// the right-hand sides to compute (uniform over a block).
+// the right-hand sides to compute (uniform over a wavefront). The arithmetic is
+// written as fused multiply-adds (four per complex multiply-accumulate): with
+// the links shared, the multiply-RHS hop is bounded by vector issue as much as
+// by memory.
 template <int NB>
 struct MultiPtrs {
   const void* in[NB];
@@ -269,9 +272,67 @@ struct MultiPtrs {
   unsigned act;
 };
 
+__device__ inline float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// c + a b and c + conj(a) b
+template <typename T>
+__device__ inline cx<T> cmadd(cx<T> a, cx<T> b, cx<T> c) {
+  return {fmat(-a.i, b.i, fmat(a.r, b.r, c.r)), fmat(a.i, b.r, fmat(a.r, b.i, c.i))};
+}
+template <typename T>
+__device__ inline cx<T> cmaddc(cx<T> a, cx<T> b, cx<T> c) {
+  return {fmat(a.i, b.i, fmat(a.r, b.r, c.r)), fmat(-a.i, b.r, fmat(a.r, b.i, c.i))};
+}
+// c + f z, c + f (i z), c - f (i z) for a real factor f
+template <typename T>
+__device__ inline cx<T> caxpy(T f, cx<T> z, cx<T> c) {
+  return {fmat(f, z.r, c.r), fmat(f, z.i, c.i)};
+}
+template <typename T>
+__device__ inline cx<T> caxpy_i(T f, cx<T> z, cx<T> c) {
+  return {fmat(-f, z.i, c.r), fmat(f, z.r, c.i)};
+}
+template <typename T>
+__device__ inline cx<T> caxpy_mi(T f, cx<T> z, cx<T> c) {
+  return {fmat(f, z.i, c.r), fmat(-f, z.r, c.i)};
+}
+
+// acc += f * (the four-spinor of w = U h for direction MU), f real: the
+// projection's factor (2 and the boundary sign in t) and the FP16 scale.
+template <int MU, bool FWD, typename T>
+__device__ inline void expand_f(cx<T> acc[12], const cx<T> w[6], T f) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<T> w0 = w[c], w1 = w[3 + c];
+    if (MU == 3) {
+      if (FWD) {
+        acc[6 + c] = caxpy(f, w0, acc[6 + c]);
+        acc[9 + c] = caxpy(f, w1, acc[9 + c]);
+      } else {
+        acc[c] = caxpy(f, w0, acc[c]);
+        acc[3 + c] = caxpy(f, w1, acc[3 + c]);
+      }
+      continue;
+    }
+    acc[c] = caxpy(f, w0, acc[c]);
+    acc[3 + c] = caxpy(f, w1, acc[3 + c]);
+    if (MU == 0) {  // lower = -+ i sigma_x w = -+ i (w1, w0)
+      acc[6 + c] = FWD ? caxpy_mi(f, w1, acc[6 + c]) : caxpy_i(f, w1, acc[6 + c]);
+      acc[9 + c] = FWD ? caxpy_mi(f, w0, acc[9 + c]) : caxpy_i(f, w0, acc[9 + c]);
+    } else if (MU == 1) {  // -+ i sigma_y w = -+ (w1, -w0)
+      acc[6 + c] = caxpy(FWD ? -f : f, w1, acc[6 + c]);
+      acc[9 + c] = caxpy(FWD ? f : -f, w0, acc[9 + c]);
+    } else {  // -+ i sigma_z w = -+ (i w0, -i w1)
+      acc[6 + c] = FWD ? caxpy_mi(f, w0, acc[6 + c]) : caxpy_i(f, w0, acc[6 + c]);
+      acc[9 + c] = FWD ? caxpy_i(f, w1, acc[9 + c]) : caxpy_mi(f, w1, acc[9 + c]);
+    }
+  }
+}
+
 template <int P, int MU, bool FWD, bool NT, int NB>
-__device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, size_t vh, size_t nbr, size_t lidx,
-                                     bool flip, cx<typename IO<P>::T> acc[NB][12]) {
+__device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, size_t nbr, size_t lidx, bool flip,
+                                     cx<typename IO<P>::T> acc[NB][12]) {
   using T = typename IO<P>::T;
   cx<T> u[6], r2[3];
   IO<P>::template load_link<NT>(links, lidx, u);
@@ -281,15 +342,14 @@ __device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, 
   for (int r = 0; r < NB; ++r) {
     if (!((m.act >> r) & 1u)) continue;
     cx<T> h[6];
+    T f;
     if (MU == 3) {
-      cx<T> half[6];
-      IO<P>::load_half(m.in[r], nbr, !FWD, half);
-      const T two = flip ? T(-2) : T(2);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) h[k] = two * half[k];
+      // (1 - gamma_t) psi = 2 (0, 0, psi_2, psi_3); (1 + gamma_t) psi = 2 (psi_0, psi_1, 0, 0)
+      IO<P>::load_half_codes(m.in[r], nbr, !FWD, h, f);
+      f = flip ? T(-2) * f : T(2) * f;
     } else {
       cx<T> s[12];
-      IO<P>::load_spinor(m.in[r], nbr, s);
+      IO<P>::load_spinor_codes(m.in[r], nbr, s, f);
       project<MU, FWD>(s, h);
     }
     cx<T> w[6];
@@ -300,23 +360,40 @@ __device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, 
         cx<T> q;
         if (FWD) {
           q = M[3 * a] * h[3 * v];
-          q = q + M[3 * a + 1] * h[3 * v + 1];
-          q = q + M[3 * a + 2] * h[3 * v + 2];
+          q = cmadd(M[3 * a + 1], h[3 * v + 1], q);
+          q = cmadd(M[3 * a + 2], h[3 * v + 2], q);
         } else {
           q = cmulc(M[a], h[3 * v]);
-          q = q + cmulc(M[3 + a], h[3 * v + 1]);
-          q = q + cmulc(M[6 + a], h[3 * v + 2]);
+          q = cmaddc(M[3 + a], h[3 * v + 1], q);
+          q = cmaddc(M[6 + a], h[3 * v + 2], q);
         }
         w[3 * v + a] = q;
       }
-    expand<MU, FWD>(acc[r], w);
+    expand_f<MU, FWD>(acc[r], w, f);
+  }
+}
+
+// y = M x (M Hermitian 6x6 in the 18-slot packed form), fused multiply-adds.
+template <typename T>
+__device__ inline void herm6_mul_fma(const cx<T> m[18], const cx<T> x[6], cx<T> y[6]) {
+  const T d[6] = {m[0].r, m[0].i, m[1].r, m[1].i, m[2].r, m[2].i};
+#pragma unroll
+  for (int a = 0; a < 6; ++a) y[a] = d[a] * x[a];
+  int k = 3;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+#pragma unroll
+    for (int b = a + 1; b < 6; ++b) {
+      const cx<T> c = m[k++];
+      y[a] = cmadd(c, x[b], y[a]);
+      y[b] = cmaddc(c, x[a], y[b]);
+    }
   }
 }
 
 template <int P, int EPI, bool CLOV, int RED, bool NT, int NB>
 __device__ inline void hop_site_multi(const HopArgs& a, const MultiPtrs<NB>& m, size_t i, double red[NB][3]) {
   using T = typename IO<P>::T;
-  const size_t vh = (size_t)a.g.vh;
   const Geom& g = a.g;
   const int ii = (int)i;
   const int xh = ii % g.lxh;
@@ -348,16 +425,54 @@ __device__ inline void hop_site_multi(const HopArgs& a, const MultiPtrs<NB>& m, 
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
 
-  hop_dir_multi<P, 0, true, NT, NB>(m, gf + 0 * ls, vh, (size_t)(row + (xf >> 1)), i, false, acc);
-  hop_dir_multi<P, 0, false, NT, NB>(m, gb + 0 * ls, vh, (size_t)(row + (xb >> 1)), (size_t)(row + (xb >> 1)), false,
+  hop_dir_multi<P, 0, true, NT, NB>(m, gf + 0 * ls, (size_t)(row + (xf >> 1)), i, false, acc);
+  hop_dir_multi<P, 0, false, NT, NB>(m, gb + 0 * ls, (size_t)(row + (xb >> 1)), (size_t)(row + (xb >> 1)), false,
                                      acc);
-  hop_dir_multi<P, 1, true, NT, NB>(m, gf + 1 * ls, vh, (size_t)iyf, i, false, acc);
-  hop_dir_multi<P, 1, false, NT, NB>(m, gb + 1 * ls, vh, (size_t)iyb, (size_t)iyb, false, acc);
-  hop_dir_multi<P, 2, true, NT, NB>(m, gf + 2 * ls, vh, (size_t)izf, i, false, acc);
-  hop_dir_multi<P, 2, false, NT, NB>(m, gb + 2 * ls, vh, (size_t)izb, (size_t)izb, false, acc);
-  hop_dir_multi<P, 3, true, NT, NB>(m, gf + 3 * ls, vh, (size_t)itf, i, flipf, acc);
-  hop_dir_multi<P, 3, false, NT, NB>(m, gb + 3 * ls, vh, (size_t)itb, (size_t)itb, flipb, acc);
+  hop_dir_multi<P, 1, true, NT, NB>(m, gf + 1 * ls, (size_t)iyf, i, false, acc);
+  hop_dir_multi<P, 1, false, NT, NB>(m, gb + 1 * ls, (size_t)iyb, (size_t)iyb, false, acc);
+  hop_dir_multi<P, 2, true, NT, NB>(m, gf + 2 * ls, (size_t)izf, i, false, acc);
+  hop_dir_multi<P, 2, false, NT, NB>(m, gb + 2 * ls, (size_t)izb, (size_t)izb, false, acc);
+  hop_dir_multi<P, 3, true, NT, NB>(m, gf + 3 * ls, (size_t)itf, i, flipf, acc);
+  hop_dir_multi<P, 3, false, NT, NB>(m, gb + 3 * ls, (size_t)itb, (size_t)itb, flipb, acc);
 
+  if (EPI == EPI_SCALE_CLOV) {
+    // out = A (scale acc): each chiral block of A is loaded once and applied
+    // to every right-hand side (acc[q] holds c_+ in 0..5 and c_- in 6..11,
+    // then A_+ c_+ in 0..5 while the second block is applied)
+    const T sc = (T)a.scale;
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const cx<T> u = acc[q][k], l = acc[q][k + 6];
+        acc[q][k] = sc * (u - l);
+        acc[q][k + 6] = sc * (u + l);
+      }
+    cx<T> mb[18];
+    IO<P>::template load_clover_block<NT>(a.clov, i, 0, mb);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!((m.act >> q) & 1u)) continue;
+      cx<T> yv[6];
+      herm6_mul_fma(mb, acc[q], yv);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[q][k] = yv[k];
+    }
+    IO<P>::template load_clover_block<NT>(a.clov, i, 1, mb);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!((m.act >> q) & 1u)) continue;
+      cx<T> yv[6], out[12];
+      herm6_mul_fma(mb, acc[q] + 6, yv);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        out[k] = acc[q][k] + yv[k];
+        out[k + 6] = yv[k] - acc[q][k];
+      }
+      IO<P>::store_spinor(m.out[q], i, out);
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     if (!((m.act >> q) & 1u)) continue;

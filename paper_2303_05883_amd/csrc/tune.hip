@@ -10,7 +10,9 @@
 //
 // Cache format: one JSON object, keys "Lx.Ly.Lz.Lt:prec", values
 // {"block": B, "remap": R, "nt": N, "split": S, "us": T}. The path comes from lqcd_autotune's
-// argument or from the LQCD_TUNE_CACHE environment variable.
+// argument or from the LQCD_TUNE_CACHE environment variable. Other tuners
+// (the batched hop) keep their entries in the same file under their own keys
+// through tune_cache_get / tune_cache_put, the four numbers in the same fields.
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -105,6 +107,34 @@ bool valid_for(const lqcd_ctx* c, int prec, const Entry& e) {
 }
 
 }  // namespace
+
+bool tune_cache_get(const std::string& key, int v[4]) {
+  const char* env = std::getenv("LQCD_TUNE_CACHE");
+  if (!env || !*env) return false;
+  const auto m = read_cache(env);
+  auto it = m.find(key);
+  if (it == m.end()) return false;
+  v[0] = it->second.block;
+  v[1] = it->second.split;
+  v[2] = it->second.remap;
+  v[3] = it->second.nt;
+  return true;
+}
+
+int tune_cache_put(const std::string& key, const int v[4], double us) {
+  const char* env = std::getenv("LQCD_TUNE_CACHE");
+  if (!env || !*env) return LQCD_OK;
+  auto m = read_cache(env);
+  Entry e;
+  e.block = v[0];
+  e.split = v[1];
+  e.remap = v[2];
+  e.nt = v[3];
+  e.us = us;
+  m[key] = e;
+  if (!write_cache(env, m)) return set_error(LQCD_EINVAL, std::string("cannot write tune cache ") + env);
+  return LQCD_OK;
+}
 
 int tune_load_defaults(lqcd_ctx* c) {
   const char* env = std::getenv("LQCD_TUNE_CACHE");

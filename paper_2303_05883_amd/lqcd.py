@@ -35,7 +35,7 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
             "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_dwf_apply",
             "lqcd_dwf_solve", "lqcd_dwf_field_bytes", "lqcd_dwf_import", "lqcd_dwf_export", "lqcd_dwf_apply_native",
             "lqcd_mg_setup", "lqcd_mg_coarse_size", "lqcd_mg_restrict", "lqcd_mg_prolong", "lqcd_mg_coarse_apply",
-            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur", "lqcd_dwf_solve_eo", "lqcd_strerror",
+            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur", "lqcd_dwf_solve_eo", "lqcd_batch_autotune", "lqcd_batch_apply_schur", "lqcd_strerror",
             "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
@@ -127,6 +127,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_solve.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
     lib.lqcd_solve_batch.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), C.POINTER(vp), C.POINTER(vp), ip,
                                      C.POINTER(SolveParams), C.POINTER(SolveStats)]
+    lib.lqcd_batch_autotune.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), ip, ip, C.POINTER(C.c_int),
+                                        C.POINTER(C.c_double)]
+    lib.lqcd_batch_apply_schur.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), ip, ip, C.POINTER(vp), C.POINTER(vp)]
     lib.lqcd_field_bytes.argtypes = [vp, ip]
     lib.lqcd_field_bytes.restype = C.c_size_t
     lib.lqcd_import.argtypes = [vp, ip, ip, vp, vp]
@@ -581,6 +584,37 @@ class Lattice:
             _check(status, "lqcd_stag_solve")
         return Stats(st.outer_iters, st.inner_iters, st.restarts, st.true_rel_resid, st.seconds_solve,
                      st.seconds_setup, status)
+
+
+def batch_autotune(lattices, nrhs, prec=F32, shape=None):
+    """Launch shape of the batched hop for these lattices with nrhs[k]
+    right-hand sides each (tuned, cached or, with shape = (nb, nw, nslot,
+    walk, nt), forced); returns (shape, microseconds per launch of the
+    A_oo^-1 H_oe hop)."""
+    lib = load()
+    n = len(lattices)
+    ctxs = (C.c_void_p * n)(*[lat.handle.value for lat in lattices])
+    nr = (C.c_int * n)(*[int(k) for k in nrhs])
+    sh = (C.c_int * 5)(*(tuple(shape) if shape is not None else (0, 0, 0, 0, 0)))
+    us = C.c_double(0.0)
+    _check(lib.lqcd_batch_autotune(ctxs, nr, n, int(prec), sh, C.byref(us)), "lqcd_batch_autotune")
+    return tuple(sh[k] for k in range(5)), us.value
+
+
+def batch_apply_schur(lattices, ins, outs, prec=F32):
+    """outs[k][r] = S ins[k][r] through the batched kernels (device arrays of
+    shape [nrhs, Lt, Lz, Ly, Lx, 4, 3])."""
+    lib = load()
+    n = len(lattices)
+    ctxs = (C.c_void_p * n)(*[lat.handle.value for lat in lattices])
+    nr = (C.c_int * n)(*[int(b.shape[0]) for b in ins])
+    pi = [_ptr(b) for b in ins]
+    po = [_ptr(x) for x in outs]
+    if any(d != 1 for _, d in pi + po):
+        raise ValueError("batch_apply_schur takes device arrays")
+    _check(lib.lqcd_batch_apply_schur(ctxs, nr, n, int(prec), (C.c_void_p * n)(*[p for p, _ in pi]),
+                                      (C.c_void_p * n)(*[p for p, _ in po])), "lqcd_batch_apply_schur")
+    return outs
 
 
 def solve_batch(lattices, bs, xs, tol=1e-10, inner_prec=F32, inner_tol=0.0, check_every=8, use_graph=True):

@@ -81,3 +81,74 @@ def test_batch_rejects_mixed_streams():
     with pytest.raises(lqcd.LqcdError) as e:
         lqcd.solve_batch([a, b], [v, v], [v.clone(), v.clone()])
     assert e.value.status == lqcd.EINVAL
+
+
+def batch_system(torch, specs, kappa, csw, stream=None):
+    stream = stream or torch.cuda.Stream()
+    lats, ops, bs = [], [], []
+    for dims, n, seed in specs:
+        U = fg.gauge_field(dims, seed, "smooth", 0.3)
+        lat = lqcd.Lattice(dims, -1, stream=stream)
+        lat.set_gauge(to_dev(U))
+        lat.set_clover(kappa, csw)
+        lats.append(lat)
+        ops.append(dirac.Operator(U, kappa, csw, -1))
+        bs.append(np.stack([fg.gaussian_spinor(dims, seed + 100 + k) for k in range(n)]))
+    return lats, ops, bs
+
+
+# (rhs per lane, waves per workgroup, workgroups per XCD, walk, non-temporal)
+SHAPES = {lqcd.F64: [(1, 8, 16, 0, 0), (2, 3, 64, 1, 1), (2, 1, 128, 1, 0)],
+          lqcd.F32: [(1, 8, 64, 1, 0), (2, 2, 16, 0, 1), (3, 4, 128, 1, 1), (4, 3, 256, 0, 0), (4, 1, 8, 1, 0)],
+          lqcd.F16: [(1, 8, 64, 0, 1), (2, 6, 128, 1, 0), (3, 2, 32, 1, 1), (4, 3, 256, 0, 0), (4, 1, 64, 1, 1)]}
+
+
+@pytest.mark.parametrize("prec", [lqcd.F64, lqcd.F32, lqcd.F16])
+@pytest.mark.parametrize("csw", [1.0, 0.0])
+def test_batched_schur_matches_oracle(prec, csw):
+    """The batched Schur operator, element by element against the oracle's
+    S = D_ee - D_eo D_oo^-1 D_oe for every right-hand side, for every launch
+    shape (right-hand sides per lane, waves per workgroup fewer or more than
+    the groups of a lattice, workgroups per XCD); lattices of uneven sizes and
+    right-hand side counts, ragged last site block (4x6x8x10)."""
+    from tests.gpuutil import TOL
+    torch = torch_cuda()
+    specs = [((8, 8, 8, 8), 12, 31), ((4, 6, 8, 10), 5, 32), ((4, 4, 4, 4), 3, 33)]
+    lats, ops, bs = batch_system(torch, specs, 0.136, csw)
+    ins = [to_dev(b) for b in bs]
+    want = []
+    for op, b in zip(ops, bs):
+        w = []
+        for r in range(b.shape[0]):
+            w.append(op.schur(dirac.mask(b[r], 0)))
+        want.append(np.stack(w))
+    for shape in SHAPES[prec]:
+        outs = [to_dev(np.full_like(b, np.nan)) for b in bs]
+        got_shape, us = lqcd.batch_autotune(lats, [b.shape[0] for b in bs], prec, shape)
+        assert got_shape == shape and us > 0
+        lqcd.batch_apply_schur(lats, ins, outs, prec)
+        for w, o in zip(want, outs):
+            oh = from_dev(o)
+            for r in range(w.shape[0]):
+                err = dirac.rel_l2(oh[r], w[r])
+                assert err <= TOL[prec], (shape, r, err)
+
+
+def test_batch_autotune_picks_a_valid_shape_and_solves():
+    torch = torch_cuda()
+    specs = [((8, 8, 8, 8), 12, 41), ((4, 4, 4, 8), 7, 42)]
+    lats, ops, bs = batch_system(torch, specs, 0.136, 1.0)
+    shape, us = lqcd.batch_autotune(lats, [12, 7], lqcd.F32)
+    assert 1 <= shape[0] <= 4 and 1 <= shape[1] <= 8 and shape[2] >= 1 and shape[3] in (0, 1) and us > 0
+    ds = [to_dev(b) for b in bs]
+    xs = [to_dev(np.zeros_like(b)) for b in bs]
+    stats = lqcd.solve_batch(lats, ds, xs, inner_prec=lqcd.F32)
+    k = 0
+    for op, b, x in zip(ops, bs, xs):
+        xh = from_dev(x)
+        for r in range(b.shape[0]):
+            assert dirac.rel_l2(op.D(xh[r]), b[r]) <= 1e-10, (r, stats[k])
+            k += 1
+    with pytest.raises(lqcd.LqcdError) as e:
+        lqcd.batch_autotune(lats, [12, 7], lqcd.F64, (3, 2, 64, 0, 0))  # 3 RHS per lane is not built in FP64
+    assert e.value.status == lqcd.EINVAL
