@@ -80,8 +80,10 @@ def _slice(args):
     return fg.gaussian_spinor(dims, seed, t_slices=[t])
 
 
-def generate(dims, seed, eps=0.3, workers=8, source=True, scale=1.0):
+def generate(dims, seed, eps=0.3, workers=None, source=True, scale=1.0):
     lt = dims[3]
+    if workers is None:
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
         U = np.concatenate(list(ex.map(_slice, [("gauge", dims, seed, eps, scale, t) for t in range(lt)])))
         b = (np.concatenate(list(ex.map(_slice, [("src", dims, seed, eps, scale, t) for t in range(lt)])))

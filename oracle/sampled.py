@@ -104,22 +104,25 @@ def _linear(dims, s):
     return s[:, 0] + dims[0] * (s[:, 1] + dims[1] * (s[:, 2] + dims[2] * s[:, 3]))
 
 
-def schur_at(U, x_even, kappa, csw, t_bc, sites):
+def schur_at(U, x_even, kappa, csw, t_bc, sites, x_at=None):
     """(S x)(x) = A(x) x(x) - kappa^2 (H A_oo^-1 H x)(x) at even sites x, for a
-    field x supported on even sites: S = D_ee - D_eo D_oo^-1 D_oe."""
+    field x supported on even sites: S = D_ee - D_eo D_oo^-1 D_oe. x is the
+    whole field x_even, or (x_at given) a function returning x at listed sites."""
+    if x_at is None:
+        x_at = full_lookup(x_even)
     dims = _dims(U)
     sites = np.asarray(sites)
     nbr = np.concatenate([step(dims, sites, mu, s) for mu in range(4) for s in (+1, -1)])
     lin = _linear(dims, nbr)
     uniq, first = np.unique(lin, return_index=True)
     odd_sites = nbr[first]
-    y = hop_at(U, full_lookup(x_even), t_bc, odd_sites)
+    y = hop_at(U, x_at, t_bc, odd_sites)
     y = site_mul(np.linalg.inv(clover_at(U, kappa, csw, odd_sites)), y)
 
     def y_at(s):
         return y[np.searchsorted(uniq, _linear(dims, s))]
 
-    return site_mul(clover_at(U, kappa, csw, sites), gather(x_even, sites)) \
+    return site_mul(clover_at(U, kappa, csw, sites), x_at(sites)) \
         - kappa * kappa * hop_at(U, y_at, t_bc, sites)
 
 

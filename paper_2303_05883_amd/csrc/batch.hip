@@ -513,7 +513,7 @@ int batch_tune(Batch& B, bool sweep, const BShape* forced = nullptr) {
     for (int nb = 1; nb <= (B.prec == 0 ? 2 : 4); ++nb) {
       const int ngroup = (B.max_rhs + nb - 1) / nb;
       for (int nw : {1, std::min(BHOP_MAX_WAVES, ngroup)})
-        for (int nslot : {128, 256})
+        for (int nslot : {128, 256, 512})
           for (int walk = 0; walk < 2; ++walk)
             for (int nt = 0; nt < 2; ++nt) {
               BShape sh;

@@ -93,3 +93,29 @@ def test_mixed_solve_true_residual_sampled(setup):
     # the global residual is <= 1e-10 |b| with |b|^2 ~ 12 per site, so the rms
     # residual per site is ~4e-10; a wrong solution would leave O(1)
     assert np.sqrt(np.mean(np.abs(r) ** 2) * 12) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", [lqcd.F32, lqcd.F16])
+def test_schur_low_precision_sampled(setup, prec):
+    """The Schur operator in the solver's inner precisions (FP32, FP16 storage
+    with FP32 arithmetic) at sampled even sites, to the single-apply tolerance."""
+    U, b, lat, kappa, csw = setup
+    out = to_dev(np.zeros_like(b))
+    lat.apply("DPREC_SCHUR", prec, to_dev(b), out)
+    se = sites(0, n=24, seed=9)
+    got = sampled.gather(from_dev(out), se)
+    ref = sampled.schur_at(U, dirac.mask(b, 0), kappa, csw, -1, se)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL[prec]
+
+
+def test_mixed_f16_solve_true_residual_sampled(setup):
+    """The FP16-inner solve (the fastest mode) reaches 1e-10 by the library's
+    FP64 residual, and the oracle's residual at sampled sites agrees."""
+    U, b, lat, kappa, csw = setup
+    x = to_dev(np.zeros_like(b))
+    st = lat.solve(to_dev(b), x, inner_prec=lqcd.F16)
+    assert st.true_rel_resid <= 1e-10 and st.outer_iters >= 2
+    xh = from_dev(x)
+    sa = np.concatenate([sites(0, n=32, seed=10), sites(1, n=32, seed=11)])
+    r = sampled.dirac_at(U, xh, kappa, csw, -1, sa) - sampled.gather(b, sa)
+    assert np.sqrt(np.mean(np.abs(r) ** 2) * 12) <= 1e-8
