@@ -407,6 +407,20 @@ int lqcd_export(lqcd_ctx* ctx, int prec, int parity, const void* native, double*
  * LQCD_DEE_INV, LQCD_DOO_INV (site terms) or LQCD_DPREC_SCHUR (even -> even). */
 int lqcd_apply_native(lqcd_ctx* ctx, int op, int prec, const void* in, void* out);
 
+/* lqcd_apply_native without allocating: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same operators, arguments and results as
+ * lqcd_apply_native; the Schur operator's intermediate odd half field lives in
+ * a file-scope device array of the library (NOALLOC limit: 128 MiB per GPU,
+ * e.g. FP32 up to 32^3 x 64, FP64 up to 32^3 x 32), held on each GPU from the
+ * first context created on it to the end of the process. No hipMalloc, hipFree
+ * or allocating library call is made. EINVAL when the operator's half field
+ * exceeds the limit (with the sizes in lqcd_last_error); ESTATE before
+ * set_gauge / set_clover. All calls on one GPU share that array, so calls
+ * that overlap in time on one GPU (other streams or threads) race; calls
+ * ordered on one stream are safe. Enqueued without synchronising. */
+int lqcd_apply_native_noalloc(lqcd_ctx* ctx, int op, int prec, const void* in, void* out);
+
 /* Autotune the launch shape of the hop for (op, prec) on this lattice: times
  * each candidate workgroup size and block-to-XCD mapping on native scratch
  * fields and keeps the fastest in the context. If path is not NULL the choice

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "blas.h"
@@ -16,6 +17,35 @@
 #include "tune.h"
 
 namespace lq {
+
+// Scratch of lqcd_apply_native_noalloc: the odd half field between the two
+// hops of the Schur operator, in a file-scope device array instead of a
+// library allocation. Each GPU the library runs on holds its own copy (from
+// the first use of this code object on that GPU to the end of the process);
+// host code reaches it only through the per-device address that
+// hipGetSymbolAddress returns (the array's name is a host-side stand-in).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void* g_scratch_addr[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_scratch_mutex;
+
+// The scratch array's address on the current device (looked up once per device).
+static int noalloc_scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return set_error(LQCD_EHIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return set_error(LQCD_EHIP, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+    }
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return LQCD_OK;
+}
 
 static thread_local std::string g_last_error;
 
@@ -160,7 +190,7 @@ int lqcd_create(const int dims[4], int t_bc, void* hip_stream, lqcd_ctx** out) {
     }
     c->own_stream = true;
   }
-  int s = LQCD_OK;
+  int s = noalloc_scratch_address(c->device, &c->noalloc_scratch);
   for (int p = 0; p < 3 && s == LQCD_OK; ++p) s = dalloc(&c->gauge[p], 8 * link_bytes(p, c->g.vh));
   if (s == LQCD_OK) s = dalloc(reinterpret_cast<void**>(&c->dscal), 64 * sizeof(double));
   if (s == LQCD_OK && hipHostMalloc(reinterpret_cast<void**>(&c->hscal), 64 * sizeof(double)) != hipSuccess)
@@ -928,6 +958,24 @@ int lqcd_apply_native(lqcd_ctx* c, int op, int prec, const void* in, void* out) 
     LQ_TRY(dalloc(&c->half_d[prec], spinor_bytes(prec, c->g.vh)));
     tmp = c->half_d[prec];
   }
+  return op_native(c, op, prec, in, out, tmp);
+}
+
+int lqcd_apply_native_noalloc(lqcd_ctx* c, int op, int prec, const void* in, void* out) {
+  if (!c || !in || !out) return set_error(LQCD_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");
+  if (in == out) return set_error(LQCD_EINVAL, "in and out must differ");
+  void* tmp = nullptr;
+  if (op == LQCD_DPREC_SCHUR) {
+    const size_t need = spinor_bytes(prec, c->g.vh);
+    if (need > NOALLOC_SCRATCH_BYTES)
+      return set_error(LQCD_EINVAL, "the Schur operator needs a " + std::to_string(need) +
+                                        "-byte half field, more than the " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                        "-byte scratch of lqcd_apply_native_noalloc");
+    if (!c->noalloc_scratch) return set_error(LQCD_ESTATE, "no scratch address for this context");
+    tmp = c->noalloc_scratch;
+  }
+  if (!c->have_gauge || !c->have_clover) return set_error(LQCD_ESTATE, "set_gauge and set_clover must come first");
   return op_native(c, op, prec, in, out, tmp);
 }
 

@@ -113,6 +113,7 @@ struct lqcd_ctx {
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
   bool own_stream = false;
   int device = 0;
+  void* noalloc_scratch = nullptr;  // this device's copy of the no-allocation scratch array
 
   // gauge[prec]: 2 parities x 4 directions x link_bytes
   void* gauge[3] = {nullptr, nullptr, nullptr};

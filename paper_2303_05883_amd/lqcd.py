@@ -35,7 +35,7 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
             "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_dwf_apply",
             "lqcd_dwf_solve", "lqcd_dwf_field_bytes", "lqcd_dwf_import", "lqcd_dwf_export", "lqcd_dwf_apply_native",
             "lqcd_mg_setup", "lqcd_mg_coarse_size", "lqcd_mg_restrict", "lqcd_mg_prolong", "lqcd_mg_coarse_apply",
-            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur", "lqcd_dwf_solve_eo", "lqcd_batch_autotune", "lqcd_batch_apply_schur", "lqcd_strerror",
+            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur", "lqcd_dwf_solve_eo", "lqcd_batch_autotune", "lqcd_batch_apply_schur", "lqcd_apply_native_noalloc", "lqcd_strerror",
             "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
@@ -135,6 +135,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.lqcd_import.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_export.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_apply_native.argtypes = [vp, ip, ip, vp, vp]
+    lib.lqcd_apply_native_noalloc.argtypes = [vp, ip, ip, vp, vp]
     lib.lqcd_autotune.argtypes = [vp, ip, C.c_char_p]
     lib.lqcd_set_hop_shape.argtypes = [vp, ip, ip, ip, ip, ip]
     lib.lqcd_get_hop_shape.argtypes = [vp, ip] + [C.POINTER(C.c_int)] * 4
@@ -325,6 +326,12 @@ class Lattice:
         op = OPS[op] if isinstance(op, str) else int(op)
         _check(self._call(self.lib.lqcd_apply_native, self.handle, op, int(prec), _ptr(native_in)[0],
                           _ptr(native_out)[0]), "lqcd_apply_native")
+
+    def apply_native_noalloc(self, op, prec, native_in, native_out):
+        """apply_native without any device allocation (the library's static scratch)."""
+        op = OPS[op] if isinstance(op, str) else int(op)
+        _check(self._call(self.lib.lqcd_apply_native_noalloc, self.handle, op, int(prec), _ptr(native_in)[0],
+                          _ptr(native_out)[0]), "lqcd_apply_native_noalloc")
 
     def apply_native_repeat(self, op, prec, ins, outs, reps: int):
         """reps launches of one native operator, cycling over the (in, out)
