@@ -447,7 +447,7 @@ def batched_hop_roofline(lqcd, lats, nrhs, vhs, prec):
            "kernel": f"k_bhop<{prec},EPI_SCALE_CLOV> (batched A_oo^-1 H_oe hop, {name} storage, all right-hand "
                      "sides of all lattices in one launch)",
            "launch_shape": {"rhs_per_lane": shape[0], "waves_per_workgroup": shape[1], "workgroups_per_xcd": shape[2],
-                            "walk": ["linear", "slab"][shape[3]], "nt_links_clover": shape[4]},
+                            "walk": ["linear", "slab", "slab/2", "slab/4"][shape[3]], "nt_links_clover": shape[4]},
            "us": round(us, 2), "bytes_per_launch": nbytes,
            "gflops": round(BHOP_FLOPS * site_rhs / (us * 1e-6) / 1e9, 1)}
     log(f"batched hop ({name}): {out}")

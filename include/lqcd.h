@@ -183,7 +183,8 @@ int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const
  * Sec. 3): shape = {right-hand sides per lane (1..4; 1..2 in FP64),
  * wavefronts per workgroup (1..8, one group of right-hand sides each),
  * workgroups per XCD, tile walk (0: linear in the site index, 1: every XCD
- * walks its range of blocks of each time slice, slice after slice), 1 for
+ * walks its range of blocks of each time slice, slice after slice; 2, 3: the
+ * same with the range cut into 2 or 4 parts walked one after the other), 1 for
  * non-temporal loads of links and clover blocks}. With shape NULL or
  * shape[0] <= 0 the shape comes from the tune cache (LQCD_TUNE_CACHE) or,
  * without an entry, from timing every candidate with HIP events on the

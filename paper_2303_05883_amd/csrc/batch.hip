@@ -288,12 +288,19 @@ int set_shape(Batch& B, const BShape& sh) {
       auto push = [&](int blk) {
         for (int gs = 0; gs < nset; ++gs) tl.push_back(make_int2((int)l | (gs << 8), blk));
       };
-      if (sh.walk == 1 && per_t % SB == 0) {
-        // slab walk: this XCD's range of blocks in every time slice, slices in order
+      if (sh.walk >= 1 && per_t % SB == 0) {
+        // slab walk: this XCD's range of blocks in every time slice, slices in
+        // order; walk w > 1 cuts the range into 2^(w-1) sub-ranges walked one
+        // after the other (a smaller working set per time step)
         const int nbt = (int)(per_t / SB);
         const int lo = (int)((long long)nbt * k / 8), hi = (int)((long long)nbt * (k + 1) / 8);
-        for (int t = 0; t < L.g.lt; ++t)
-          for (int bb = lo; bb < hi; ++bb) push(t * nbt + bb);
+        const int nsub = 1 << (sh.walk - 1);
+        for (int q = 0; q < nsub; ++q) {
+          const int slo = lo + (int)((long long)(hi - lo) * q / nsub);
+          const int shi = lo + (int)((long long)(hi - lo) * (q + 1) / nsub);
+          for (int t = 0; t < L.g.lt; ++t)
+            for (int bb = slo; bb < shi; ++bb) push(t * nbt + bb);
+        }
       } else {
         const int lo = (int)((long long)L.nsb * k / 8), hi = (int)((long long)L.nsb * (k + 1) / 8);
         for (int bb = lo; bb < hi; ++bb) push(bb);
@@ -450,7 +457,7 @@ std::string batch_key(const Batch& B) {
 bool shape_ok(const Batch& B, const BShape& sh) {
   const int max_nb = B.prec == 0 ? 2 : 4;
   return sh.nb >= 1 && sh.nb <= max_nb && sh.nw >= 1 && sh.nw <= BHOP_MAX_WAVES && sh.nslot >= 1 &&
-         sh.nslot <= 4096 && (sh.walk == 0 || sh.walk == 1) && (sh.nt == 0 || sh.nt == 1);
+         sh.nslot <= 4096 && sh.walk >= 0 && sh.walk <= 3 && (sh.nt == 0 || sh.nt == 1);
 }
 
 // Average duration (us) of the batched A_oo^-1 H_oe hop (the first hop of the
@@ -490,8 +497,8 @@ int batch_tune(Batch& B, bool sweep, const BShape* forced = nullptr) {
       sh.nw = v[0] / 64;
       sh.nb = v[1];
       sh.nslot = v[2];
-      sh.walk = v[3] & 1;
-      sh.nt = (v[3] >> 1) & 1;
+      sh.walk = v[3] & 3;
+      sh.nt = (v[3] >> 2) & 1;
       if (shape_ok(B, sh)) {
         LQ_TRY(set_shape(B, sh));
         B.tuned = true;
@@ -514,8 +521,8 @@ int batch_tune(Batch& B, bool sweep, const BShape* forced = nullptr) {
       const int ngroup = (B.max_rhs + nb - 1) / nb;
       for (int nw : {1, std::min(BHOP_MAX_WAVES, ngroup)})
         for (int nslot : {128, 256, 512})
-          for (int walk = 0; walk < 2; ++walk)
-            for (int nt = 0; nt < 2; ++nt) {
+          for (int walk = 0; walk < 4; ++walk)
+            for (int nt = 0; nt < 1; ++nt) {  // streaming loads measured slower: forced shapes only
               BShape sh;
               sh.nb = nb;
               sh.nw = nw;
@@ -548,7 +555,7 @@ int batch_tune(Batch& B, bool sweep, const BShape* forced = nullptr) {
   B.hop_us = best_us;
   B.tuned = true;
   if (!forced) {
-    const int v[4] = {64 * best.nw, best.nb, best.nslot, best.walk | (best.nt << 1)};
+    const int v[4] = {64 * best.nw, best.nb, best.nslot, best.walk | (best.nt << 2)};
     LQ_TRY(tune_cache_put(key, v, best_us));
   }
   return LQCD_OK;

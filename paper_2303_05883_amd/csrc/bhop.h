@@ -13,9 +13,10 @@
 // follow a walk chosen by the tuner: linear in the site index, or "slab"
 // (each XCD owns the same range of blocks in every time slice and walks the
 // slices in order, so that the neighbours in t and z of the sites in flight
-// were read shortly before and are still in its L2). With 12 right-hand
-// sides a tile's spinors are 12 times a single field's, so the walk decides
-// whether neighbour spinors come from L2 or again from HBM.
+// were read shortly before and are still in its L2), optionally with the
+// range cut into 2 or 4 sub-ranges walked one after the other. With 12
+// right-hand sides a tile's spinors are 12 times a single field's, so the
+// walk decides whether neighbour spinors come from L2 or again from HBM.
 #pragma once
 
 #include "blas.h"
@@ -62,7 +63,8 @@ struct BHopArgs {
 
 // Launch shape of the batched hop: nb right-hand sides per lane, nw wavefronts
 // (groups) per workgroup, nslot workgroups per XCD (the grid is 8 nslot
-// workgroups), the tile walk (0 linear, 1 slab) and nt = 1 for non-temporal
+// workgroups), the tile walk (0 linear, 1 slab, 2 and 3 slab in 2 or 4
+// sub-ranges) and nt = 1 for non-temporal
 // (streaming) loads of the links and clover blocks.
 struct BShape {
   int nb = 4, nw = 3, nslot = 256, walk = 1, nt = 0;

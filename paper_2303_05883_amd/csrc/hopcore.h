@@ -8,6 +8,85 @@
 
 namespace lq {
 
+// Fused multiply-add forms of the complex arithmetic (four FMAs per complex
+// multiply-accumulate), used where the hop is bounded by vector issue: the
+// multi-RHS hop and the FP16 hop (conversions on top of the arithmetic).
+__device__ inline float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// c + a b and c + conj(a) b
+template <typename T>
+__device__ inline cx<T> cmadd(cx<T> a, cx<T> b, cx<T> c) {
+  return {fmat(-a.i, b.i, fmat(a.r, b.r, c.r)), fmat(a.i, b.r, fmat(a.r, b.i, c.i))};
+}
+template <typename T>
+__device__ inline cx<T> cmaddc(cx<T> a, cx<T> b, cx<T> c) {
+  return {fmat(a.i, b.i, fmat(a.r, b.r, c.r)), fmat(-a.i, b.r, fmat(a.r, b.i, c.i))};
+}
+// c + f z, c + f (i z), c - f (i z) for a real factor f
+template <typename T>
+__device__ inline cx<T> caxpy(T f, cx<T> z, cx<T> c) {
+  return {fmat(f, z.r, c.r), fmat(f, z.i, c.i)};
+}
+template <typename T>
+__device__ inline cx<T> caxpy_i(T f, cx<T> z, cx<T> c) {
+  return {fmat(-f, z.i, c.r), fmat(f, z.r, c.i)};
+}
+template <typename T>
+__device__ inline cx<T> caxpy_mi(T f, cx<T> z, cx<T> c) {
+  return {fmat(f, z.i, c.r), fmat(-f, z.r, c.i)};
+}
+
+// acc += f * (the four-spinor of w = U h for direction MU), f real: the
+// projection's factor (2 and the boundary sign in t) and the FP16 scale.
+template <int MU, bool FWD, typename T>
+__device__ inline void expand_f(cx<T> acc[12], const cx<T> w[6], T f) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<T> w0 = w[c], w1 = w[3 + c];
+    if (MU == 3) {
+      if (FWD) {
+        acc[6 + c] = caxpy(f, w0, acc[6 + c]);
+        acc[9 + c] = caxpy(f, w1, acc[9 + c]);
+      } else {
+        acc[c] = caxpy(f, w0, acc[c]);
+        acc[3 + c] = caxpy(f, w1, acc[3 + c]);
+      }
+      continue;
+    }
+    acc[c] = caxpy(f, w0, acc[c]);
+    acc[3 + c] = caxpy(f, w1, acc[3 + c]);
+    if (MU == 0) {  // lower = -+ i sigma_x w = -+ i (w1, w0)
+      acc[6 + c] = FWD ? caxpy_mi(f, w1, acc[6 + c]) : caxpy_i(f, w1, acc[6 + c]);
+      acc[9 + c] = FWD ? caxpy_mi(f, w0, acc[9 + c]) : caxpy_i(f, w0, acc[9 + c]);
+    } else if (MU == 1) {  // -+ i sigma_y w = -+ (w1, -w0)
+      acc[6 + c] = caxpy(FWD ? -f : f, w1, acc[6 + c]);
+      acc[9 + c] = caxpy(FWD ? f : -f, w0, acc[9 + c]);
+    } else {  // -+ i sigma_z w = -+ (i w0, -i w1)
+      acc[6 + c] = FWD ? caxpy_mi(f, w0, acc[6 + c]) : caxpy_i(f, w0, acc[6 + c]);
+      acc[9 + c] = FWD ? caxpy_i(f, w1, acc[9 + c]) : caxpy_mi(f, w1, acc[9 + c]);
+    }
+  }
+}
+
+// y = M x (M Hermitian 6x6 in the 18-slot packed form), fused multiply-adds.
+template <typename T>
+__device__ inline void herm6_mul_fma(const cx<T> m[18], const cx<T> x[6], cx<T> y[6]) {
+  const T d[6] = {m[0].r, m[0].i, m[1].r, m[1].i, m[2].r, m[2].i};
+#pragma unroll
+  for (int a = 0; a < 6; ++a) y[a] = d[a] * x[a];
+  int k = 3;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+#pragma unroll
+    for (int b = a + 1; b < 6; ++b) {
+      const cx<T> c = m[k++];
+      y[a] = cmadd(c, x[b], y[a]);
+      y[b] = cmaddc(c, x[a], y[b]);
+    }
+  }
+}
+
 // Spin projection for direction MU; FWD: (1 - gamma_mu), else (1 + gamma_mu).
 // s: 12 complex (3*spin + colour), or for MU == 3 only the 6 needed (see below).
 template <int MU, bool FWD, typename T>
@@ -272,64 +351,6 @@ struct MultiPtrs {
   unsigned act;
 };
 
-__device__ inline float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ inline double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// c + a b and c + conj(a) b
-template <typename T>
-__device__ inline cx<T> cmadd(cx<T> a, cx<T> b, cx<T> c) {
-  return {fmat(-a.i, b.i, fmat(a.r, b.r, c.r)), fmat(a.i, b.r, fmat(a.r, b.i, c.i))};
-}
-template <typename T>
-__device__ inline cx<T> cmaddc(cx<T> a, cx<T> b, cx<T> c) {
-  return {fmat(a.i, b.i, fmat(a.r, b.r, c.r)), fmat(-a.i, b.r, fmat(a.r, b.i, c.i))};
-}
-// c + f z, c + f (i z), c - f (i z) for a real factor f
-template <typename T>
-__device__ inline cx<T> caxpy(T f, cx<T> z, cx<T> c) {
-  return {fmat(f, z.r, c.r), fmat(f, z.i, c.i)};
-}
-template <typename T>
-__device__ inline cx<T> caxpy_i(T f, cx<T> z, cx<T> c) {
-  return {fmat(-f, z.i, c.r), fmat(f, z.r, c.i)};
-}
-template <typename T>
-__device__ inline cx<T> caxpy_mi(T f, cx<T> z, cx<T> c) {
-  return {fmat(f, z.i, c.r), fmat(-f, z.r, c.i)};
-}
-
-// acc += f * (the four-spinor of w = U h for direction MU), f real: the
-// projection's factor (2 and the boundary sign in t) and the FP16 scale.
-template <int MU, bool FWD, typename T>
-__device__ inline void expand_f(cx<T> acc[12], const cx<T> w[6], T f) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const cx<T> w0 = w[c], w1 = w[3 + c];
-    if (MU == 3) {
-      if (FWD) {
-        acc[6 + c] = caxpy(f, w0, acc[6 + c]);
-        acc[9 + c] = caxpy(f, w1, acc[9 + c]);
-      } else {
-        acc[c] = caxpy(f, w0, acc[c]);
-        acc[3 + c] = caxpy(f, w1, acc[3 + c]);
-      }
-      continue;
-    }
-    acc[c] = caxpy(f, w0, acc[c]);
-    acc[3 + c] = caxpy(f, w1, acc[3 + c]);
-    if (MU == 0) {  // lower = -+ i sigma_x w = -+ i (w1, w0)
-      acc[6 + c] = FWD ? caxpy_mi(f, w1, acc[6 + c]) : caxpy_i(f, w1, acc[6 + c]);
-      acc[9 + c] = FWD ? caxpy_mi(f, w0, acc[9 + c]) : caxpy_i(f, w0, acc[9 + c]);
-    } else if (MU == 1) {  // -+ i sigma_y w = -+ (w1, -w0)
-      acc[6 + c] = caxpy(FWD ? -f : f, w1, acc[6 + c]);
-      acc[9 + c] = caxpy(FWD ? f : -f, w0, acc[9 + c]);
-    } else {  // -+ i sigma_z w = -+ (i w0, -i w1)
-      acc[6 + c] = FWD ? caxpy_mi(f, w0, acc[6 + c]) : caxpy_i(f, w0, acc[6 + c]);
-      acc[9 + c] = FWD ? caxpy_i(f, w1, acc[9 + c]) : caxpy_mi(f, w1, acc[9 + c]);
-    }
-  }
-}
-
 template <int P, int MU, bool FWD, bool NT, int NB>
 __device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, size_t nbr, size_t lidx, bool flip,
                                      cx<typename IO<P>::T> acc[NB][12]) {
@@ -370,24 +391,6 @@ __device__ inline void hop_dir_multi(const MultiPtrs<NB>& m, const void* links, 
         w[3 * v + a] = q;
       }
     expand_f<MU, FWD>(acc[r], w, f);
-  }
-}
-
-// y = M x (M Hermitian 6x6 in the 18-slot packed form), fused multiply-adds.
-template <typename T>
-__device__ inline void herm6_mul_fma(const cx<T> m[18], const cx<T> x[6], cx<T> y[6]) {
-  const T d[6] = {m[0].r, m[0].i, m[1].r, m[1].i, m[2].r, m[2].i};
-#pragma unroll
-  for (int a = 0; a < 6; ++a) y[a] = d[a] * x[a];
-  int k = 3;
-#pragma unroll
-  for (int a = 0; a < 6; ++a) {
-#pragma unroll
-    for (int b = a + 1; b < 6; ++b) {
-      const cx<T> c = m[k++];
-      y[a] = cmadd(c, x[b], y[a]);
-      y[b] = cmaddc(c, x[a], y[b]);
-    }
   }
 }
 
