@@ -168,7 +168,8 @@ int lqcd_solve(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_param
  * operator's data): for each lattice k < nlattices, nrhs[k] right-hand sides
  * b[k] (nrhs[k] canonical vectors back to back) on context ctxs[k]; solutions
  * to x[k], by the even-odd preconditioned (mixed-precision) BiCGStab of
- * lqcd_solve (even_odd = 0 is EINVAL here). All contexts must share one stream. Each RHS runs its own
+ * lqcd_solve (even_odd = 0 is EINVAL here; with inner_tol 0 the FP16 inner
+ * solves default to 5e-3 instead of 1e-2). All contexts must share one stream. Each RHS runs its own
  * BiCGStab (own alpha, beta, omega; not block Krylov) but every operator step
  * of every unconverged RHS of every lattice is one persistent kernel launch that
  * loads each link once per site for all RHS of that lattice. Converged RHS are

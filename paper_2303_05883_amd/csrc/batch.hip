@@ -593,7 +593,9 @@ extern "C" int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const do
   Scal* dscal_all = B.dscal_all;
   const int nseg = (int)B.hseg.size();
   const int check = prm.check_every > 0 ? prm.check_every : 8;
-  const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : (IP == 2 ? 1e-2 : 1e-10));
+  // default inner tolerances: FP32 1e-6; FP16 5e-3 (measured on 36 point
+  // sources on three clover lattices: 355 iterations against 397 at 1e-2)
+  const double delta = prm.inner_tol > 0 ? prm.inner_tol : (IP == 1 ? 1e-6 : (IP == 2 ? 5e-3 : 1e-10));
 
   // import and prepare every segment: b', |b|^2, x = 0, r = b'
   for (int s = 0; s < nseg; ++s) {

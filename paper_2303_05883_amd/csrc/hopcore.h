@@ -476,6 +476,68 @@ __device__ inline void hop_site_multi(const HopArgs& a, const MultiPtrs<NB>& m, 
     }
     return;
   }
+  if (EPI == EPI_XPAY && CLOV) {
+    // out = A x_own + scale acc, the chiral blocks of A loaded once for all
+    // right-hand sides: xo[q] holds c_+, c_- of x_own, then A_+ c_+ in 0..5
+    const T sc = (T)a.scale;
+    cx<T> xo[NB][12];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!((m.act >> q) & 1u)) continue;
+      IO<P>::load_spinor(m.own[q], i, xo[q]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const cx<T> u = xo[q][k], l = xo[q][k + 6];
+        xo[q][k] = u - l;
+        xo[q][k + 6] = u + l;
+      }
+    }
+    cx<T> mb[18];
+    IO<P>::template load_clover_block<NT>(a.clov, i, 0, mb);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!((m.act >> q) & 1u)) continue;
+      cx<T> yv[6];
+      herm6_mul_fma(mb, xo[q], yv);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) xo[q][k] = yv[k];
+    }
+    IO<P>::template load_clover_block<NT>(a.clov, i, 1, mb);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!((m.act >> q) & 1u)) continue;
+      cx<T> yv[6], out[12];
+      herm6_mul_fma(mb, xo[q] + 6, yv);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        out[k] = caxpy(sc, acc[q][k], xo[q][k] + yv[k]);
+        out[k + 6] = caxpy(sc, acc[q][k + 6], yv[k] - xo[q][k]);
+      }
+      if (RED == RED_TS) {
+        // <out, x_own> and <out, out> (x_own read again, from the cache)
+        cx<T> x0[12];
+        IO<P>::load_spinor(m.own[q], i, x0);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          const cx<T> d = cmulc(out[k], x0[k]);
+          red[q][0] += (double)d.r;
+          red[q][1] += (double)d.i;
+          red[q][2] += (double)out[k].r * (double)out[k].r + (double)out[k].i * (double)out[k].i;
+        }
+      } else if (RED == RED_DOT) {
+        cx<T> wv[12];
+        IO<P>::load_spinor(m.w[q], i, wv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          const cx<T> d = cmulc(wv[k], out[k]);
+          red[q][0] += (double)d.r;
+          red[q][1] += (double)d.i;
+        }
+      }
+      IO<P>::store_spinor(m.out[q], i, out);
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     if (!((m.act >> q) & 1u)) continue;
