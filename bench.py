@@ -425,6 +425,9 @@ def run_single(a, torch, lqcd):
     return value, ms_step, config, roof, hop, compare, cpu, inner
 
 
+BHOP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_hop_traffic_36rhs.txt")
+BHOP_SOURCES = ("bhop.h", "bhop_f32.hip", "bhop_f16.hip", "hopcore.h", "fieldio.h")
+
 # algorithmic bytes per site of the batched A_oo^-1 H_oe hop: links (8 x 12
 # reals) and the clover block (72 reals) once per site, the input and output
 # spinor once per site and right-hand side (FP16: 24 codes + the FP32 scale)
@@ -442,8 +445,15 @@ def batched_hop_roofline(lqcd, lats, nrhs, vhs, prec):
     site_rhs = sum(vh * n for vh, n in zip(vhs, nrhs))
     gbs = nbytes / (us * 1e-6) / 1e9
     name = {0: "f64", 1: "f32", 2: "f16"}[prec]
+    # the committed counters hold for the kernel instantiation they were taken on
+    tmpl = f"k_bhop<{prec}, 1, true, 0, {'true' if shape[4] else 'false'}, {shape[0]}>"
+    traffic = None
+    if len(vhs) == 3 and measured_traffic(name, BHOP_TRAFFIC_FILE, BHOP_SOURCES) is not None:
+        for ln in open(BHOP_TRAFFIC_FILE).read().splitlines():
+            if ln.startswith(name + ":") and tmpl in ln:
+                traffic = measured_traffic(name, BHOP_TRAFFIC_FILE, BHOP_SOURCES)
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
            "kernel": f"k_bhop<{prec},EPI_SCALE_CLOV> (batched A_oo^-1 H_oe hop, {name} storage, all right-hand "
                      "sides of all lattices in one launch)",
            "launch_shape": {"rhs_per_lane": shape[0], "waves_per_workgroup": shape[1], "workgroups_per_xcd": shape[2],

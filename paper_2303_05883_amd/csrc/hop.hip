@@ -323,10 +323,12 @@ __global__ void __launch_bounds__(256) k_hop2(HopArgs a) {
 // the zc planes in turn. At each z the input spinors of the tile's plane pass
 // through LDS, each loaded from memory once, by the lane of the same (xh, y),
 // and supply the x and y neighbours of every lane; the z neighbours are the
-// lane's own column (the next plane's spinor, loaded one step ahead, is the
-// z-forward neighbour and then this lane's LDS entry; the projected half of
-// the previous plane is kept for the z-backward hop); the t neighbours and the
-// links come from memory. Rows above and below the tile are staged by the
+// lane's own column (the spinors of the next two planes are held in
+// registers: the nearer is the z-forward neighbour and then this lane's LDS
+// entry, the farther is loaded two steps ahead, so that a chunk's last (halo)
+// plane is read at about the time the next chunk's workgroup reads it as its
+// own; the projected half of the previous plane is kept for the z-backward
+// hop); the t neighbours and the links come from memory. Rows above and below the tile are staged by the
 // first and last row of lanes unless the tile is the whole plane (WRAP).
 template <typename T>
 struct LdsWord;
@@ -415,7 +417,7 @@ __global__ void __launch_bounds__(512) k_hopz(HopArgs a, int ty, int zc) {
   const char* gb = a.gauge + (size_t)((1 - a.p) * 4) * a.link_stride;  // U_mu(x - mu), parity 1-p
   const size_t ls = a.link_stride;
 
-  cx<T> nxt[12], hnx[12], zb[6];
+  cx<T> nxt[12], nx2[12], hnx[12], zb[6];
   {
     const int zm = z0 == 0 ? g.lz - 1 : z0 - 1;
     cx<T> sp[12];
@@ -423,6 +425,10 @@ __global__ void __launch_bounds__(512) k_hopz(HopArgs a, int ty, int zc) {
     project<2, false>(sp, zb);
   }
   IO<P>::load_spinor(a.in, xh + yl * y + zl * z0 + tbase, nxt);
+  {
+    const int z1 = z0 + 1 == g.lz ? 0 : z0 + 1;
+    IO<P>::load_spinor(a.in, xh + yl * y + zl * z1 + tbase, nx2);
+  }
   if (halo) IO<P>::load_spinor(a.in, xh + yl * yh + zl * z0 + tbase, hnx);
   double red[3] = {0.0, 0.0, 0.0};
   for (int s = 0; s < zc; ++s) {
@@ -435,7 +441,12 @@ __global__ void __launch_bounds__(512) k_hopz(HopArgs a, int ty, int zc) {
     __syncthreads();
     const size_t row = yl * y + zl * z + tbase;
     const size_t i = row + xh;
-    IO<P>::load_spinor(a.in, xh + yl * y + zl * zf + tbase, nxt);  // z-forward neighbour, next LDS entry
+#pragma unroll
+    for (int k = 0; k < 12; ++k) nxt[k] = nx2[k];  // plane z + 1: z-forward neighbour, next LDS entry
+    if (s + 1 < zc) {
+      const int zf2 = zf + 1 == g.lz ? 0 : zf + 1;
+      IO<P>::load_spinor(a.in, xh + yl * y + zl * zf2 + tbase, nx2);  // plane z + 2, one step ahead
+    }
     if (halo && s + 1 < zc) IO<P>::load_spinor(a.in, xh + yl * yh + zl * zf + tbase, hnx);
     const int x = 2 * xh + ((y + z + t + a.p) & 1);
     const int xf = (x + 1 == g.lx) ? 0 : x + 1;
