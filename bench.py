@@ -113,6 +113,48 @@ def time_hop(torch, lat, prec, reps=40, nbuf=3):
     return e0.elapsed_time(e1) / reps
 
 
+def time_hop_rotated(torch, lqcd, lat, U, kappa, csw, prec, reps=30, nctx=3):
+    """Average Dslash duration (ms) with the links rotated as well as the
+    spinors: nctx contexts holding copies of the same gauge field, in the tuned
+    launch shape of lat, are launched in turn on one stream, each with its own
+    input and output, so that neither the links nor the spinors of a launch
+    were touched by the launch before it (the 256 MB Infinity Cache then
+    cannot serve them)."""
+    stream = torch.cuda.Stream()
+    Ud = torch.from_numpy(U).cuda()
+    lats = []
+    try:
+        for _ in range(nctx):
+            c = lqcd.Lattice(lat.dims, -1, stream=stream)
+            lats.append(c)
+            c.set_gauge(Ud)
+            c.set_clover(kappa, csw)
+            c.set_hop_shape(prec, *lat.get_hop_shape(prec))
+        del Ud
+        nbytes = lat.field_bytes(prec)
+        src = torch.from_numpy(fg.gaussian_spinor(lat.dims, 5)).cuda()
+        ins = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nctx)]
+        outs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nctx)]
+        for c, t in zip(lats, ins):
+            c.import_field(prec, 1, src, t)
+        del src
+        for k in range(nctx):
+            lats[k].apply_native("HOP_EO", prec, ins[k], outs[k])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for r in range(reps):
+            k = r % nctx
+            lats[k].apply_native("HOP_EO", prec, ins[k], outs[k])
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+    finally:
+        for c in lats:
+            c.close()
+
+
 def copy_probe(torch, mib=1024, reps=5):
     """A plain device copy of known size, best of reps (the practical HBM
     ceiling on this machine; also calibrates the traffic counters)."""
@@ -130,6 +172,25 @@ def copy_probe(torch, mib=1024, reps=5):
         e1.synchronize()
         best = min(best, e0.elapsed_time(e1))
     return 2 * (mib << 20) / (best * 1e-3) / 1e9
+
+
+def read_probe(torch, mib=1024, reps=5):
+    """A read-only stream of known size (torch's sum over FP32 words), best of
+    reps: a lower bound on the read bandwidth a kernel that mostly reads (the
+    hop reads 92% of its bytes) can reach on this machine."""
+    a = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
+    a.sum()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        a.sum()
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return (mib << 20) / (best * 1e-3) / 1e9
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x64.txt")
@@ -295,7 +356,7 @@ def tune(lat, lqcd, cached, label):
     log(f"autotuned {label}")
 
 
-def roofline_of(torch, lat, lqcd, dom, vh):
+def roofline_of(torch, lat, lqcd, dom, vh, U=None, kappa=None, csw=None):
     hop = {}
     for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.F16, "f16")):
         ms = time_hop(torch, lat, p)
@@ -314,6 +375,12 @@ def roofline_of(torch, lat, lqcd, dom, vh):
             "traffic": measured_traffic(dom, kernel=kname) if tuple(lat.dims) == DIMS else None,
             "kernel": f"{kname}<{pd},EPI_SCALE> (Dslash, {dom} storage)", "launch_shape": shape,
             "bytes_per_launch": HOP_BYTES[pd] * vh}
+    if U is not None and tuple(lat.dims) == DIMS:
+        ms = time_hop_rotated(torch, lqcd, lat, U, kappa, csw, pd)
+        gbs = HOP_BYTES[pd] * vh / (ms * 1e-3) / 1e9
+        roof["links_rotated"] = {"us": round(1000 * ms, 2), "achieved": round(gbs, 1),
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"hop {dom} with links rotated over 3 contexts: {roof['links_rotated']}")
     return roof, hop
 
 
@@ -405,8 +472,9 @@ def run_single(a, torch, lqcd):
     log(f"timed {a.steps} solves: {ms_step:.1f} ms each, {stats[-1]}")
 
     dom = "f32" if inner == lqcd.F32 else "f16"
-    roof, hop = roofline_of(torch, lat, lqcd, dom, vh)
+    roof, hop = roofline_of(torch, lat, lqcd, dom, vh, U, w["kappa"], w["csw"])
     roof["copy_gbs"] = round(copy_probe(torch), 1)
+    roof["read_gbs"] = round(read_probe(torch), 1)
     compare = None if a.no_compare else compare_solves(torch, lat, lqcd, bd)
     cpu = None if (a.no_cpu or a.workload != "wilson") else cpu_baseline(U, b, dims)
     if cpu:

@@ -186,16 +186,19 @@ int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const
  * workgroups per XCD, tile walk (0: linear in the site index, 1: every XCD
  * walks its range of blocks of each time slice, slice after slice; 2, 3: the
  * same with the range cut into 2 or 4 parts walked one after the other), 1 for
- * non-temporal loads of links and clover blocks}. With shape NULL or
- * shape[0] <= 0 the shape comes from the tune cache (LQCD_TUNE_CACHE) or,
- * without an entry, from timing every candidate with HIP events on the
- * batch's own fields (the choice is then written to the cache); otherwise the
- * given shape is used as is. The batch keeps the shape for the next
+ * non-temporal loads of links and clover blocks}. A batch holds one shape
+ * per kind of batched hop: the A_oo^-1 H_oe hop and the two XPAY hops of the
+ * BiCGStab iteration (with <rhat, v>, and with <t, s>, <t, t>), whose extra
+ * reads and sums hold more registers. With shape NULL or shape[0] <= 0 each
+ * kind's shape comes from the tune cache (LQCD_TUNE_CACHE) or, without an
+ * entry, from timing its candidates with HIP events on the batch's own fields
+ * (the choices are then written to the cache); otherwise the given shape is
+ * used as is for every kind. The batch keeps the shapes for the next
  * lqcd_solve_batch of the same contexts, nrhs and precision (which tunes by
  * itself when no shape was set). On return shape (if not NULL) holds the
- * shape in use and *us (if not NULL) the average duration in microseconds of
- * its A_oo^-1 H_oe hop over all right-hand sides of all lattices, timed with
- * HIP events on the contexts' stream over 20 launches. Allocates the batch's
+ * shape of the A_oo^-1 H_oe hop and *us (if not NULL) its average duration in
+ * microseconds over all right-hand sides of all lattices, timed with HIP
+ * events on the contexts' stream over 20 launches. Allocates the batch's
  * fields; EINVAL for a bad shape or precision, otherwise as lqcd_solve_batch. */
 int lqcd_batch_autotune(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, int prec, int shape[5], double* us);
 

@@ -6,15 +6,15 @@ from the definitions in ``oracle.dirac`` by gathering exactly the links and
 spinor values it depends on. Site lists are integer arrays of shape (N, 4)
 holding (x, y, z, t).
 
-Pinned against the whole-field oracle on small lattices (tests/
-test_oracle_sampled.py).
+Pinned against the whole-field oracle on small lattices
+(tests/test_oracle_pins.py).
 """
 
 from __future__ import annotations
 
 import numpy as np
 
-from .dirac import GAMMA, ONE4, sigma
+from .dirac import GAMMA, GAMMA5, ONE4, sigma
 
 
 def _dims(U):
@@ -134,3 +134,112 @@ def random_sites(dims, n: int, seed: int, parity=None):
         bad = (s.sum(axis=1) % 2) != parity
         s[bad, 0] = (s[bad, 0] + 1) % dims[0]
     return s
+
+
+# ---------------------------------------------------------------- domain wall
+# Five-dimensional fields are indexed [s, t, z, y, x, spin, colour] as in
+# oracle.dwf; the forms below return every s at the listed 4-d sites,
+# (Ls, N, 4, 3). The operator is the Moebius one of oracle.dwf:
+#   D = D_W (b5 + c5 S) + 1 - S,  D^dag = (b5 + c5 S^dag) D_W^dag + 1 - S^dag,
+#   D_W = (4 - M5) - H/2 on every slice,
+# with H^dag = gamma5 H gamma5 here (oracle.dwf takes H^dag term by term, so
+# the two agree only if both are right).
+
+P_PLUS = (ONE4 + GAMMA5) / 2
+P_MINUS = (ONE4 - GAMMA5) / 2
+
+
+def gather5(field, sites):
+    return field[:, sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
+
+
+def s_hop(v, mf: float, dag: bool = False):
+    """S v (or S^dag v) of values v at the same sites, (Ls, N, 4, 3):
+    (S v)_s = P_- v_{s+1} + P_+ v_{s-1}, v_{Ls} = -m_f v_0, v_{-1} = -m_f v_{Ls-1};
+    the adjoint exchanges the projectors."""
+    Ls = v.shape[0]
+    pu, pd = (P_PLUS, P_MINUS) if dag else (P_MINUS, P_PLUS)
+    out = np.empty_like(v)
+    for s in range(Ls):
+        up = v[s + 1] if s + 1 < Ls else -mf * v[0]
+        dn = v[s - 1] if s > 0 else -mf * v[Ls - 1]
+        out[s] = pu @ up + pd @ dn
+    return out
+
+
+def _hop5(U, v_at, t_bc, sites, Ls, gamma5_sandwich=False):
+    """H applied slice by slice at the sites; v_at(sites) gives (Ls, N, 4, 3).
+    With gamma5_sandwich the result is gamma5 H gamma5 = H^dag."""
+    out = np.empty((Ls, len(sites), 4, 3), dtype=np.complex128)
+    for s in range(Ls):
+        if gamma5_sandwich:
+            out[s] = GAMMA5 @ hop_at(U, lambda x, s=s: GAMMA5 @ v_at(x)[s], t_bc, sites)
+        else:
+            out[s] = hop_at(U, lambda x, s=s: v_at(x)[s], t_bc, sites)
+    return out
+
+
+def dwf_at(U, psi, M5, mf, b5, c5, t_bc, sites, dag: bool = False):
+    """(D psi) or (D^dag psi) at the listed 4-d sites, every s."""
+    sites = np.asarray(sites)
+    Ls = psi.shape[0]
+    own = gather5(psi, sites)
+    if not dag:
+        def phi_at(x):
+            v = gather5(psi, x)
+            return b5 * v + c5 * s_hop(v, mf)
+        dw = (4.0 - M5) * phi_at(sites) - 0.5 * _hop5(U, phi_at, t_bc, sites, Ls)
+        return dw + own - s_hop(own, mf)
+    u = (4.0 - M5) * own - 0.5 * _hop5(U, lambda x: gather5(psi, x), t_bc, sites, Ls, gamma5_sandwich=True)
+    return b5 * u + c5 * s_hop(u, mf, True) + own - s_hop(own, mf, True)
+
+
+def m5op_matrix(Ls, M5, mf, b5, c5):
+    """The site-local part M5op = (4 - M5)(b5 + c5 S) + 1 - S as an
+    (Ls 4) x (Ls 4) matrix over (s, spin), row and column index s 4 + spin."""
+    cols = []
+    for s in range(Ls):
+        for a in range(4):
+            e = np.zeros((Ls, 1, 4, 1), dtype=np.complex128)
+            e[s, 0, a, 0] = 1.0
+            col = (4.0 - M5) * (b5 * e + c5 * s_hop(e, mf)) + e - s_hop(e, mf)
+            cols.append(col[:, 0, :, 0].reshape(-1))
+    return np.array(cols).T
+
+
+def local_apply(K, v):
+    """(K v) at every site and colour for K over (s, spin), v (Ls, N, 4, 3)."""
+    Ls, n = v.shape[:2]
+    w = v.transpose(1, 3, 0, 2).reshape(n, 3, Ls * 4) @ K.T
+    return w.reshape(n, 3, Ls, 4).transpose(2, 0, 3, 1)
+
+
+def dwf_schur_at(U, x_even, M5, mf, b5, c5, t_bc, sites, dag: bool = False):
+    """(S_ee x) or (S_ee^dag x) at listed even sites, every s, for x supported
+    on the even sites: S_ee = M5op - Dhop M5op^-1 Dhop with the hopping part
+    Dhop = -1/2 H (b5 + c5 S), and S_ee^dag = M5op^dag - Dhop^dag M5op^-dag Dhop^dag,
+    Dhop^dag = -1/2 (b5 + c5 S^dag) H^dag."""
+    sites = np.asarray(sites)
+    Ls = x_even.shape[0]
+    dims = _dims(U)
+    K = m5op_matrix(Ls, M5, mf, b5, c5)
+    if dag:
+        K = np.conj(K.T)
+    Kinv = np.linalg.inv(K)
+
+    def dhop(v_at, at):
+        if not dag:
+            return -0.5 * _hop5(U, lambda x: b5 * v_at(x) + c5 * s_hop(v_at(x), mf), t_bc, at, Ls)
+        h = -0.5 * _hop5(U, v_at, t_bc, at, Ls, gamma5_sandwich=True)
+        return b5 * h + c5 * s_hop(h, mf, True)
+
+    nbr = np.concatenate([step(dims, sites, mu, s) for mu in range(4) for s in (+1, -1)])
+    lin = _linear(dims, nbr)
+    uniq, first = np.unique(lin, return_index=True)
+    odd_sites = nbr[first]
+    z = local_apply(Kinv, dhop(lambda x: gather5(x_even, x), odd_sites))
+
+    def z_at(x):
+        return z[:, np.searchsorted(uniq, _linear(dims, x))]
+
+    return local_apply(K, gather5(x_even, sites)) - dhop(z_at, sites)

@@ -119,6 +119,11 @@ __global__ void __launch_bounds__(1024) k_bfin(const BLat* lat, const BSeg* seg,
 
 // ------------------------------------------------------------------ host side
 
+// kinds of batched hop, each with a launch shape of its own
+enum BKind { BK_SC = 0, BK_DOT = 1, BK_TS = 2, BK_N = 3 };
+
+inline int bkind(int epi, int red) { return epi != EPI_XPAY ? BK_SC : (red == RED_DOT ? BK_DOT : BK_TS); }
+
 struct Batch {
   std::vector<lqcd_ctx*> ctx;
   std::vector<BLat> hlat;
@@ -135,7 +140,7 @@ struct Batch {
   Scal* hscal = nullptr;     // pinned host copies of the segments' Scal
   int prec = 1, xprec = 1;
   int hop_tiles = 0, blas_tiles = 0;
-  int bound[9] = {};
+  int bound[BK_N][9] = {};
   bool clover = false;
   hipStream_t stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -145,12 +150,15 @@ struct Batch {
   std::vector<std::pair<int, int>> key;
   Scal* dscal_all = nullptr;
   bool ready = false;  // every buffer allocated
-  BShape shape;        // launch shape of the batched hop
-  bool tuned = false;  // shape chosen for this batch
-  int2* dtiles = nullptr;  // device tile list of the current shape
-  size_t tile_cap = 0;     // its capacity (tiles of the largest shape)
-  std::vector<int2> htiles;
-  double hop_us = 0;   // its average duration when timed (microseconds)
+  // launch shape and device tile list of each kind of batched hop (the
+  // A_oo^-1 H_oe hop, the XPAY hop with <rhat, v>, the XPAY hop with <t, s>
+  // and <t, t>): the XPAY forms hold more registers and are tuned apart
+  BShape shape[BK_N];
+  bool tuned = false;           // shapes chosen for this batch
+  int2* dtiles[BK_N] = {};      // device tile lists of the current shapes
+  size_t tile_cap = 0;          // capacity of each (tiles of the largest shape)
+  std::vector<int2> htiles[BK_N];
+  double hop_us = 0;  // average duration of the A_oo^-1 H_oe hop when timed (microseconds)
   int max_rhs = 1;
 
   ~Batch() {
@@ -176,7 +184,8 @@ int batch_hop(Batch& B, hipStream_t s, int in_sel, int out_sel, int own_sel, int
   BHopArgs a;
   a.lat = B.dlat;
   a.seg = B.dseg;
-  a.tiles = B.dtiles;
+  const int kind = bkind(epi, red);
+  a.tiles = B.dtiles[kind];
   a.nlat = (int)B.hlat.size();
   a.in_sel = in_sel;
   a.out_sel = out_sel;
@@ -185,10 +194,10 @@ int batch_hop(Batch& B, hipStream_t s, int in_sel, int out_sel, int own_sel, int
   a.out_parity = parity;
   a.clov_slot = clov_slot;
   a.scale_mode = scale_mode;
-  for (int k = 0; k < 9; ++k) a.bound[k] = B.bound[k];
-  if (B.prec == 1) return launch_bhop<1>(a, B.shape, epi, red, B.clover, s);
-  if (B.prec == 2) return launch_bhop<2>(a, B.shape, epi, red, B.clover, s);
-  return launch_bhop<0>(a, B.shape, epi, red, B.clover, s);
+  for (int k = 0; k < 9; ++k) a.bound[k] = B.bound[kind][k];
+  if (B.prec == 1) return launch_bhop<1>(a, B.shape[kind], epi, red, B.clover, s);
+  if (B.prec == 2) return launch_bhop<2>(a, B.shape[kind], epi, red, B.clover, s);
+  return launch_bhop<0>(a, B.shape[kind], epi, red, B.clover, s);
 }
 
 template <int OP>
@@ -274,11 +283,11 @@ void free_batch(void* p) { delete reinterpret_cast<Batch*>(p); }
 // Make sh the batch's launch shape: the tile list of its walk and group sets,
 // dealt to the XCDs in 8 contiguous chunks, uploaded (on the batch's stream)
 // and a captured iteration graph dropped (its launches hold the old shape).
-int set_shape(Batch& B, const BShape& sh) {
-  std::vector<int2>& tl = B.htiles;
+int set_shape(Batch& B, int kind, const BShape& sh) {
+  std::vector<int2>& tl = B.htiles[kind];
   tl.clear();
   for (int k = 0; k < 8; ++k) {
-    B.bound[k] = (int)tl.size();
+    B.bound[kind][k] = (int)tl.size();
     for (size_t l = 0; l < B.hlat.size(); ++l) {
       const BLat& L = B.hlat[l];
       const int ngroup = (L.nrhs + sh.nb - 1) / sh.nb;
@@ -307,10 +316,10 @@ int set_shape(Batch& B, const BShape& sh) {
       }
     }
   }
-  B.bound[8] = (int)tl.size();
+  B.bound[kind][8] = (int)tl.size();
   if (tl.size() > B.tile_cap) return set_error(LQCD_EINVAL, "batched hop tile list exceeds its buffer");
-  LQ_HIP(hipMemcpyAsync(B.dtiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, B.stream));
-  B.shape = sh;
+  LQ_HIP(hipMemcpyAsync(B.dtiles[kind], tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, B.stream));
+  B.shape[kind] = sh;
   if (B.exec) {
     (void)hipStreamSynchronize(B.stream);
     (void)hipGraphExecDestroy(B.exec);
@@ -427,7 +436,7 @@ int batch_prepare(lqcd_ctx* const* ctxs, const int* nrhs, int nlattices, int IP,
     size_t cap = 0;
     for (const BLat& L : B.hlat) cap += (size_t)L.nsb * L.nrhs;
     B.tile_cap = cap;
-    LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dtiles), cap * sizeof(int2)));
+    for (int k = 0; k < BK_N; ++k) LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dtiles[k]), cap * sizeof(int2)));
     LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dlat), B.hlat.size() * sizeof(BLat)));
     LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.dseg), B.hseg.size() * sizeof(BSeg)));
     LQ_TRY(B.dev_alloc(reinterpret_cast<void**>(&B.snorm), (size_t)nseg * 16 * sizeof(double)));
@@ -460,19 +469,24 @@ bool shape_ok(const Batch& B, const BShape& sh) {
          sh.nslot <= 4096 && sh.walk >= 0 && sh.walk <= 3 && (sh.nt == 0 || sh.nt == 1);
 }
 
-// Average duration (us) of the batched A_oo^-1 H_oe hop (the first hop of the
-// Schur operator, input F_P, output F_Y) with shape sh, HIP events on the
-// batch's stream, reps launches after two warm-up launches.
-int time_bhop(Batch& B, const BShape& sh, int reps, double* us) {
-  LQ_TRY(set_shape(B, sh));
+// Average duration (us) of one kind of batched hop with shape sh, HIP events
+// on the batch's stream, reps launches after two warm-up launches: the
+// A_oo^-1 H_oe hop (F_P -> F_Y) or one of the two XPAY hops of the solver's
+// iteration (F_Y -> F_V with <rhat, v>, F_Y -> F_T with <t, s>, <t, t>).
+int time_bhop(Batch& B, int kind, const BShape& sh, int reps, double* us) {
+  LQ_TRY(set_shape(B, kind, sh));
+  auto launch = [&]() {
+    if (kind == BK_SC) return batch_hop(B, B.stream, F_P, F_Y, -1, -1, 1, EPI_SCALE_CLOV, RED_NONE, 3, 0);
+    if (kind == BK_DOT) return batch_hop(B, B.stream, F_Y, F_V, F_P, F_RHAT, 0, EPI_XPAY, RED_DOT, 0, 1);
+    return batch_hop(B, B.stream, F_Y, F_T, F_S, -1, 0, EPI_XPAY, RED_TS, 0, 1);
+  };
   hipEvent_t e0, e1;
   LQ_HIP(hipEventCreate(&e0));
   LQ_HIP(hipEventCreate(&e1));
   int st = LQCD_OK;
-  for (int k = 0; k < 2 && st == LQCD_OK; ++k) st = batch_hop(B, B.stream, F_P, F_Y, -1, -1, 1, EPI_SCALE_CLOV, RED_NONE, 3, 0);
+  for (int k = 0; k < 2 && st == LQCD_OK; ++k) st = launch();
   (void)hipEventRecord(e0, B.stream);
-  for (int k = 0; k < reps && st == LQCD_OK; ++k)
-    st = batch_hop(B, B.stream, F_P, F_Y, -1, -1, 1, EPI_SCALE_CLOV, RED_NONE, 3, 0);
+  for (int k = 0; k < reps && st == LQCD_OK; ++k) st = launch();
   (void)hipEventRecord(e1, B.stream);
   (void)hipEventSynchronize(e1);
   float ms = 0;
@@ -484,80 +498,95 @@ int time_bhop(Batch& B, const BShape& sh, int reps, double* us) {
   return LQCD_OK;
 }
 
-// Pick the batched hop's launch shape for this batch (right-hand sides per
-// lane x wavefronts per workgroup x workgroups per XCD) by timing every
-// candidate on the batch's own fields; a forced shape (nb > 0) is only timed.
-// The choice is read from and written to the tune cache (LQCD_TUNE_CACHE).
+// Pick the launch shape of each kind of batched hop for this batch
+// (right-hand sides per lane x wavefronts per workgroup x workgroups per XCD x
+// walk) by timing the candidates on the batch's own fields; a forced shape
+// (nb > 0) is used for every kind and only the A_oo^-1 H_oe hop is timed.
+// The choices are read from and written to the tune cache (LQCD_TUNE_CACHE),
+// one entry per kind.
 int batch_tune(Batch& B, bool sweep, const BShape* forced = nullptr) {
-  const std::string key = batch_key(B);
+  const std::string base = batch_key(B);
+  const std::string keys[BK_N] = {base, base + ":xpay_dot", base + ":xpay_ts"};
+  auto unpack = [](const int v[4]) {
+    BShape sh;
+    sh.nw = v[0] / 64;
+    sh.nb = v[1];
+    sh.nslot = v[2];
+    sh.walk = v[3] & 3;
+    sh.nt = (v[3] >> 2) & 1;
+    return sh;
+  };
   if (!sweep && !forced) {
-    int v[4];
-    if (tune_cache_get(key, v)) {
-      BShape sh;
-      sh.nw = v[0] / 64;
-      sh.nb = v[1];
-      sh.nslot = v[2];
-      sh.walk = v[3] & 3;
-      sh.nt = (v[3] >> 2) & 1;
-      if (shape_ok(B, sh)) {
-        LQ_TRY(set_shape(B, sh));
-        B.tuned = true;
-        return LQCD_OK;
-      }
+    BShape got[BK_N];
+    bool all = true;
+    for (int k = 0; k < BK_N && all; ++k) {
+      int v[4];
+      all = tune_cache_get(keys[k], v) && shape_ok(B, got[k] = unpack(v));
+    }
+    if (all) {
+      for (int k = 0; k < BK_N; ++k) LQ_TRY(set_shape(B, k, got[k]));
+      B.tuned = true;
+      return LQCD_OK;
     }
   }
   // the timed launches read zeroed fields of every segment, none masked
   for (size_t s = 0; s < B.hseg.size(); ++s) {
     lqcd_ctx* c = B.ctx[B.seg_lat[s]];
-    LQ_TRY(blas_zero(c, B.prec, B.hseg[s].f[F_P]));
+    for (int f : {F_P, F_Y, F_S, F_RHAT}) LQ_TRY(blas_zero(c, B.prec, B.hseg[s].f[f]));
   }
   LQ_HIP(hipMemsetAsync(B.dscal_all, 0, B.hseg.size() * sizeof(Scal), B.stream));
-  std::vector<BShape> cand;
   if (forced) {
     if (!shape_ok(B, *forced)) return set_error(LQCD_EINVAL, "bad batched hop launch shape");
-    cand.push_back(*forced);
-  } else {
-    for (int nb = 1; nb <= (B.prec == 0 ? 2 : 4); ++nb) {
-      const int ngroup = (B.max_rhs + nb - 1) / nb;
-      for (int nw : {1, std::min(BHOP_MAX_WAVES, ngroup)})
-        for (int nslot : {128, 256, 512})
-          for (int walk = 0; walk < 4; ++walk)
-            for (int nt = 0; nt < 1; ++nt) {  // streaming loads measured slower: forced shapes only
-              BShape sh;
-              sh.nb = nb;
-              sh.nw = nw;
-              sh.nslot = nslot;
-              sh.walk = walk;
-              sh.nt = nt;
-              bool dup = false;
-              for (const BShape& c : cand)
-                dup = dup || (c.nb == sh.nb && c.nw == sh.nw && c.nslot == sh.nslot && c.walk == sh.walk &&
-                              c.nt == sh.nt);
-              if (!dup) cand.push_back(sh);
-            }
-    }
+    for (int k = BK_N - 1; k >= 0; --k) LQ_TRY(set_shape(B, k, *forced));
+    LQ_TRY(time_bhop(B, BK_SC, *forced, 5, &B.hop_us));
+    B.tuned = true;
+    return LQCD_OK;
   }
   const bool verbose = std::getenv("LQCD_TUNE_VERBOSE") != nullptr;
-  BShape best = cand[0];
-  double best_us = 1e30;
-  for (const BShape& sh : cand) {
-    double us = 0;
-    LQ_TRY(time_bhop(B, sh, 5, &us));
-    if (verbose)
-      std::fprintf(stderr, "[lqcd tune] %s nb %d nw %d nslot %d walk %d nt %d: %.1f us\n", key.c_str(), sh.nb,
-                   sh.nw, sh.nslot, sh.walk, sh.nt, us);
-    if (us < best_us) {
-      best_us = us;
-      best = sh;
+  for (int kind = 0; kind < BK_N; ++kind) {
+    // candidates: 1-4 right-hand sides per lane (1-2 in FP64) x 1, 2, 3, 4, 6
+    // or all groups per workgroup (at most 8 waves) x 128, 256, 512
+    // workgroups per XCD x the walks (the XPAY forms: linear and slab, the
+    // split slabs never won for them); streaming loads measured slower
+    std::vector<BShape> cand;
+    for (int nb = 1; nb <= (B.prec == 0 ? 2 : 4); ++nb) {
+      const int ngroup = (B.max_rhs + nb - 1) / nb;
+      for (int nw : {1, 2, 3, 4, 6, ngroup}) {
+        if (nw > ngroup || nw > BHOP_MAX_WAVES) continue;
+        for (int nslot : {128, 256, 512})
+          for (int walk = 0; walk < (kind == BK_SC ? 4 : 2); ++walk) {
+            BShape sh;
+            sh.nb = nb;
+            sh.nw = nw;
+            sh.nslot = nslot;
+            sh.walk = walk;
+            sh.nt = 0;
+            bool dup = false;
+            for (const BShape& c : cand)
+              dup = dup || (c.nb == sh.nb && c.nw == sh.nw && c.nslot == sh.nslot && c.walk == sh.walk);
+            if (!dup) cand.push_back(sh);
+          }
+      }
     }
-  }
-  LQ_TRY(set_shape(B, best));
-  B.hop_us = best_us;
-  B.tuned = true;
-  if (!forced) {
+    BShape best = cand[0];
+    double best_us = 1e30;
+    for (const BShape& sh : cand) {
+      double us = 0;
+      LQ_TRY(time_bhop(B, kind, sh, 5, &us));
+      if (verbose)
+        std::fprintf(stderr, "[lqcd tune] %s nb %d nw %d nslot %d walk %d nt %d: %.1f us\n", keys[kind].c_str(),
+                     sh.nb, sh.nw, sh.nslot, sh.walk, sh.nt, us);
+      if (us < best_us) {
+        best_us = us;
+        best = sh;
+      }
+    }
+    LQ_TRY(set_shape(B, kind, best));
+    if (kind == BK_SC) B.hop_us = best_us;
     const int v[4] = {64 * best.nw, best.nb, best.nslot, best.walk | (best.nt << 2)};
-    LQ_TRY(tune_cache_put(key, v, best_us));
+    LQ_TRY(tune_cache_put(keys[kind], v, best_us));
   }
+  B.tuned = true;
   return LQCD_OK;
 }
 
@@ -786,17 +815,18 @@ extern "C" int lqcd_batch_autotune(lqcd_ctx* const* ctxs, const int* nrhs, int n
     B.tuned = false;
     LQ_TRY(batch_tune(B, false));
   }
-  // time the chosen shape on its own (also after a cache hit)
+  // time the chosen shape of the A_oo^-1 H_oe hop on its own (also after a cache hit)
+  const BShape sh = B.shape[BK_SC];
   double t = 0;
-  LQ_TRY(time_bhop(B, B.shape, 20, &t));
+  LQ_TRY(time_bhop(B, BK_SC, sh, 20, &t));
   B.hop_us = t;
   if (us) *us = t;
   if (shape) {
-    shape[0] = B.shape.nb;
-    shape[1] = B.shape.nw;
-    shape[2] = B.shape.nslot;
-    shape[3] = B.shape.walk;
-    shape[4] = B.shape.nt;
+    shape[0] = sh.nb;
+    shape[1] = sh.nw;
+    shape[2] = sh.nslot;
+    shape[3] = sh.walk;
+    shape[4] = sh.nt;
   }
   LQ_HIP(hipStreamSynchronize(B.stream));
   return LQCD_OK;

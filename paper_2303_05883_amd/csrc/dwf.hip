@@ -15,9 +15,10 @@
 // first. One lane computes one 5-d site: the Ls lanes of a 4-d site load the
 // same links (one cache line serves them all) and spinors at consecutive j, and
 // the s-hops come from the neighbouring lanes through LDS. A launch covers
-// both parities. Where lz is a multiple of 8 the workgroups walk XCD z-slabs
-// (dwf_site); measured on 64x32x16x8 x 8 this cuts the L2 misses of the z and
-// t neighbours and the FP64 D time by about 8 %, FP32 by about 15 %.
+// both parities. The workgroups walk the lattice in an XCD-aware order
+// (dwf_site, dwf_walk): each XCD takes a range of y rows (or of z planes) in
+// every slice and walks it so that the neighbours of the sites in flight were
+// read shortly before by the same XCD and are still in its L2.
 //
 // Kernels per application: D with c5 = 0 (b5 folded into the diagonal and the
 // hop scale) and D^dag are one kernel each; D with c5 != 0 first forms
@@ -26,6 +27,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "dwf.h"
@@ -46,33 +48,65 @@ struct DwfArgs {
   char* out;
   size_t hb;  // bytes of one parity half
   int Ls;
-  int spb;  // 5-d sites per workgroup
-  int hz;   // > 0: z extent of one XCD slab (lz = 8 hz); 0: linear order
+  int spb;   // 5-d sites per workgroup
+  int walk;  // 0: linear order; 1: XCD z-slabs of hw planes (lz = 8 hw); 2: XCD y-ranges of hw rows (ly = 8 hw)
+  int hw;
   double d4;         // 4 - M5
   double b5, c5, mf;
 };
 
-// The 5-d site of this lane, or false past the end. With hz > 0, XCD k (the
-// workgroups are dealt to the 8 XCDs round-robin) takes the slab z in
-// [k hz, (k+1) hz) and walks it x, y fastest, then z, then t, so that the z
-// and t neighbours of the sites in flight were read shortly before by the same
-// XCD and are still in its L2.
+// The 5-d site of this lane, or false past the end. XCD k (the workgroups
+// are dealt to the 8 XCDs round-robin) takes
+//   walk 1: the slab z in [k hw, (k+1) hw), walked x, y fastest, then z, then
+//           t: the z and t neighbours were read one z plane or one slab slice
+//           earlier;
+//   walk 2: the rows y in [k hw, (k+1) hw), walked x fastest, then those rows,
+//           then t, then z: the t neighbours were read one step earlier and the
+//           z neighbours lt steps earlier, a working set of lt + 1 slices of
+//           lx/2 x hw sites (the neighbours of the two edge rows come from the
+//           other XCDs' ranges).
+// All Ls lanes of a 4-d site are in one workgroup in every walk.
 __device__ inline bool dwf_site(const DwfArgs& a, size_t& j) {
   const Geom& g = a.g;
   if (threadIdx.x >= a.spb) return false;
-  if (a.hz == 0) {
+  if (a.walk == 0) {
     j = (size_t)blockIdx.x * a.spb + threadIdx.x;
     return j < (size_t)g.vh * a.Ls;
   }
   const int k = blockIdx.x & 7;
   const size_t q = (size_t)(blockIdx.x >> 3) * a.spb + threadIdx.x;
   const size_t q4 = q / a.Ls, s = q - q4 * a.Ls;
-  const size_t xy = (size_t)g.lxh * g.ly;
-  if (q4 >= xy * a.hz * g.lt) return false;
-  const size_t xyi = q4 % xy, rest = q4 / xy;
-  const size_t zin = rest % a.hz, t = rest / a.hz;
-  j = (xyi + xy * ((size_t)k * a.hz + zin + (size_t)g.lz * t)) * a.Ls + s;
+  if (a.walk == 1) {
+    const size_t xy = (size_t)g.lxh * g.ly;
+    if (q4 >= xy * a.hw * g.lt) return false;
+    const size_t xyi = q4 % xy, rest = q4 / xy;
+    const size_t zin = rest % a.hw, t = rest / a.hw;
+    j = (xyi + xy * ((size_t)k * a.hw + zin + (size_t)g.lz * t)) * a.Ls + s;
+    return true;
+  }
+  const size_t rows = (size_t)g.lxh * a.hw;
+  if (q4 >= rows * g.lt * g.lz) return false;
+  const size_t xr = q4 % rows, rest = q4 / rows;
+  const size_t t = rest % g.lt, z = rest / g.lt;
+  const size_t xin = xr % g.lxh, yin = xr / g.lxh;
+  j = (xin + (size_t)g.lxh * ((size_t)k * a.hw + yin + (size_t)g.ly * (z + (size_t)g.lz * t))) * a.Ls + s;
   return true;
+}
+
+// The walk of a lattice: LQCD_DWF_WALK (0 linear, 1 z-slabs, 2 y-ranges)
+// where it fits the lattice, else y-ranges where ly is a multiple of 8, else
+// z-slabs where lz is, else linear; returns the grid's workgroup count for n
+// 5-d sites of one parity.
+unsigned dwf_walk(const Geom& g, DwfArgs& a, size_t n) {
+  const bool y_ok = g.ly % 8 == 0, z_ok = g.lz % 8 == 0;
+  int w = y_ok ? 2 : (z_ok ? 1 : 0);
+  if (const char* env = std::getenv("LQCD_DWF_WALK")) {
+    const int f = std::atoi(env);
+    if (f == 0 || (f == 1 && z_ok) || (f == 2 && y_ok)) w = f;
+  }
+  a.walk = w;
+  a.hw = w == 2 ? g.ly / 8 : (w == 1 ? g.lz / 8 : 0);
+  return w ? 8u * (unsigned)((n / 8 + a.spb - 1) / a.spb) : (unsigned)((n + a.spb - 1) / a.spb);
 }
 
 // The s-neighbours of a lane: P_+ and P_- of every lane's field x go to LDS
@@ -451,13 +485,11 @@ int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const vo
   a.hb = half_bytes(prec, c->g.vh, d.Ls);
   a.Ls = d.Ls;
   a.spb = (DWB / d.Ls) * d.Ls;
-  a.hz = c->g.lz % 8 == 0 ? c->g.lz / 8 : 0;
   a.d4 = 4.0 - d.M5;
   a.b5 = d.b5;
   a.c5 = d.c5;
   a.mf = d.mf;
-  const size_t n = (size_t)c->g.vh * d.Ls;
-  const unsigned nb = a.hz ? 8u * (unsigned)((n / 8 + a.spb - 1) / a.spb) : (unsigned)((n + a.spb - 1) / a.spb);
+  const unsigned nb = dwf_walk(c->g, a, (size_t)c->g.vh * d.Ls);
   const dim3 grid(nb, 2), block((a.spb + 63) / 64 * 64);
   if (mob) {
     DwfArgs f = a;
@@ -755,13 +787,11 @@ int eo_setup(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, const double* mats
   a.hb = half_bytes(prec, c->g.vh, d.Ls);
   a.Ls = d.Ls;
   a.spb = (DWB / d.Ls) * d.Ls;
-  a.hz = c->g.lz % 8 == 0 ? c->g.lz / 8 : 0;
   a.d4 = 4.0 - d.M5;
   a.b5 = d.b5;
   a.c5 = d.c5;
   a.mf = d.mf;
-  const size_t n = (size_t)c->g.vh * d.Ls;
-  e.grid = dim3(a.hz ? 8u * (unsigned)((n / 8 + a.spb - 1) / a.spb) : (unsigned)((n + a.spb - 1) / a.spb));
+  e.grid = dim3(dwf_walk(c->g, a, (size_t)c->g.vh * d.Ls));
   e.block = dim3((a.spb + 63) / 64 * 64);
   return LQCD_OK;
 }

@@ -594,10 +594,10 @@ class Lattice:
 
 
 def batch_autotune(lattices, nrhs, prec=F32, shape=None):
-    """Launch shape of the batched hop for these lattices with nrhs[k]
-    right-hand sides each (tuned, cached or, with shape = (nb, nw, nslot,
-    walk, nt), forced); returns (shape, microseconds per launch of the
-    A_oo^-1 H_oe hop)."""
+    """Launch shapes of the batched hops for these lattices with nrhs[k]
+    right-hand sides each (tuned per kind of hop, cached or, with shape =
+    (nb, nw, nslot, walk, nt), forced for every kind); returns (shape of the
+    A_oo^-1 H_oe hop, microseconds per launch of that hop)."""
     lib = load()
     n = len(lattices)
     ctxs = (C.c_void_p * n)(*[lat.handle.value for lat in lattices])

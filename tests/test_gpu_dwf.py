@@ -23,9 +23,10 @@ def field5(dims, Ls, seed):
     return (rng.normal(size=shape) + 1j * rng.normal(size=shape)) / np.sqrt(2)
 
 
-# (4, 4, 16, 4): two z planes per XCD slab, as on the benchmarked 64x32x16x8
+# walks: (4, 4, 16, 4) XCD z-slabs of two planes; (8, 8, 8, 8), (4, 8, 4, 4),
+# (4, 16, 2, 4) XCD y-ranges (as on the benchmarked 64x32x16x8); the rest linear
 @pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 4), ((2, 2, 2, 4), 5), ((4, 6, 8, 10), 3), ((8, 8, 8, 8), 8),
-                                     ((4, 4, 4, 4), 1), ((4, 4, 16, 4), 8)])
+                                     ((4, 4, 4, 4), 1), ((4, 4, 16, 4), 8), ((4, 8, 4, 4), 3), ((4, 16, 2, 4), 5)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("t_bc", [-1, 1])
 @pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5), (1.3, 0.0)])
@@ -159,3 +160,73 @@ def test_dwf_adjoint_at_benchmark_size():
         rhs = torch.vdot(out.flatten(), b.flatten()).item()
         # (S_ee: both outputs vanish on the odd sites, so only the even sites of a and b enter)
         assert abs(lhs - rhs) <= 1e-11 * abs(lhs), (apply, lhs, rhs)
+
+
+def test_dwf_sampled_at_benchmark_size():
+    """D, D^dag, S_ee and S_ee^dag at the benchmarked size (64x32x16x8, Ls 8,
+    Moebius b5 1.5, c5 0.5) against the oracle evaluated site by site
+    (oracle.sampled) at random sites and at sites on the edges of every
+    direction (the antiperiodic t boundary and the XCD z-slab boundaries),
+    FP64 to 1e-13 and FP32 to 1e-5."""
+    from oracle import sampled
+    dims, Ls, M5, mf, b5, c5 = (64, 32, 16, 8), 8, 1.8, 0.05, 1.5, 0.5
+    U = fg.gauge_field(dims, 125, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    psi = field5(dims, Ls, 126)
+    x = to_dev(psi)
+    out = to_dev(np.zeros_like(psi))
+
+    def sites(parity, seed):
+        s = sampled.random_sites(dims, 40, seed, parity)
+        edges = []
+        for t in (0, dims[3] - 1):
+            for z in (0, 1, 2, dims[2] - 1):
+                for xx in (0, dims[0] - 1):
+                    c = np.array([xx, dims[1] - 1, z, t])
+                    if c.sum() % 2 != parity:
+                        c[1] = 0
+                    edges.append(c)
+        return np.concatenate([s, np.array(edges)])
+
+    sa = np.concatenate([sites(0, 127), sites(1, 128)])
+    se = sites(0, 129)
+    xe = dwf.parity5(dwf.DomainWall(U, M5, mf, Ls, -1, b5, c5), psi, 0)
+    for dag in (False, True):
+        want = sampled.dwf_at(U, psi, M5, mf, b5, c5, -1, sa, dag)
+        want_s = sampled.dwf_schur_at(U, xe, M5, mf, b5, c5, -1, se, dag)
+        for prec in (0, 1):
+            lat.dwf_apply(Ls, M5, mf, prec, x, out, dag=dag, b5=b5, c5=c5)
+            got = sampled.gather5(from_dev(out), sa)
+            assert dirac.rel_l2(got, want) <= TOL[prec], ("D", dag, prec)
+            lat.dwf_apply_schur(Ls, M5, mf, prec, x, out, dag=dag, b5=b5, c5=c5)
+            got = sampled.gather5(from_dev(out), se)
+            assert dirac.rel_l2(got, want_s) <= TOL[prec], ("S_ee", dag, prec)
+
+
+def test_dwf_walks_agree(monkeypatch):
+    """The three XCD walks (linear, z-slabs, y-ranges) only reorder the sites:
+    D, D^dag and S_ee agree bit for bit on a lattice all three fit, and match
+    the oracle."""
+    dims, Ls, b5, c5 = (4, 8, 8, 4), 4, 1.5, 0.5
+    U = fg.gauge_field(dims, 131, "haar")
+    op = dwf.DomainWall(U, 1.8, 0.05, Ls, -1, b5, c5)
+    psi = field5(dims, Ls, 132)
+    lat = lattice(dims, U, 0.12, 0.0)
+    results = {}
+    for walk in ("0", "1", "2"):
+        monkeypatch.setenv("LQCD_DWF_WALK", walk)
+        outs = []
+        for prec in (0, 1):
+            for dag in (False, True):
+                out = to_dev(np.zeros_like(psi))
+                lat.dwf_apply(Ls, 1.8, 0.05, prec, to_dev(psi), out, dag=dag, b5=b5, c5=c5)
+                outs.append(from_dev(out))
+            out = to_dev(np.zeros_like(psi))
+            lat.dwf_apply_schur(Ls, 1.8, 0.05, prec, to_dev(psi), out, b5=b5, c5=c5)
+            outs.append(from_dev(out))
+        results[walk] = outs
+    for walk in ("1", "2"):
+        for a, b in zip(results["0"], results[walk]):
+            assert np.array_equal(a, b), walk
+    assert dirac.rel_l2(results["2"][0], op.D(psi)) <= TOL[0]
+    assert dirac.rel_l2(results["2"][1], op.Ddag(psi)) <= TOL[0]

@@ -298,6 +298,32 @@ def test_sampled_matches_whole_field():
     assert np.abs(got - sampled.gather(op.schur(xe), se)).max() < 1e-12
 
 
+@pytest.mark.parametrize("b5,c5,t_bc", [(1.5, 0.5, -1), (1.0, 0.0, 1)])
+def test_sampled_domain_wall_matches_whole_field(b5, c5, t_bc):
+    """The site-sampled domain-wall D, D^dag, S_ee and S_ee^dag (H^dag as
+    gamma5 H gamma5, M5op^-1 from its (s, spin) matrix) against the whole-field
+    forms of oracle.dwf (H^dag term by term, M5op^-1 from unit vectors) on a
+    small lattice; a wrong projector, wall sign or coefficient on either side
+    fails."""
+    from oracle import dwf
+    dims, Ls, M5, mf = (4, 6, 4, 8), 5, 1.8, 0.07
+    U = field(dims, 111, "smooth", 0.4)
+    rng = np.random.default_rng(112)
+    shape = (Ls, dims[3], dims[2], dims[1], dims[0], 4, 3)
+    psi = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    op = dwf.DomainWall(U, M5, mf, Ls, t_bc, b5, c5)
+    sites = sampled.random_sites(dims, 30, 9)
+    for dag, whole in ((False, op.D(psi)), (True, op.Ddag(psi))):
+        got = sampled.dwf_at(U, psi, M5, mf, b5, c5, t_bc, sites, dag)
+        assert np.abs(got - sampled.gather5(whole, sites)).max() < 1e-12, dag
+    eo = dwf.EvenOdd(op)
+    xe = dwf.parity5(op, psi, 0)
+    se = sampled.random_sites(dims, 30, 10, parity=0)
+    for dag, whole in ((False, eo.schur(xe)), (True, eo.schur_dag(xe))):
+        got = sampled.dwf_schur_at(U, xe, M5, mf, b5, c5, t_bc, se, dag)
+        assert np.abs(got - sampled.gather5(whole, se)).max() < 1e-11, dag
+
+
 def test_pins_catch_planted_mistakes(monkeypatch):
     """A plausible mistake planted in the oracle (on the CPU) fails a pin."""
     dims = (4, 4, 4, 4)
