@@ -174,25 +174,6 @@ def copy_probe(torch, mib=1024, reps=5):
     return 2 * (mib << 20) / (best * 1e-3) / 1e9
 
 
-def read_probe(torch, mib=1024, reps=5):
-    """A read-only stream of known size (torch's sum over FP32 words), best of
-    reps: a lower bound on the read bandwidth a kernel that mostly reads (the
-    hop reads 92% of its bytes) can reach on this machine."""
-    a = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
-    a.sum()
-    torch.cuda.synchronize()
-    best = float("inf")
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        a.sum()
-        e1.record()
-        e1.synchronize()
-        best = min(best, e0.elapsed_time(e1))
-    return (mib << 20) / (best * 1e-3) / 1e9
-
-
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x64.txt")
 KERNEL_SOURCES = ("hop.hip", "hopcore.h", "fieldio.h")
 
@@ -474,7 +455,7 @@ def run_single(a, torch, lqcd):
     dom = "f32" if inner == lqcd.F32 else "f16"
     roof, hop = roofline_of(torch, lat, lqcd, dom, vh, U, w["kappa"], w["csw"])
     roof["copy_gbs"] = round(copy_probe(torch), 1)
-    roof["read_gbs"] = round(read_probe(torch), 1)
+    roof["read_gbs"] = round(lat.bandwidth_probe(0), 1)
     compare = None if a.no_compare else compare_solves(torch, lat, lqcd, bd)
     cpu = None if (a.no_cpu or a.workload != "wilson") else cpu_baseline(U, b, dims)
     if cpu:

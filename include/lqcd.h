@@ -121,14 +121,17 @@ typedef struct {
   int max_iter;         /* cap on inner BiCGStab iterations over the whole solve */
   int max_outer;        /* cap on outer (defect-correction) iterations */
   int inner_prec;       /* LQCD_F64: plain FP64 BiCGStab; F32/F16: mixed precision */
-  double inner_tol;     /* relative tolerance of each inner solve (mixed only) */
+  double inner_tol;     /* relative tolerance of each inner solve (mixed only); with
+                           reliable_update, the drop of the iterated residual
+                           between two reliable updates (0: 0.1) */
   int check_every;      /* iterations between host convergence checks (>= 1) */
   int use_graph;        /* 1: replay check_every iterations from a captured hipGraph */
   const double* x0;     /* optional initial guess (canonical, same residency as b) */
   int on_device;        /* 1: b, x and x0 are device pointers; 0: host pointers */
   int reliable_update;  /* mixed only: 1 = reliable updates (one low-precision Krylov
                            space, the FP64 true residual re-injected each time the
-                           iterated one drops 10x); 0 = defect correction (restart
+                           iterated one drops by inner_tol, 10x by default); 0 =
+                           defect correction (restart
                            the inner solve from each FP64 residual) */
   int even_odd;         /* lqcd_solve only: 1 = even-odd preconditioned (Eq. (1));
                            0 = BiCGStab on the full operator D, FP64 only
@@ -452,6 +455,18 @@ int lqcd_set_hop_shape(lqcd_ctx* ctx, int prec, int block, int split, int xcd_ma
 /* The launch shape in use for one precision (as lqcd_set_hop_shape takes it);
  * any output pointer may be NULL. */
 int lqcd_get_hop_shape(lqcd_ctx* ctx, int prec, int* block, int* split, int* xcd_map, int* nt);
+
+/* Streaming bandwidth of the context's GPU, the practical ceiling the
+ * roofline figures are read against (measurement support, not a step of the
+ * method): kind 0 streams `bytes` of device memory once through a read-only
+ * kernel (a sum of 16-byte words, 2048 workgroups of 256 lanes walking the
+ * buffer in grid-sized strides), kind 1 copies them to a second buffer. The
+ * library allocates the buffers (zeroed) and frees them before returning;
+ * *gbs receives the best of reps launches in GB/s of bytes moved (read plus
+ * written), timed with HIP events on the context's stream. bytes is rounded
+ * down to a multiple of 16 and must be at least 1 MiB; EINVAL for a bad
+ * kind, size or reps, ENOMEM if the buffers cannot be allocated. */
+int lqcd_bandwidth_probe(lqcd_ctx* ctx, int kind, size_t bytes, int reps, double* gbs);
 
 /* Name of a status code; detail of the last error on this thread. */
 const char* lqcd_strerror(int status);

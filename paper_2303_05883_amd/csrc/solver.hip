@@ -215,7 +215,7 @@ static int bicg_run(lqcd_ctx* c, InnerVecs& v, double target2, int max_iters, in
 // breakdown the iteration restarts from the true residual.
 static int reliable_mixed(lqcd_ctx* c, const lqcd_solve_params& prm, InnerVecs& iv, double target, double bnorm2,
                           double& rnorm, int& total_iters, int& restarts, int& updates, int& status) {
-  constexpr double DELTA_R = 0.1;
+  const double DELTA_R = prm.inner_tol > 0 && prm.inner_tol < 1 ? prm.inner_tol : 0.1;
   Workspace* w = c->ws;
   const int IP = iv.prec;
   double* hn = w->hnorms;

@@ -261,6 +261,71 @@ extern "C" int lqcd_autotune(lqcd_ctx* c, int prec, const char* path) {
   return LQCD_OK;
 }
 
+namespace lq {
+namespace {
+
+// Read-only stream: every 16-byte word once, summed; the sum is stored only
+// if it equals -1, which a zeroed buffer never gives, so the loads stay.
+__global__ void __launch_bounds__(256) k_read_probe(const float4* __restrict__ a, size_t n, float* sink) {
+  float acc = 0.f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const float4 v = a[i];
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  if (acc == -1.f) sink[0] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_copy_probe(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) b[i] = a[i];
+}
+
+}  // namespace
+}  // namespace lq
+
+extern "C" int lqcd_bandwidth_probe(lqcd_ctx* c, int kind, size_t bytes, int reps, double* gbs) {
+  if (!c || !gbs) return set_error(LQCD_EINVAL, "null argument");
+  if (kind < 0 || kind > 1 || reps < 1 || bytes < ((size_t)1 << 20))
+    return set_error(LQCD_EINVAL, "bandwidth probe: kind 0 or 1, reps >= 1, at least 1 MiB");
+  const size_t n = bytes / 16;
+  void* a = nullptr;
+  void* b = nullptr;
+  if (hipMalloc(&a, n * 16) != hipSuccess || hipMalloc(&b, kind == 1 ? n * 16 : 256) != hipSuccess) {
+    if (a) (void)hipFree(a);
+    (void)hipGetLastError();
+    return set_error(LQCD_ENOMEM, "bandwidth probe allocation failed");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = LQCD_OK;
+  if (hipMemsetAsync(a, 0, n * 16, c->stream) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    st = set_error(LQCD_EHIP, "bandwidth probe set-up failed");
+  float best = 1e30f;
+  for (int r = 0; r <= reps && st == LQCD_OK; ++r) {  // the first launch is a warm-up
+    (void)hipEventRecord(e0, c->stream);
+    if (kind == 0)
+      hipLaunchKernelGGL(k_read_probe, dim3(2048), dim3(256), 0, c->stream, static_cast<const float4*>(a), n,
+                         static_cast<float*>(b));
+    else
+      hipLaunchKernelGGL(k_copy_probe, dim3(2048), dim3(256), 0, c->stream, static_cast<const float4*>(a),
+                         static_cast<float4*>(b), n);
+    (void)hipEventRecord(e1, c->stream);
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = set_error(LQCD_EHIP, "bandwidth probe launch failed");
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (r > 0 && ms < best) best = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (st != LQCD_OK) return st;
+  *gbs = (double)(kind == 1 ? 2 : 1) * (double)(n * 16) / (best * 1e-3) / 1e9;
+  return LQCD_OK;
+}
+
 extern "C" int lqcd_set_hop_shape(lqcd_ctx* c, int prec, int block, int split, int xcd_map, int nt) {
   if (!c) return set_error(LQCD_EINVAL, "null argument");
   if (prec < 0 || prec > 2) return set_error(LQCD_EINVAL, "bad precision");

@@ -35,7 +35,7 @@ EXPORTED = ["lqcd_create", "lqcd_destroy", "lqcd_set_gauge", "lqcd_set_clover", 
             "lqcd_stag_import", "lqcd_stag_export", "lqcd_stag_hop_native", "lqcd_dwf_apply",
             "lqcd_dwf_solve", "lqcd_dwf_field_bytes", "lqcd_dwf_import", "lqcd_dwf_export", "lqcd_dwf_apply_native",
             "lqcd_mg_setup", "lqcd_mg_coarse_size", "lqcd_mg_restrict", "lqcd_mg_prolong", "lqcd_mg_coarse_apply",
-            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur", "lqcd_dwf_solve_eo", "lqcd_batch_autotune", "lqcd_batch_apply_schur", "lqcd_apply_native_noalloc", "lqcd_strerror",
+            "lqcd_mg_apply", "lqcd_solve_mg", "lqcd_dwf_apply_schur", "lqcd_dwf_solve_eo", "lqcd_batch_autotune", "lqcd_batch_apply_schur", "lqcd_apply_native_noalloc", "lqcd_bandwidth_probe", "lqcd_strerror",
             "lqcd_last_error"]
 STAG_OPS = {"D": 0, "SCHUR": 1}
 
@@ -163,6 +163,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     for name in ("lqcd_mg_restrict", "lqcd_mg_prolong", "lqcd_mg_coarse_apply", "lqcd_mg_apply"):
         getattr(lib, name).argtypes = [vp, vp, vp, ip]
     lib.lqcd_solve_mg.argtypes = [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveStats)]
+    lib.lqcd_bandwidth_probe.argtypes = [vp, ip, C.c_size_t, ip, C.POINTER(C.c_double)]
+    lib.lqcd_bandwidth_probe.restype = ip
     lib.lqcd_strerror.argtypes = [ip]
     lib.lqcd_strerror.restype = C.c_char_p
     lib.lqcd_last_error.argtypes = []
@@ -356,6 +358,14 @@ class Lattice:
         v = [C.c_int() for _ in range(4)]
         _check(self.lib.lqcd_get_hop_shape(self.handle, int(prec), *[C.byref(x) for x in v]), "lqcd_get_hop_shape")
         return tuple(x.value for x in v)
+
+    def bandwidth_probe(self, kind: int, nbytes: int = 1 << 30, reps: int = 5) -> float:
+        """Best-of-reps GB/s of a read-only stream (kind 0) or a copy (kind 1)
+        of nbytes on this context's GPU."""
+        g = C.c_double(0.0)
+        _check(self._call(self.lib.lqcd_bandwidth_probe, self.handle, int(kind), int(nbytes), int(reps), C.byref(g)),
+               "lqcd_bandwidth_probe")
+        return g.value
 
     def autotune(self, prec: int, path: str | None = None):
         _check(self._call(self.lib.lqcd_autotune, self.handle, int(prec), path.encode() if path else None),
