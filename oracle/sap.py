@@ -24,6 +24,14 @@ textbook ones:
   the update of colour ``c`` solves the block equations with right-hand side
   the current residual ``P_c (eta - D psi)`` and adds the block solutions to
   ``psi``; the preconditioner ``M eta`` runs ``ncy`` cycles from ``psi = 0``;
+* even-odd block solves (``sap_eo``): the block equation ``D_B delta = rho``
+  splits by site parity like the whole-lattice operator (Eq. (1)),
+  ``D_B = [[A_ee, -kappa H_eo], [-kappa H_oe, A_oo]]`` with ``H`` the hops
+  inside the block; the minimal-residual steps run on the block's Schur
+  complement ``S_B = A_ee - kappa^2 H_eo A_oo^-1 H_oe`` with right-hand side
+  ``rho_e + kappa H_eo A_oo^-1 rho_o`` (one ``alpha`` per block), and the odd
+  sites follow as ``delta_o = A_oo^-1 (rho_o + kappa H_oe delta_e)``: the
+  block LU solve of ``D_B`` with the even block solved approximately;
 * flexible BiCGStab: BiCGStab for ``D x = b`` with right preconditioning by a
   possibly varying ``M`` (the preconditioned vectors ``M p`` and ``M s`` are
   used directly in the solution update, so no fixed ``M`` is assumed).
@@ -35,7 +43,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
-from . import solvers
+from . import dirac, solvers
 
 
 class Blocks:
@@ -100,6 +108,57 @@ def sap(D, blocks: Blocks, eta: np.ndarray, ncy: int, n_mr: int) -> np.ndarray:
         for colour in (0, 1):
             rho = np.where(blocks.mask(colour), eta - D(psi), 0)
             psi = psi + mr_blocks(D, blocks, colour, rho, n_mr)
+    return psi
+
+
+def block_hop(op, blocks: Blocks, colour: int, psi: np.ndarray) -> np.ndarray:
+    """H_B psi: the hopping term with only the hops inside the blocks of one
+    colour (op a dirac.Operator, D = A - kappa H)."""
+    m = blocks.mask(colour)
+    return np.where(m, op.hop(np.where(m, psi, 0)), 0)
+
+
+def mr_blocks_eo(op, blocks: Blocks, colour: int, rho: np.ndarray, n_mr: int) -> np.ndarray:
+    """The block equations of one colour solved through each block's even-odd
+    Schur complement (n_mr minimal-residual steps on it, from zero), then the
+    odd sites exactly."""
+    m = blocks.mask(colour)
+    par = dirac.parity_field(blocks.dims)[..., None, None]
+    ev, od = m & (par == 0), m & (par == 1)
+    k = op.kappa
+
+    def A(v, where):
+        return np.where(where, dirac.site_apply(op.A, v), 0)
+
+    def Ainv(v, where):
+        return np.where(where, dirac.site_apply(op.Ainv, v), 0)
+
+    def H(v, where):
+        return np.where(where, block_hop(op, blocks, colour, v), 0)
+
+    rho_e, rho_o = np.where(ev, rho, 0), np.where(od, rho, 0)
+    r = rho_e + k * H(Ainv(rho_o, od), ev)
+    de = np.zeros_like(rho)
+    for _ in range(n_mr):
+        q = A(r, ev) - k * k * H(Ainv(H(r, od), od), ev)
+        qr = _per_block_sum(blocks, np.sum(np.conj(q) * r, axis=(-2, -1)))
+        qq = _per_block_sum(blocks, np.sum(np.abs(q) ** 2, axis=(-2, -1))).real
+        alpha = np.where(qq > 0, qr / np.where(qq > 0, qq, 1), 0)
+        a = alpha[blocks.block_id][..., None, None]
+        de = de + np.where(ev, a * r, 0)
+        r = r - np.where(ev, a * q, 0)
+    do = Ainv(rho_o + k * H(de, od), od)
+    return de + do
+
+
+def sap_eo(op, blocks: Blocks, eta: np.ndarray, ncy: int, n_mr: int) -> np.ndarray:
+    """The SAP preconditioner with even-odd block solves: ncy cycles over the
+    two colours from psi = 0."""
+    psi = np.zeros_like(eta)
+    for _ in range(ncy):
+        for colour in (0, 1):
+            rho = np.where(blocks.mask(colour), eta - op.D(psi), 0)
+            psi = psi + mr_blocks_eo(op, blocks, colour, rho, n_mr)
     return psi
 
 
