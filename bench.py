@@ -278,11 +278,14 @@ def cpu_all_cores(U, b, dims, workers):
     return dt
 
 
-def cpu_baseline(U, b, dims):
+def cpu_baseline(U, b, dims, kappa=None, gpu_iters=None):
     """The CPU oracle timed on the host: its hopping term on the benchmark's
     own field (one full-lattice application = 1320 flop x V) on one thread and
-    on all usable cores, and the 8^4 Haar Wilson system (kappa 0.12) applied
-    and solved by its unpreconditioned BiCGStab."""
+    on all usable cores; one application of its even-odd Wilson operator
+    S = 1 - kappa^2 H_eo H_oe on that field, two of which make a BiCGStab
+    iteration, extrapolated to the GPU's FP64 iteration count; and the 8^4 Haar
+    Wilson system (kappa 0.12) applied and solved by its unpreconditioned
+    BiCGStab."""
     from oracle import dirac, solvers
     host = host_info()
     reps = 2
@@ -293,6 +296,18 @@ def cpu_baseline(U, b, dims):
     v = int(np.prod(dims))
     workers = max(1, min(16, host["usable_cpus"]))
     dt_all = cpu_all_cores(U, b, dims, workers)
+    c2 = None
+    if kappa is not None:
+        xe = dirac.mask(b, 0)
+        t0 = time.perf_counter()
+        dirac.mask(xe - kappa * kappa * dirac.hop(U, dirac.mask(dirac.hop(U, xe, -1), 1), -1), 0)
+        dt_s = time.perf_counter() - t0
+        c2 = {"schur_apply_s": round(dt_s, 2), "per_iteration_s": round(2 * dt_s, 2),
+              "sample": "one oracle application of S = 1 - kappa^2 H_eo H_oe on the benchmark's field "
+                        "(NumPy float64, one thread); a BiCGStab iteration applies S twice"}
+        if gpu_iters:
+            c2["iterations"] = gpu_iters
+            c2["solve_s_extrapolated"] = round(2 * dt_s * gpu_iters, 1)
     c1_dims = (8, 8, 8, 8)
     U1 = fg.gauge_field(c1_dims, 1001, "haar")
     b1 = fg.gaussian_spinor(c1_dims, 1001)
@@ -313,7 +328,8 @@ def cpu_baseline(U, b, dims):
             "c1_8x8x8x8": {"apply_ms": round(1000 * dt_apply, 2), "solve_s": round(dt_solve, 3),
                            "iterations": info.iterations, "rel_resid": info.residual,
                            "sample": "oracle D apply and unpreconditioned FP64 BiCGStab to 1e-10, Haar links, "
-                                     "kappa 0.12, one thread"}}
+                                     "kappa 0.12, one thread"},
+            "c2_even_odd_iteration": c2}
 
 
 def make_lattice(torch, lqcd, dims, seed, eps, kappa, csw, stream=None, source=True, scale=1.0):
@@ -457,7 +473,8 @@ def run_single(a, torch, lqcd):
     roof["copy_gbs"] = round(copy_probe(torch), 1)
     roof["read_gbs"] = round(lat.bandwidth_probe(0), 1)
     compare = None if a.no_compare else compare_solves(torch, lat, lqcd, bd)
-    cpu = None if (a.no_cpu or a.workload != "wilson") else cpu_baseline(U, b, dims)
+    cpu = None if (a.no_cpu or a.workload != "wilson") else cpu_baseline(
+        U, b, dims, w["kappa"], compare["f64"]["inner"] if compare else None)
     if cpu:
         log(f"cpu baseline: {cpu}")
     if a.workload == "wilson" and not a.no_compare and not a.no_extra:
@@ -494,12 +511,13 @@ def batched_hop_roofline(lqcd, lats, nrhs, vhs, prec):
     site_rhs = sum(vh * n for vh, n in zip(vhs, nrhs))
     gbs = nbytes / (us * 1e-6) / 1e9
     name = {0: "f64", 1: "f32", 2: "f16"}[prec]
-    # the committed counters hold for the kernel instantiation they were taken on
+    # the committed counters hold for the kernel instantiation and launch shape they were taken on
     tmpl = f"k_bhop<{prec}, 1, true, 0, {'true' if shape[4] else 'false'}, {shape[0]}>"
+    shp = "shape " + ",".join(str(v) for v in shape)
     traffic = None
     if len(vhs) == 3 and measured_traffic(name, BHOP_TRAFFIC_FILE, BHOP_SOURCES) is not None:
         for ln in open(BHOP_TRAFFIC_FILE).read().splitlines():
-            if ln.startswith(name + ":") and tmpl in ln:
+            if ln.startswith(name + ":") and tmpl in ln and shp + " " in ln:
                 traffic = measured_traffic(name, BHOP_TRAFFIC_FILE, BHOP_SOURCES)
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
