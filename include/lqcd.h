@@ -174,9 +174,11 @@ int lqcd_solve(lqcd_ctx* ctx, const double* b, double* x, const lqcd_solve_param
  * lqcd_solve (even_odd = 0 is EINVAL here; with inner_tol 0 the FP16 inner
  * solves default to 5e-3 instead of 1e-2). All contexts must share one stream. Each RHS runs its own
  * BiCGStab (own alpha, beta, omega; not block Krylov) but every operator step
- * of every unconverged RHS of every lattice is one persistent kernel launch that
- * loads each link once per site for all RHS of that lattice. Converged RHS are
- * masked out. stats has one entry per RHS, lattice-major. */
+ * of every unconverged RHS of every lattice is one persistent kernel launch in
+ * which a lane applies each link and clover block it loads to several RHS and
+ * the waves of a workgroup share a site block's loads (launch shapes tuned per
+ * batch, see lqcd_batch_autotune). Converged RHS are masked out. stats has one
+ * entry per RHS, lattice-major. */
 int lqcd_solve_batch(lqcd_ctx* const* ctxs, const int* nrhs, const double* const* b,
                      double* const* x, int nlattices, const lqcd_solve_params* prm,
                      lqcd_solve_stats* stats);
