@@ -633,20 +633,36 @@ def run_batch(a, torch, lqcd):
 SAP_BLOCK, SAP_NCY, SAP_NMR = (16, 4, 2, 2), 6, 6
 
 
-def sap_flops(vh, st, ncy, nmr):
-    """Hop flops of one SAP-preconditioned solve: 2 full-lattice D per flexible
-    BiCGStab iteration plus 1 per restart, and per preconditioner application
-    ncy cycles of (residual + nmr block operators) over the whole lattice."""
-    full = 2 * vh
-    return HOP_FLOPS * full * (2 * st.outer_iters + st.restarts + 1 + st.inner_iters * ncy * (1 + nmr))
+def sap_face_flops(block):
+    """Flops per site of a SAP block launch's right-hand side update: the hops
+    that cross the block faces (on average sum_mu 2 / b_mu of the 8 hops, 165
+    flop each) and the addition to the stored residual (24 flop)."""
+    return (HOP_FLOPS / 8) * sum(2.0 / b for b in block) + 24
+
+
+def sap_application_flops(vh, ncy, nmr, block):
+    """One SAP preconditioner application: 2 ncy block launches, each over
+    half of the 2 vh sites, with nmr block operators (1320 + 504 flop) and MR
+    updates (96 flop) per site; every launch but the first also updates its
+    right-hand side (sap_face_flops)."""
+    return vh * ((2 * ncy - 1) * sap_face_flops(block) + 2 * ncy * nmr * (1320 + 504 + 96))
+
+
+def sap_flops(vh, st, ncy, nmr, block):
+    """Flops of one SAP-preconditioned solve: the FP64 full operator (two hops
+    and two clover terms per application: 2 per flexible BiCGStab iteration
+    and 1 per restart check) and the preconditioner applications."""
+    full = 2 * (1320 + 504) * vh
+    return full * (2 * st.outer_iters + st.restarts + 1) + st.inner_iters * sap_application_flops(vh, ncy, nmr, block)
 
 
 def sap_kernel_roofline(torch, lat, vh):
     """Average duration of the SAP block kernel, from HIP events on the library's
     stream: preconditioner applications with ncy cycles minus those with one
     cycle (the import/export around them cancels), per block-kernel launch.
-    Work per launch (half the lattice's sites): a residual (1320 + 504 + 48
-    flop) and nmr block-operator + MR steps (1320 + 504 + 96 flop) per site."""
+    Work per launch (half the lattice's sites): the right-hand side update
+    (sap_face_flops) and nmr block-operator + MR steps (1320 + 504 + 96 flop)
+    per site."""
     b = torch.from_numpy(fg.gaussian_spinor(lat.dims, 5)).cuda()
     out = torch.zeros_like(b)
 
@@ -663,7 +679,7 @@ def sap_kernel_roofline(torch, lat, vh):
         return e0.elapsed_time(e1) / reps
 
     ms = (run(SAP_NCY) - run(1)) / (2 * (SAP_NCY - 1))
-    flops = vh * ((1320 + 504 + 48) + SAP_NMR * (1320 + 504 + 96))
+    flops = vh * (sap_face_flops(SAP_BLOCK) + SAP_NMR * (1320 + 504 + 96))
     tf = flops / (ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(tf, 3), "peak": 157.3, "unit": "TFLOP/s", "frac": round(tf / 157.3, 4),
             "traffic": None, "kernel": "k_sap_block (FP32, one workgroup per block)", "us_per_launch": round(1000 * ms, 1),
@@ -689,7 +705,7 @@ def run_sap(a, torch, lqcd):
     if not worst <= 1e-10:
         log(f"true residual {worst} above 1e-10")
         sys.exit(1)
-    value = sum(sap_flops(vh, s, SAP_NCY, SAP_NMR) for s in stats) / elapsed / 1e9
+    value = sum(sap_flops(vh, s, SAP_NCY, SAP_NMR, SAP_BLOCK) for s in stats) / elapsed / 1e9
     ms_step = 1000 * elapsed / a.steps
     log(f"timed {a.steps} SAP solves: {ms_step:.1f} ms each, {stats[-1]}")
     roof = sap_kernel_roofline(torch, lat, vh)
@@ -723,8 +739,8 @@ def mg_fine_flops(vh, st, ncy, nmr):
     one FP32 full operator and 2 ncy SAP block launches over half the sites.
     The coarse grid, restriction and prolongation are not counted."""
     full = 2 * (1320 + 504) * vh
-    sap_launch = vh * ((1320 + 504 + 48) + nmr * (1320 + 504 + 96))
-    return full * (2 * st.outer_iters + st.restarts + 2) + st.inner_iters * (full + 2 * ncy * sap_launch)
+    return full * (2 * st.outer_iters + st.restarts + 2) + st.inner_iters * (
+        full + sap_application_flops(vh, ncy, nmr, MG["sap_block"]))
 
 
 def run_mg(a, torch, lqcd):

@@ -232,6 +232,8 @@ int lqcd_destroy(lqcd_ctx* c) {
   }
   dfree(c->canon_a);
   dfree(c->canon_b);
+  dfree(c->sap_res);
+  dfree(c->sap_delta);
   void* d = c->dscal;
   dfree(d);
   if (c->hscal) (void)hipHostFree(c->hscal);

@@ -151,6 +151,10 @@ struct lqcd_ctx {
   // field or the clover term changes
   void* mg = nullptr;
   void (*mg_free)(void*) = nullptr;
+  // SAP: block residuals and last block updates (FP32 full fields, even half
+  // then odd half), allocated on first use
+  void* sap_res = nullptr;
+  void* sap_delta = nullptr;
 };
 
 namespace lq {

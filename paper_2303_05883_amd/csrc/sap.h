@@ -12,6 +12,8 @@ namespace lq {
 bool sap_shape_ok(const Geom& g, const int b[4]);
 // psi = M eta on FP32 native half fields: ncy cycles over the two block
 // colours, nmr minimal-residual iterations per block solve, from psi = 0.
+// Uses the context's two FP32 SAP fields (block residuals and updates,
+// allocated on first use); calls on one context must not overlap.
 int sap_apply(lqcd_ctx* c, const int b[4], int ncy, int nmr, const void* eta_e, const void* eta_o, void* psi_e,
               void* psi_o);
 // A right preconditioner for solve_flexible: FP64 native halves in and out.

@@ -6,11 +6,20 @@
 // BiCGStab).
 //
 // One workgroup per block of the colour being updated, one lane per block
-// site. The lane forms the block right-hand side rho = eta - D psi at its site
-// from global memory, then the block's minimal-residual iterations run on
-// chip: the block residual and the block's internal forward links sit in LDS,
-// q = D_B r takes its neighbours from LDS, the block dot products <q, r> and
-// <q, q> are workgroup reductions, and only psi += delta goes back to memory.
+// site. The lane forms the block right-hand side rho = eta - D psi at its
+// site, then the block's minimal-residual iterations run on chip: the block
+// residual and the block's internal forward links sit in LDS, q = D_B r takes
+// its neighbours from LDS, the block dot products <q, r> and <q, q> are
+// workgroup reductions, and psi += delta goes back to memory.
+// The right-hand side is kept up to date instead of recomputed: after a
+// colour's update its residual eta - D psi on its own sites is exactly the
+// blocks' final MR residual r = rho - D_B delta (the neighbouring blocks are
+// of the other colour, so no hop of the update lands on its own colour), and
+// the other colour's update changes it only through the hops that cross the
+// block faces, by +kappa H delta_other. So each launch stores r and delta, and
+// the next launch of the colour starts from r plus those face hops (the
+// first launch from eta alone, psi being zero) - no clover term and no
+// interior hops from memory.
 // The preconditioner works in FP32; the outer solve in FP64.
 #include <chrono>
 #include <cmath>
@@ -36,7 +45,10 @@ struct SapArgs {
   const char* gauge;  // FP32 links, 2 parities x 4 directions
   size_t link_stride;
   const void* clov[2];  // FP32 A on even / odd sites, or null (Wilson: A = 1)
-  const void* eta[2];
+  const void* base[2];   // eta (first cycle) or the stored block residuals
+  const void* dother[2]; // the other colour's last update delta, or null (first launch)
+  void* res[2];          // this launch's final block residuals
+  void* dout[2];         // this launch's delta
   void* psi[2];
 };
 
@@ -143,50 +155,46 @@ __global__ void __launch_bounds__(256) k_sap_block(SapArgs a) {
   const int lc[4] = {lx, ly, lz, lt};
   const int stride[4] = {1, a.b[0], a.b[0] * a.b[1], a.b[0] * a.b[1] * a.b[2]};
 
-  // ---- rho = eta - D psi at this site (neighbours from memory)
+  // ---- rho = base + kappa (H delta_other) over the hops that cross the block
+  // faces (neighbours from memory; the interior hops are in base)
   cx<float> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
-  const void* pin = a.psi[1 - p];
+  if (a.dother[1 - p]) {
+    const void* pin = a.dother[1 - p];
 #pragma unroll 1
-  for (int mu = 0; mu < 4; ++mu) {
-    int f[4] = {c[0], c[1], c[2], c[3]}, bk[4] = {c[0], c[1], c[2], c[3]};
-    f[mu] = c[mu] + 1 == L[mu] ? 0 : c[mu] + 1;
-    bk[mu] = c[mu] == 0 ? L[mu] - 1 : c[mu] - 1;
-    const size_t jf = hidx(f[0], f[1], f[2], f[3]), jb = hidx(bk[0], bk[1], bk[2], bk[3]);
-    const bool ff = mu == 3 && g.t_bc < 0 && c[3] + 1 == L[3];
-    const bool fb = mu == 3 && g.t_bc < 0 && c[3] == 0;
-    switch (mu) {
-      case 0:
-        hop_dir<1, 0, true, false>(pin, gf + 0 * ls, 0, jf, i, false, acc);
-        hop_dir<1, 0, false, false>(pin, gb + 0 * ls, 0, jb, jb, false, acc);
-        break;
-      case 1:
-        hop_dir<1, 1, true, false>(pin, gf + 1 * ls, 0, jf, i, false, acc);
-        hop_dir<1, 1, false, false>(pin, gb + 1 * ls, 0, jb, jb, false, acc);
-        break;
-      case 2:
-        hop_dir<1, 2, true, false>(pin, gf + 2 * ls, 0, jf, i, false, acc);
-        hop_dir<1, 2, false, false>(pin, gb + 2 * ls, 0, jb, jb, false, acc);
-        break;
-      default:
-        hop_dir<1, 3, true, false>(pin, gf + 3 * ls, 0, jf, i, ff, acc);
-        hop_dir<1, 3, false, false>(pin, gb + 3 * ls, 0, jb, jb, fb, acc);
-        break;
+    for (int mu = 0; mu < 4; ++mu) {
+      int f[4] = {c[0], c[1], c[2], c[3]}, bk[4] = {c[0], c[1], c[2], c[3]};
+      f[mu] = c[mu] + 1 == L[mu] ? 0 : c[mu] + 1;
+      bk[mu] = c[mu] == 0 ? L[mu] - 1 : c[mu] - 1;
+      const size_t jf = hidx(f[0], f[1], f[2], f[3]), jb = hidx(bk[0], bk[1], bk[2], bk[3]);
+      const bool ff = mu == 3 && g.t_bc < 0 && c[3] + 1 == L[3];
+      const bool fb = mu == 3 && g.t_bc < 0 && c[3] == 0;
+      const bool face_f = lc[mu] + 1 == a.b[mu], face_b = lc[mu] == 0;
+      switch (mu) {
+        case 0:
+          if (face_f) hop_dir<1, 0, true, false>(pin, gf + 0 * ls, 0, jf, i, false, acc);
+          if (face_b) hop_dir<1, 0, false, false>(pin, gb + 0 * ls, 0, jb, jb, false, acc);
+          break;
+        case 1:
+          if (face_f) hop_dir<1, 1, true, false>(pin, gf + 1 * ls, 0, jf, i, false, acc);
+          if (face_b) hop_dir<1, 1, false, false>(pin, gb + 1 * ls, 0, jb, jb, false, acc);
+          break;
+        case 2:
+          if (face_f) hop_dir<1, 2, true, false>(pin, gf + 2 * ls, 0, jf, i, false, acc);
+          if (face_b) hop_dir<1, 2, false, false>(pin, gb + 2 * ls, 0, jb, jb, false, acc);
+          break;
+        default:
+          if (face_f) hop_dir<1, 3, true, false>(pin, gf + 3 * ls, 0, jf, i, ff, acc);
+          if (face_b) hop_dir<1, 3, false, false>(pin, gb + 3 * ls, 0, jb, jb, fb, acc);
+          break;
+      }
     }
   }
   cx<float> r[12];
-  {
-    cx<float> ps[12], aps[12];
-    IO<1>::load_spinor(a.psi[p], i, ps);
-    if (a.clov[p]) clover_apply<1>(a.clov[p], i, ps, aps);
-    else
+  IO<1>::load_spinor(a.base[p], i, r);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) aps[k] = ps[k];
-    IO<1>::load_spinor(a.eta[p], i, r);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) r[k] = r[k] - aps[k] + a.kappa * acc[k];
-  }
+  for (int k = 0; k < 12; ++k) r[k] = r[k] + a.kappa * acc[k];
 
   // ---- the block's internal forward links into LDS
 #pragma unroll
@@ -252,7 +260,9 @@ __global__ void __launch_bounds__(256) k_sap_block(SapArgs a) {
       r[k] = r[k] - alpha * qv[k];
     }
   }
-  // ---- psi += delta on this block
+  // ---- psi += delta on this block; the residual and delta for the next launches
+  IO<1>::store_spinor(a.res[p], i, r);
+  IO<1>::store_spinor(a.dout[p], i, delta);
   cx<float> ps[12];
   IO<1>::load_spinor(a.psi[p], i, ps);
 #pragma unroll
@@ -293,16 +303,35 @@ int sap_apply(lqcd_ctx* c, const int b[4], int ncy, int nmr, const void* eta_e, 
   a.link_stride = link_bytes(1, c->g.vh);
   a.clov[0] = clover_slot(c, 1, 0);
   a.clov[1] = clover_slot(c, 1, 1);
-  a.eta[0] = eta_e;
-  a.eta[1] = eta_o;
+  const size_t hb = spinor_bytes(1, c->g.vh);
+  for (void** f : {&c->sap_res, &c->sap_delta})
+    if (!*f && hipMalloc(f, 2 * hb) != hipSuccess) {
+      *f = nullptr;
+      (void)hipGetLastError();
+      return set_error(LQCD_ENOMEM, "SAP workspace allocation failed");
+    }
+  char* res = static_cast<char*>(c->sap_res);
+  char* del = static_cast<char*>(c->sap_delta);
   a.psi[0] = psi_e;
   a.psi[1] = psi_o;
+  a.res[0] = res;
+  a.res[1] = res + hb;
+  a.dout[0] = del;
+  a.dout[1] = del + hb;
   LQ_TRY(blas_zero(c, 1, psi_e));
   LQ_TRY(blas_zero(c, 1, psi_o));
   const size_t lds = (size_t)vol * (6 + 12) * 16;
   for (int cy = 0; cy < ncy; ++cy)
     for (int colour = 0; colour < 2; ++colour) {
       a.colour = colour;
+      // right-hand side: eta on the first cycle, then this colour's stored
+      // residual; plus the face hops of the other colour's last update (none
+      // before the first update)
+      a.base[0] = cy == 0 ? eta_e : res;
+      a.base[1] = cy == 0 ? eta_o : res + hb;
+      const bool none = cy == 0 && colour == 0;
+      a.dother[0] = none ? nullptr : del;
+      a.dother[1] = none ? nullptr : del + hb;
       hipLaunchKernelGGL(k_sap_block, dim3(nblocks / 2), dim3(vol), lds, c->stream, a);
     }
   LQ_HIP(hipGetLastError());
