@@ -56,6 +56,13 @@ def test_host_only_entry_points():
     assert lib.lqcd_create(good, 0, None, ctypes.byref(h)) == lqcd.EINVAL
     assert lib.lqcd_set_clover(None, 0.1, 0.0) == lqcd.EINVAL
     assert lib.lqcd_apply(None, 0, 0, None, None, 0) == lqcd.EINVAL
+    # batched entry points: no lattices, too many lattices, null lists
+    one = (ctypes.c_int * 1)(1)
+    assert lib.lqcd_solve_batch(None, one, None, None, 0, None, None) == lqcd.EINVAL
+    assert lib.lqcd_solve_batch(None, one, None, None, 17, None, None) == lqcd.EINVAL
+    assert lib.lqcd_batch_autotune(None, one, 1, 3, None, None) == lqcd.EINVAL
+    g = ctypes.c_double()
+    assert lib.lqcd_bandwidth_probe(None, 0, 1 << 20, 1, ctypes.byref(g)) == lqcd.EINVAL
 
 
 def test_single_hip_runtime_in_process():

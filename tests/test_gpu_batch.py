@@ -152,3 +152,38 @@ def test_batch_autotune_picks_a_valid_shape_and_solves():
     with pytest.raises(lqcd.LqcdError) as e:
         lqcd.batch_autotune(lats, [12, 7], lqcd.F64, (3, 2, 64, 0, 0))  # 3 RHS per lane is not built in FP64
     assert e.value.status == lqcd.EINVAL
+
+
+def test_batch_rejects_bad_arguments():
+    """A lattice with no right-hand side, an initial guess, the unpreconditioned
+    operator and a batch that names one context twice are argument errors."""
+    import ctypes as C
+    torch = torch_cuda()
+    stream = torch.cuda.Stream()
+    lats, _, bs = batch_system(torch, [((4, 4, 4, 4), 2, 51), ((4, 4, 4, 8), 1, 52)], 0.12, 1.0, stream)
+    lib = lqcd.load()
+    ds = [to_dev(b) for b in bs]
+    xs = [to_dev(np.zeros_like(b)) for b in bs]
+
+    def call(lat_list, nrhs, **kw):
+        n = len(lat_list)
+        ctxs = (C.c_void_p * n)(*[lat.handle.value for lat in lat_list])
+        nr = (C.c_int * n)(*nrhs)
+        prm = lqcd.default_params()
+        prm.inner_prec, prm.on_device = lqcd.F32, 1
+        for k, v in kw.items():
+            setattr(prm, k, v)
+        st = (lqcd.SolveStats * max(1, sum(nrhs)))()
+        pb = (C.c_void_p * n)(*[b.data_ptr() for b in ds[:n]])
+        px = (C.c_void_p * n)(*[x.data_ptr() for x in xs[:n]])
+        torch.cuda.synchronize()
+        return lib.lqcd_solve_batch(ctxs, nr, pb, px, n, C.byref(prm), st)
+
+    assert call(lats, [2, 0]) == lqcd.EINVAL
+    assert call(lats, [2, 1], even_odd=0) == lqcd.EINVAL
+    assert call(lats, [2, 1], x0=ds[0].data_ptr()) == lqcd.EINVAL
+    assert call([lats[0], lats[0]], [2, 2]) == lqcd.EINVAL
+    # the valid call still works afterwards
+    assert call(lats, [2, 1]) == lqcd.OK
+    for lat in lats:
+        lat.close()
