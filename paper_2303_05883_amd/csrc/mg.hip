@@ -321,23 +321,26 @@ __global__ void __launch_bounds__(256) k_mg_restrict(MgGeom m, const char* B, co
   restrict_agg<NC>(m, B, r2, agg, -1, 0, rc + (size_t)agg * 2 * m.n, 1);
 }
 
-// columns col of the coarse blocks from y = D (P e_{class, col}); M is
-// [agg][dir][row][col], dir 0 = self, 1 + 2 mu = +mu, 2 + 2 mu = -mu
+// columns col of the coarse blocks from y = D (P e_{class, col}); M holds,
+// for each (agg, dir), the 2n x 2n block by pairs of columns: entry (row, col)
+// at ((agg * 9 + dir) * n + col / 2) * 4n + 2 row + col % 2 (dir 0 = self,
+// 1 + 2 mu = +mu, 2 + 2 mu = -mu), so that the lanes of consecutive rows read
+// consecutive 16-byte pairs in the coarse apply
 template <int NC>
 __global__ void __launch_bounds__(256) k_mg_collect(MgGeom m, const char* B, const void* y2, int cls, int col,
                                                     float2* M) {
   const int agg = agg_of_block(m);
   const int d = class_of(m, agg) ^ cls;
   const int n2 = 2 * m.n;
-  float2* base = M + (size_t)agg * 9 * n2 * n2 + col;
+  float2* base = M + (size_t)agg * 9 * n2 * n2 + (size_t)(col >> 1) * 2 * n2 + (col & 1);
   if (d == 0) {
-    restrict_agg<NC>(m, B, y2, agg, -1, 0, base, n2);
+    restrict_agg<NC>(m, B, y2, agg, -1, 0, base, 2);
     return;
   }
   if (d & (d - 1)) return;  // two or more bits: no neighbour of class cls
   const int mu = d == 1 ? 0 : d == 2 ? 1 : d == 4 ? 2 : 3;
-  restrict_agg<NC>(m, B, y2, agg, mu, +1, base + (size_t)(1 + 2 * mu) * n2 * n2, n2);
-  restrict_agg<NC>(m, B, y2, agg, mu, -1, base + (size_t)(2 + 2 * mu) * n2 * n2, n2);
+  restrict_agg<NC>(m, B, y2, agg, mu, +1, base + (size_t)(1 + 2 * mu) * n2 * n2, 2);
+  restrict_agg<NC>(m, B, y2, agg, mu, -1, base + (size_t)(2 + 2 * mu) * n2 * n2, 2);
 }
 
 // ------------------------------------------------------------------ prolongation
@@ -399,11 +402,12 @@ __global__ void __launch_bounds__(256) k_mg_capply(MgGeom m, const float2* M, co
         cc[mu] = (cc[mu] + sg + m.na[mu]) % m.na[mu];
         nb = cc[0] + m.na[0] * (cc[1] + m.na[1] * (cc[2] + m.na[2] * cc[3]));
       }
-      // n2 is even: rows and vectors start on 16-byte boundaries, two entries per load
-      const float4* Mr = reinterpret_cast<const float4*>(M + (((size_t)agg * 9 + dir) * n2 + row) * n2);
+      // a pair of columns per load; the rows of a block sit side by side for
+      // each pair, so consecutive lanes read consecutive 16 bytes
+      const float4* Mr = reinterpret_cast<const float4*>(M + ((size_t)agg * 9 + dir) * n2 * n2) + row;
       const float4* xv = reinterpret_cast<const float4*>(x + (size_t)nb * n2);
       for (int c = 0; c < n2 / 2; ++c) {
-        const float4 a = Mr[c], b = xv[c];
+        const float4 a = Mr[(size_t)c * n2], b = xv[c];
         re += a.x * b.x - a.y * b.y + a.z * b.z - a.w * b.w;
         im += a.x * b.y + a.y * b.x + a.z * b.w + a.w * b.z;
       }
@@ -466,7 +470,7 @@ struct MgState {
   MgGeom m{};
   lqcd_mg_params prm{};
   char* B = nullptr;    // n chiral basis fields (FP32, two halves each)
-  float2* M = nullptr;  // [nagg][9][2n][2n]
+  float2* M = nullptr;  // [nagg][9][n column pairs][2n rows][2]
   float2* cv[8] = {};   // coarse work vectors
   char* f32[4] = {};    // FP32 full fields (two halves)
   double* partials = nullptr;
