@@ -243,3 +243,109 @@ def dwf_schur_at(U, x_even, M5, mf, b5, c5, t_bc, sites, dag: bool = False):
         return z[:, np.searchsorted(uniq, _linear(dims, x))]
 
     return local_apply(K, gather5(x_even, sites)) - dhop(z_at, sites)
+
+
+# ---------------------------------------------------------------- staggered
+def stag_phase(sites, mu):
+    """The staggered phase eta_mu at each listed site (oracle.staggered)."""
+    x, y, z = sites[:, 0], sites[:, 1], sites[:, 2]
+    return [np.ones(len(sites)), (-1.0) ** x, (-1.0) ** (x + y), (-1.0) ** (x + y + z)][mu]
+
+
+def stag_dirac_at(U, psi, mass, t_bc, sites):
+    """(m + H) psi at the listed sites for a colour-vector field psi[t, z, y, x, c]:
+    (H psi)(x) = 1/2 sum_mu eta_mu(x) [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)]."""
+    dims = _dims(U)
+    sites = np.asarray(sites)
+    out = mass * gather(psi, sites)
+    for mu in range(4):
+        f = step(dims, sites, mu, +1)
+        b = step(dims, sites, mu, -1)
+        ef = np.ones(len(sites))
+        eb = np.ones(len(sites))
+        if mu == 3:
+            ef[sites[:, 3] == dims[3] - 1] = t_bc
+            eb[sites[:, 3] == 0] = t_bc
+        fwd = (gather(U, sites)[:, mu] @ gather(psi, f)[..., None])[..., 0]
+        bwd = (_dag(gather(U, b)[:, mu]) @ gather(psi, b)[..., None])[..., 0]
+        out = out + 0.5 * stag_phase(sites, mu)[:, None] * (ef[:, None] * fwd - eb[:, None] * bwd)
+    return out
+
+
+# ---------------------------------------------------------------- SAP, one cycle at listed blocks
+def _block_sites(origin, bdims):
+    bx, by, bz, bt = bdims
+    t, z, y, x = np.meshgrid(np.arange(bt), np.arange(bz), np.arange(by), np.arange(bx), indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel(), t.ravel()], axis=1) + np.asarray(origin)
+
+
+def _block_mr(U, kappa, csw, t_bc, sites, rho, n_mr):
+    """n_mr minimal-residual steps on one block, D_B = A - kappa H with the hops
+    that leave the block removed, from delta = 0 (oracle.sap.mr_blocks on one
+    block); rho and the result are (N, 4, 3) at the block's sites."""
+    dims = _dims(U)
+    lin = _linear(dims, sites)
+    order = np.argsort(lin)
+    slin = lin[order]
+    A = clover_at(U, kappa, csw, sites)
+
+    def DB(v):
+        def v_at(x):
+            lx = _linear(dims, x)
+            pos = np.clip(np.searchsorted(slin, lx), 0, len(slin) - 1)
+            inside = slin[pos] == lx
+            out = np.zeros((len(x), 4, 3), dtype=np.complex128)
+            out[inside] = v[order[pos[inside]]]
+            return out
+        return site_mul(A, v) - kappa * hop_at(U, v_at, t_bc, sites)
+
+    r = rho.copy()
+    delta = np.zeros_like(rho)
+    for _ in range(n_mr):
+        q = DB(r)
+        qq = np.sum(np.abs(q) ** 2)
+        a = np.sum(np.conj(q) * r) / qq if qq > 0 else 0.0
+        delta = delta + a * r
+        r = r - a * q
+    return delta
+
+
+def sap_one_cycle_at(U, kappa, csw, t_bc, eta, bdims, block_origin, n_mr):
+    """M eta of one SAP cycle (colour 0 blocks from eta, then colour 1 blocks
+    from eta - D psi), at the sites of the block starting at block_origin:
+    a colour-0 block depends only on its own sites; a colour-1 block also on
+    the colour-0 updates of the blocks across its faces, computed here
+    (oracle.sap.sap with ncy = 1, evaluated block by block)."""
+    dims = _dims(U)
+    origin = np.asarray(block_origin)
+    colour = int(np.sum(origin // np.asarray(bdims)) % 2)
+    sites = _block_sites(origin, bdims)
+    if colour == 0:
+        return sites, _block_mr(U, kappa, csw, t_bc, sites, gather(eta, sites), n_mr)
+    # psi after the colour-0 half cycle, on the neighbouring colour-0 blocks
+    psi0 = {}
+    for mu in range(4):
+        for sg in (+1, -1):
+            o = origin.copy()
+            o[mu] = (o[mu] + sg * bdims[mu]) % dims[mu]
+            key = tuple(o)
+            if key not in psi0:
+                s0 = _block_sites(o, bdims)
+                psi0[key] = (s0, _block_mr(U, kappa, csw, t_bc, s0, gather(eta, s0), n_mr))
+    all_s = np.concatenate([v[0] for v in psi0.values()])
+    all_v = np.concatenate([v[1] for v in psi0.values()])
+    alin = _linear(dims, all_s)
+    order = np.argsort(alin)
+    slin = alin[order]
+
+    def psi_at(x):
+        lx = _linear(dims, x)
+        pos = np.clip(np.searchsorted(slin, lx), 0, len(slin) - 1)
+        out = np.zeros((len(x), 4, 3), dtype=np.complex128)
+        hit = slin[pos] == lx
+        out[hit] = all_v[order[pos[hit]]]
+        return out
+
+    # rho = eta - D psi at the block (psi is zero on the block itself)
+    rho = gather(eta, sites) + kappa * hop_at(U, psi_at, t_bc, sites)
+    return sites, _block_mr(U, kappa, csw, t_bc, sites, rho, n_mr)

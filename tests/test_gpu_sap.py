@@ -115,3 +115,14 @@ def test_sap_properties_at_benchmark_size():
     dm = torch.empty_like(eta)
     lat.apply("D", 0, m1, dm)
     assert torch.linalg.vector_norm(eta - dm) < 0.5 * torch.linalg.vector_norm(eta)
+    # one cycle against the oracle evaluated block by block (oracle.sampled):
+    # blocks of both colours, at the lattice edges (antiperiodic t) and inside
+    from oracle import sampled
+    m1c = torch.empty_like(eta)
+    lat.apply_sap(eta, m1c, (16, 4, 2, 2), 1, 6)
+    got_all = from_dev(m1c)
+    eta_h = from_dev(eta)
+    for origin in ((0, 0, 0, 0), (16, 0, 0, 0), (16, 28, 30, 62), (0, 28, 30, 62), (16, 4, 14, 32), (0, 4, 14, 32)):
+        sites, want = sampled.sap_one_cycle_at(U, kappa, 1.0, -1, eta_h, (16, 4, 2, 2), origin, 6)
+        got = sampled.gather(got_all, sites)
+        assert dirac.rel_l2(got, want) <= SAP_TOL, origin

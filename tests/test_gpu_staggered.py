@@ -117,3 +117,24 @@ def test_stag_antihermitian_at_benchmark_size():
     lhs = torch.vdot(a.flatten(), hb.flatten()).item()
     rhs = -torch.vdot(ha.flatten(), b.flatten()).item()
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs), (lhs, rhs)
+
+
+def test_stag_sampled_at_benchmark_size():
+    """D = m + H at the benchmarked 32^3x64 size against the oracle evaluated
+    site by site (oracle.sampled) at random sites and at sites on both ends of
+    every direction (the antiperiodic t boundary), FP64 to 1e-13 and FP32 to
+    1e-5."""
+    from oracle import sampled
+    dims, mass = (32, 32, 32, 64), 0.05
+    U = fg.gauge_field(dims, 93, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    chi = colour_field(dims, 94)
+    a = to_dev(chi)
+    out = to_dev(np.zeros_like(chi))
+    edges = np.array([[x, y, z, t] for x in (0, 31) for y in (0, 31) for z in (0, 31) for t in (0, 63)])
+    sites = np.concatenate([sampled.random_sites(dims, 64, 95), edges])
+    want = sampled.stag_dirac_at(U, chi, mass, -1, sites)
+    for prec in (0, 1):
+        lat.stag_apply("D", prec, mass, a, out)
+        got = sampled.gather(from_dev(out), sites)
+        assert dirac.rel_l2(got, want) <= TOL[prec], prec

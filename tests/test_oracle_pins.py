@@ -341,3 +341,28 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     # periodic instead of antiperiodic time
     monkeypatch.setattr(dirac, "boundary_factor", lambda d, mu, s, bc: np.ones((d[3], d[2], d[1], d[0])))
     assert dirac.rel_l2(dirac.Operator(U, 0.12).D(psi), expect) > 1e-3
+
+
+def test_sampled_staggered_and_sap_match_whole_field():
+    """The site-sampled staggered operator and the block-by-block SAP cycle
+    against the whole-field oracle (oracle.staggered, oracle.sap) on small
+    lattices."""
+    from oracle import sap, staggered
+    dims = (4, 6, 4, 8)
+    U = field(dims, 121, "smooth", 0.4)
+    rng = np.random.default_rng(122)
+    chi = rng.normal(size=(dims[3], dims[2], dims[1], dims[0], 3)) + 1j * rng.normal(
+        size=(dims[3], dims[2], dims[1], dims[0], 3))
+    op = staggered.Staggered(U, 0.07, -1)
+    sites = sampled.random_sites(dims, 40, 11)
+    got = sampled.stag_dirac_at(U, chi, 0.07, -1, sites)
+    assert np.abs(got - sampled.gather(op.D(chi), sites)).max() < 1e-13
+    dims = (8, 4, 4, 8)
+    U = field(dims, 123, "smooth", 0.4)
+    eta = fg.gaussian_spinor(dims, 124)
+    bdims = (4, 2, 2, 2)
+    d = dirac.Operator(U, 0.13, 1.1, -1)
+    whole = sap.sap(d.D, sap.Blocks(dims, bdims), eta, 1, 3)
+    for origin in ((0, 0, 0, 0), (4, 0, 0, 0), (0, 2, 2, 6), (4, 2, 0, 4)):
+        s, v = sampled.sap_one_cycle_at(U, 0.13, 1.1, -1, eta, bdims, origin, 3)
+        assert np.abs(v - sampled.gather(whole, s)).max() < 1e-12 * np.abs(v).max(), origin
