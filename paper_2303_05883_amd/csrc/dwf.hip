@@ -350,22 +350,68 @@ __global__ void __launch_bounds__(DWB) k_dwf_sop(DwfArgs a, int p, const char* x
   if (live) IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, o);
 }
 
-// out = scale H in (DAG: scale gamma5 H gamma5 in) on the parity-p half, from
-// the other half of in
+// The one-parity hop followed by site-local operators in one pass: y = scale
+// H in (DAG: scale gamma5 H gamma5 in) at this lane's 5-d site, then
+// out_s = sum_s' (X_+ P_+ x + X_- P_- x)_s' + (Y_+ P_+ y + Y_- P_- y)_s' on
+// the parity-p half, the x part only when mx is given (x read from memory at
+// the own 4-d site), the y part from the lanes' registers through LDS, so the
+// hop result never goes to memory. mx, my: pairs of Ls x Ls row-major real
+// matrices (A_+, A_-) as k_dwf_sop takes them.
 template <int P, bool DAG>
-__global__ void __launch_bounds__(DWB) k_dwf_hop1(DwfArgs a, int p, double scale) {
+__global__ void __launch_bounds__(DWB) k_dwf_hopsop(DwfArgs a, int p, double scale, const char* x5,
+                                                    const double* mx, const double* my) {
   using T = typename IO<P>::T;
+  __shared__ cx<T> lp[6][DWB], lm[6][DWB];
+  const int Ls = a.Ls;
   size_t j = 0;
-  if (!dwf_site(a, j)) return;
-  const int i = (int)(j / a.Ls), s = (int)(j - (size_t)i * a.Ls);
-  cx<T> acc[12];
+  const bool live = dwf_site(a, j);
+  const int i = live ? (int)(j / Ls) : 0;
+  const int s = live ? (int)(j - (size_t)i * Ls) : 0;
+  const int base = (int)threadIdx.x - s;
+  cx<T> y[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
-  dwf_hop<P, DAG>(a, a.in, p, i, s, acc);
-  const T sc = (T)scale;
+  for (int k = 0; k < 12; ++k) y[k] = {T(0), T(0)};
+  if (live) {
+    dwf_hop<P, DAG>(a, a.in, p, i, s, y);
+    const T sc = (T)scale;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
-  IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, acc);
+    for (int k = 0; k < 12; ++k) y[k] = sc * y[k];
+  }
+  cx<T> o[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o[k] = {T(0), T(0)};
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* M = pass == 0 ? mx : my;
+    if (!M) continue;  // uniform over the launch
+    cx<T> v[12];
+    if (pass == 1) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = y[k];
+      if (mx) __syncthreads();  // the x pass has read its halves
+    } else if (live) {
+      IO<P>::load_spinor(x5 + (size_t)p * a.hb, j, v);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = {T(0), T(0)};
+    }
+    put_halves(lp, lm, v);
+    __syncthreads();
+    if (live) {
+      const double* Ap = M + (size_t)s * Ls;
+      const double* Am = Ap + (size_t)Ls * Ls;
+      for (int t = 0; t < Ls; ++t) {
+        const T cp = (T)Ap[t], cm = (T)Am[t];
+        if (cp == T(0) && cm == T(0)) continue;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const cx<T> up = cp * lp[k][base + t], um = cm * lm[k][base + t];
+          o[k] = o[k] + up + um;
+          o[6 + k] = o[6 + k] - up + um;
+        }
+      }
+    }
+  }
+  if (live) IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, o);
 }
 
 // canonical [s][t][z][y][x][spin][colour] complex128 <-> native 5-d field
@@ -741,33 +787,35 @@ struct EoCtx {
     LQ_HIP(hipGetLastError());
     return LQCD_OK;
   }
-  int hop(int p, const void* in, void* out, bool dag) const {
+  // out = scale H in, then the site-local operators of k_dwf_hopsop (x part
+  // with pair ex when x is given, y part with pair ey)
+  int hopsop(int p, const void* in, const void* x, int ex, int ey, void* out, bool dag) const {
     DwfArgs b = a;
     b.in = reinterpret_cast<const char*>(in);
     b.out = reinterpret_cast<char*>(out);
+    const char* xs = reinterpret_cast<const char*>(x);
+    const double* mx = x ? pair(ex) : nullptr;
+    const double* my = pair(ey);
     if (prec == 0) {
-      if (dag) hipLaunchKernelGGL((k_dwf_hop1<0, true>), grid, block, 0, c->stream, b, p, -0.5);
-      else hipLaunchKernelGGL((k_dwf_hop1<0, false>), grid, block, 0, c->stream, b, p, -0.5);
+      if (dag) hipLaunchKernelGGL((k_dwf_hopsop<0, true>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
+      else hipLaunchKernelGGL((k_dwf_hopsop<0, false>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
     } else {
-      if (dag) hipLaunchKernelGGL((k_dwf_hop1<1, true>), grid, block, 0, c->stream, b, p, -0.5);
-      else hipLaunchKernelGGL((k_dwf_hop1<1, false>), grid, block, 0, c->stream, b, p, -0.5);
+      if (dag) hipLaunchKernelGGL((k_dwf_hopsop<1, true>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
+      else hipLaunchKernelGGL((k_dwf_hopsop<1, false>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
     }
     LQ_HIP(hipGetLastError());
     return LQCD_OK;
   }
-  // out_e = S_ee x_e (dag 0) or S_ee^dag x_e (dag 1); tA, tB: scratch 5-d fields
+  // out_e = S_ee x_e (dag 0) or S_ee^dag x_e (dag 1); tA, tB: scratch 5-d fields.
+  // Each hop is fused with the site-local operator after it (k_dwf_hopsop).
   int schur(int dag, const void* x, void* out, void* tA, void* tB) const {
     if (!dag) {
-      LQ_TRY(sop(0, x, nullptr, EP_B, tA));           // B x
-      LQ_TRY(hop(1, tA, tB, false));                  // Dhop_oe x
-      LQ_TRY(sop(1, tB, nullptr, EP_BMINV, tA));      // B M5^-1 ...
-      LQ_TRY(hop(0, tA, tB, false));                  // Dhop_eo M5^-1 Dhop_oe x
-      return sop(0, x, tB, EP_M5, out);               // M5 x - that
+      LQ_TRY(sop(0, x, nullptr, EP_B, tA));                       // B x
+      LQ_TRY(hopsop(1, tA, nullptr, 0, EP_BMINV, tB, false));     // B M5^-1 Dhop_oe x
+      return hopsop(0, tB, x, EP_M5, EP_MINUS_I, out, false);     // M5 x - Dhop_eo (that)
     }
-    LQ_TRY(hop(1, x, tA, true));                      // -1/2 H^dag_oe x
-    LQ_TRY(sop(1, tA, nullptr, EP_BMINV_T, tB));      // M5^-dag B^dag ...
-    LQ_TRY(hop(0, tB, tA, true));                     // -1/2 H^dag_eo ...
-    return sop(0, x, tA, EP_M5_T, out);               // M5^dag x - B^dag that
+    LQ_TRY(hopsop(1, x, nullptr, 0, EP_BMINV_T, tA, true));       // M5^-dag B^dag (-1/2 H^dag_oe x)
+    return hopsop(0, tA, x, EP_M5_T, EP_MINUS_B_T, out, true);   // M5^dag x - B^dag (-1/2 H^dag_eo that)
   }
 };
 
@@ -850,8 +898,7 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
   if (bnorm == 0.0) return LQCD_OK;
   // b' = b_e - Dhop_eo M5^-1 b_o
   LQ_TRY(e.sop(1, b, nullptr, EP_BMINV, tA));
-  LQ_TRY(e.hop(0, tA, tB, false));
-  LQ_TRY(e.sop(0, b, tB, EP_I, bp));
+  LQ_TRY(e.hopsop(0, tA, b, EP_I, EP_MINUS_I2, bp, false));
   LQ_TRY(e.schur(1, bp, sx, tA, tB));  // S^dag b'
   double sbb = 0.0;
   LQ_TRY(dot(c, w, nh, ev(sx), ev(sx), nullptr, &sbb));
@@ -864,8 +911,7 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
   for (;;) {
     // x_o from x_e, then the true residual with the full operator
     LQ_TRY(e.sop(0, x, nullptr, EP_B, tA));
-    LQ_TRY(e.hop(1, tA, tB, false));
-    LQ_TRY(e.sop(1, b, tB, EP_MINV, x));
+    LQ_TRY(e.hopsop(1, tA, b, EP_MINV, EP_MINUS_MINV, x, false));
     LQ_TRY(dwf_apply(c, 0, d, 0, x, q, tA));
     LQ_TRY(axpy(c, nf, res, b, q, -1.0));
     double tt = 0.0;
