@@ -468,6 +468,31 @@ __global__ void __launch_bounds__(256) k_flat_axpy(void* out, const void* a, con
   IO<0>::store_spinor(out, i, x);
 }
 
+// The CG update in one pass: x += alpha p, r -= alpha q, and the
+// per-workgroup partial sums of |r|^2 (slot 1 of each pair, as k_flat_dot)
+__global__ void __launch_bounds__(256) k_flat_xr(void* x, const void* p, void* r, const void* q, double alpha,
+                                                 double* partials, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (i < n) {
+    cx<double> a[12], b[12];
+    IO<0>::load_spinor(x, i, a);
+    IO<0>::load_spinor(p, i, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = a[k] + alpha * b[k];
+    IO<0>::store_spinor(x, i, a);
+    IO<0>::load_spinor(r, i, a);
+    IO<0>::load_spinor(q, i, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      a[k] = a[k] + (-alpha) * b[k];
+      v[1] += a[k].r * a[k].r + a[k].i * a[k].i;
+    }
+    IO<0>::store_spinor(r, i, a);
+  }
+  block_reduce<2>(v, partials + (size_t)blockIdx.x * 2);
+}
+
 // per-workgroup partial sums of Re <a, b> and <b, b>
 __global__ void __launch_bounds__(256) k_flat_dot(const void* a, const void* b, double* partials, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -584,10 +609,27 @@ int axpy(lqcd_ctx* c, size_t n, void* out, const void* a, const void* b, double 
   return LQCD_OK;
 }
 
+int sum_partials_host(lqcd_ctx* c, DWork& w, size_t n, double* ab, double* bb);
+
 int dot(lqcd_ctx* c, DWork& w, size_t n, const void* a, const void* b, double* ab, double* bb) {
   const int nb = (int)((n + 255) / 256);
   hipLaunchKernelGGL(k_flat_dot, dim3(nb), dim3(256), 0, c->stream, a, b, w.partials, n);
   LQ_HIP(hipGetLastError());
+  return sum_partials_host(c, w, n, ab, bb);
+}
+
+// x += alpha p, r -= alpha q, *rr = |r|^2 (after the update)
+int xr_update(lqcd_ctx* c, DWork& w, size_t n, void* x, const void* p, void* r, const void* q, double alpha,
+              double* rr) {
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_flat_xr, dim3(nb), dim3(256), 0, c->stream, x, p, r, q, alpha, w.partials, n);
+  LQ_HIP(hipGetLastError());
+  return sum_partials_host(c, w, n, nullptr, rr);
+}
+
+// the sums of the (Re <a, b>, <b, b>) partials of the last reduction, on the host
+int sum_partials_host(lqcd_ctx* c, DWork& w, size_t n, double* ab, double* bb) {
+  const int nb = (int)((n + 255) / 256);
   w.host.resize((size_t)nb * 2);
   LQ_HIP(hipMemcpyAsync(w.host.data(), w.partials, w.host.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   LQ_HIP(hipStreamSynchronize(c->stream));
@@ -656,10 +698,8 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
       LQ_TRY(dot(c, w, n, p, q, &pq, nullptr));
       if (!(pq > 0.0)) break;
       const double alpha = rr / pq;
-      LQ_TRY(axpy(c, n, x, x, p, alpha));
-      LQ_TRY(axpy(c, n, r, r, q, -alpha));
       double rn = 0.0;
-      LQ_TRY(dot(c, w, n, r, r, nullptr, &rn));
+      LQ_TRY(xr_update(c, w, n, x, p, r, q, alpha, &rn));
       ++iters;
       if (std::sqrt(rn) <= tgt) {
         rr = rn;
@@ -944,10 +984,8 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
       LQ_TRY(dot(c, w, nh, ev(pv), ev(q), &pq, nullptr));
       if (!(pq > 0.0)) break;
       const double alpha = rr / pq;
-      LQ_TRY(axpy(c, nh, ev(x), ev(x), ev(pv), alpha));
-      LQ_TRY(axpy(c, nh, ev(r), ev(r), ev(q), -alpha));
       double rn = 0.0;
-      LQ_TRY(dot(c, w, nh, ev(r), ev(r), nullptr, &rn));
+      LQ_TRY(xr_update(c, w, nh, ev(x), ev(pv), ev(r), ev(q), alpha, &rn));
       ++iters;
       if (std::sqrt(rn) <= tgt) break;
       LQ_TRY(axpy(c, nh, ev(pv), ev(r), ev(pv), rn / rr));
