@@ -16,9 +16,9 @@
 // same links (one cache line serves them all) and spinors at consecutive j, and
 // the s-hops come from the neighbouring lanes through LDS. A launch covers
 // both parities. The workgroups walk the lattice in an XCD-aware order
-// (dwf_site, dwf_walk): each XCD takes a range of y rows (or of z planes) in
-// every slice and walks it so that the neighbours of the sites in flight were
-// read shortly before by the same XCD and are still in its L2.
+// (dwf_site, dwf_walk): each XCD takes a range of x columns, y rows or z
+// planes in every slice and walks it so that the neighbours of the sites in
+// flight were read shortly before by the same XCD and may still be in its L2.
 //
 // Kernels per application: D with c5 = 0 (b5 folded into the diagonal and the
 // hop scale) and D^dag are one kernel each; D with c5 != 0 first forms
@@ -49,7 +49,8 @@ struct DwfArgs {
   size_t hb;  // bytes of one parity half
   int Ls;
   int spb;   // 5-d sites per workgroup
-  int walk;  // 0: linear order; 1: XCD z-slabs of hw planes (lz = 8 hw); 2: XCD y-ranges of hw rows (ly = 8 hw)
+  int walk;  // 0: linear order; 1: XCD z-slabs of hw planes (lz = 8 hw); 2: XCD y-ranges of hw rows (ly = 8 hw);
+             // 3: XCD x-ranges of hw checkerboard columns (lx/2 = 8 hw)
   int hw;
   double d4;         // 4 - M5
   double b5, c5, mf;
@@ -64,7 +65,16 @@ struct DwfArgs {
 //           then t, then z: the t neighbours were read one step earlier and the
 //           z neighbours lt steps earlier, a working set of lt + 1 slices of
 //           lx/2 x hw sites (the neighbours of the two edge rows come from the
-//           other XCDs' ranges).
+//           other XCDs' ranges);
+//   walk 3: the checkerboard columns xh in [k hw, (k+1) hw), walked those
+//           columns fastest, then t, then z, then y: the t and z neighbours were
+//           read hw and hw lt sites earlier and the y neighbours one y step
+//           (hw lt lz sites) earlier, so the span between the first and the last
+//           read of a spinor is two y steps (2 hw lt lz sites, about 2.7 MB of
+//           traffic through the XCD's L2 at 64x32x16x8 x 8 in FP32); only the x
+//           neighbours of the two edge columns come from other XCDs (a quarter
+//           of a spinor per site at hw = 4, against half of one for the y edges
+//           of walk 2).
 // All Ls lanes of a 4-d site are in one workgroup in every walk.
 __device__ inline bool dwf_site(const DwfArgs& a, size_t& j) {
   const Geom& g = a.g;
@@ -84,6 +94,16 @@ __device__ inline bool dwf_site(const DwfArgs& a, size_t& j) {
     j = (xyi + xy * ((size_t)k * a.hw + zin + (size_t)g.lz * t)) * a.Ls + s;
     return true;
   }
+  if (a.walk == 3) {
+    if (q4 >= (size_t)a.hw * g.lt * g.lz * g.ly) return false;
+    const size_t xin = q4 % a.hw;
+    size_t rest = q4 / a.hw;
+    const size_t t = rest % g.lt;
+    rest /= g.lt;
+    const size_t z = rest % g.lz, y = rest / g.lz;
+    j = ((size_t)k * a.hw + xin + (size_t)g.lxh * (y + (size_t)g.ly * (z + (size_t)g.lz * t))) * a.Ls + s;
+    return true;
+  }
   const size_t rows = (size_t)g.lxh * a.hw;
   if (q4 >= rows * g.lt * g.lz) return false;
   const size_t xr = q4 % rows, rest = q4 / rows;
@@ -93,19 +113,23 @@ __device__ inline bool dwf_site(const DwfArgs& a, size_t& j) {
   return true;
 }
 
-// The walk of a lattice: LQCD_DWF_WALK (0 linear, 1 z-slabs, 2 y-ranges)
-// where it fits the lattice, else y-ranges where ly is a multiple of 8, else
-// z-slabs where lz is, else linear; returns the grid's workgroup count for n
-// 5-d sites of one parity.
-unsigned dwf_walk(const Geom& g, DwfArgs& a, size_t n) {
-  const bool y_ok = g.ly % 8 == 0, z_ok = g.lz % 8 == 0;
-  int w = y_ok ? 2 : (z_ok ? 1 : 0);
+// The walk of a lattice: LQCD_DWF_WALK (0 linear, 1 z-slabs, 2 y-ranges,
+// 3 x-ranges) where it fits the lattice, else x-ranges for FP64 fields where
+// lx/2 is a multiple of 8, else y-ranges where ly is, else z-slabs where lz
+// is, else linear; returns the grid's workgroup count for n 5-d sites of one
+// parity. The x-ranges cut the FP64 spinor re-reads (each XCD keeps whole
+// rows of its columns' neighbours); in FP32 a cache line of a link component
+// spans 32 checkerboard sites of a row, so columns of lx/16 sites would fetch
+// every link line on several XCDs, and the y-ranges are kept.
+unsigned dwf_walk(const Geom& g, DwfArgs& a, size_t n, int prec) {
+  const bool x_ok = g.lxh % 8 == 0, y_ok = g.ly % 8 == 0, z_ok = g.lz % 8 == 0;
+  int w = (prec == 0 && x_ok) ? 3 : (y_ok ? 2 : (z_ok ? 1 : 0));
   if (const char* env = std::getenv("LQCD_DWF_WALK")) {
     const int f = std::atoi(env);
-    if (f == 0 || (f == 1 && z_ok) || (f == 2 && y_ok)) w = f;
+    if (f == 0 || (f == 1 && z_ok) || (f == 2 && y_ok) || (f == 3 && x_ok)) w = f;
   }
   a.walk = w;
-  a.hw = w == 2 ? g.ly / 8 : (w == 1 ? g.lz / 8 : 0);
+  a.hw = w == 3 ? g.lxh / 8 : (w == 2 ? g.ly / 8 : (w == 1 ? g.lz / 8 : 0));
   return w ? 8u * (unsigned)((n / 8 + a.spb - 1) / a.spb) : (unsigned)((n + a.spb - 1) / a.spb);
 }
 
@@ -560,7 +584,7 @@ int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const vo
   a.b5 = d.b5;
   a.c5 = d.c5;
   a.mf = d.mf;
-  const unsigned nb = dwf_walk(c->g, a, (size_t)c->g.vh * d.Ls);
+  const unsigned nb = dwf_walk(c->g, a, (size_t)c->g.vh * d.Ls, prec);
   const dim3 grid(nb, 2), block((a.spb + 63) / 64 * 64);
   if (mob) {
     DwfArgs f = a;
@@ -879,7 +903,7 @@ int eo_setup(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, const double* mats
   a.b5 = d.b5;
   a.c5 = d.c5;
   a.mf = d.mf;
-  e.grid = dim3(dwf_walk(c->g, a, (size_t)c->g.vh * d.Ls));
+  e.grid = dim3(dwf_walk(c->g, a, (size_t)c->g.vh * d.Ls, prec));
   e.block = dim3((a.spb + 63) / 64 * 64);
   return LQCD_OK;
 }

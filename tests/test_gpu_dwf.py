@@ -24,9 +24,12 @@ def field5(dims, Ls, seed):
 
 
 # walks: (4, 4, 16, 4) XCD z-slabs of two planes; (8, 8, 8, 8), (4, 8, 4, 4),
-# (4, 16, 2, 4) XCD y-ranges (as on the benchmarked 64x32x16x8); the rest linear
+# (4, 16, 2, 4) XCD y-ranges (as the benchmarked 64x32x16x8 in FP32);
+# (16, 4, 2, 4) XCD x-ranges of one column in FP64 (as 64x32x16x8 in FP64) and
+# linear in FP32; the rest linear
 @pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 4), ((2, 2, 2, 4), 5), ((4, 6, 8, 10), 3), ((8, 8, 8, 8), 8),
-                                     ((4, 4, 4, 4), 1), ((4, 4, 16, 4), 8), ((4, 8, 4, 4), 3), ((4, 16, 2, 4), 5)])
+                                     ((4, 4, 4, 4), 1), ((4, 4, 16, 4), 8), ((4, 8, 4, 4), 3), ((4, 16, 2, 4), 5),
+                                     ((16, 4, 2, 4), 6)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("t_bc", [-1, 1])
 @pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5), (1.3, 0.0)])
@@ -204,16 +207,16 @@ def test_dwf_sampled_at_benchmark_size():
 
 
 def test_dwf_walks_agree(monkeypatch):
-    """The three XCD walks (linear, z-slabs, y-ranges) only reorder the sites:
-    D, D^dag and S_ee agree bit for bit on a lattice all three fit, and match
-    the oracle."""
-    dims, Ls, b5, c5 = (4, 8, 8, 4), 4, 1.5, 0.5
+    """The four XCD walks (linear, z-slabs, y-ranges, x-ranges) only reorder
+    the sites: D, D^dag and S_ee agree bit for bit on a lattice all four fit,
+    and match the oracle."""
+    dims, Ls, b5, c5 = (16, 8, 8, 4), 4, 1.5, 0.5
     U = fg.gauge_field(dims, 131, "haar")
     op = dwf.DomainWall(U, 1.8, 0.05, Ls, -1, b5, c5)
     psi = field5(dims, Ls, 132)
     lat = lattice(dims, U, 0.12, 0.0)
     results = {}
-    for walk in ("0", "1", "2"):
+    for walk in ("0", "1", "2", "3"):
         monkeypatch.setenv("LQCD_DWF_WALK", walk)
         outs = []
         for prec in (0, 1):
@@ -225,7 +228,7 @@ def test_dwf_walks_agree(monkeypatch):
             lat.dwf_apply_schur(Ls, 1.8, 0.05, prec, to_dev(psi), out, b5=b5, c5=c5)
             outs.append(from_dev(out))
         results[walk] = outs
-    for walk in ("1", "2"):
+    for walk in ("1", "2", "3"):
         for a, b in zip(results["0"], results[walk]):
             assert np.array_equal(a, b), walk
     assert dirac.rel_l2(results["2"][0], op.D(psi)) <= TOL[0]
