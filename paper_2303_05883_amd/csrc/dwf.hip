@@ -380,10 +380,11 @@ __global__ void __launch_bounds__(DWB) k_dwf_sop(DwfArgs a, int p, const char* x
 // the parity-p half, the x part only when mx is given (x read from memory at
 // the own 4-d site), the y part from the lanes' registers through LDS, so the
 // hop result never goes to memory. mx, my: pairs of Ls x Ls row-major real
-// matrices (A_+, A_-) as k_dwf_sop takes them.
+// matrices (A_+, A_-) as k_dwf_sop takes them. With norm_partials, the
+// workgroup's partial sum of |out|^2 goes to slot 1 of its pair (slot 0 = 0).
 template <int P, bool DAG>
 __global__ void __launch_bounds__(DWB) k_dwf_hopsop(DwfArgs a, int p, double scale, const char* x5,
-                                                    const double* mx, const double* my) {
+                                                    const double* mx, const double* my, double* norm_partials) {
   using T = typename IO<P>::T;
   __shared__ cx<T> lp[6][DWB], lm[6][DWB];
   const int Ls = a.Ls;
@@ -436,6 +437,14 @@ __global__ void __launch_bounds__(DWB) k_dwf_hopsop(DwfArgs a, int p, double sca
     }
   }
   if (live) IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, o);
+  if (norm_partials) {  // uniform over the launch
+    double v[2] = {0.0, 0.0};
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[1] += (double)o[k].r * (double)o[k].r + (double)o[k].i * (double)o[k].i;
+    }
+    block_reduce<2>(v, norm_partials + (size_t)blockIdx.x * 2);
+  }
 }
 
 // canonical [s][t][z][y][x][spin][colour] complex128 <-> native 5-d field
@@ -853,7 +862,8 @@ struct EoCtx {
   }
   // out = scale H in, then the site-local operators of k_dwf_hopsop (x part
   // with pair ex when x is given, y part with pair ey)
-  int hopsop(int p, const void* in, const void* x, int ex, int ey, void* out, bool dag) const {
+  int hopsop(int p, const void* in, const void* x, int ex, int ey, void* out, bool dag,
+             double* norm_partials = nullptr) const {
     DwfArgs b = a;
     b.in = reinterpret_cast<const char*>(in);
     b.out = reinterpret_cast<char*>(out);
@@ -861,22 +871,24 @@ struct EoCtx {
     const double* mx = x ? pair(ex) : nullptr;
     const double* my = pair(ey);
     if (prec == 0) {
-      if (dag) hipLaunchKernelGGL((k_dwf_hopsop<0, true>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
-      else hipLaunchKernelGGL((k_dwf_hopsop<0, false>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
+      if (dag) hipLaunchKernelGGL((k_dwf_hopsop<0, true>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my, norm_partials);
+      else hipLaunchKernelGGL((k_dwf_hopsop<0, false>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my, norm_partials);
     } else {
-      if (dag) hipLaunchKernelGGL((k_dwf_hopsop<1, true>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
-      else hipLaunchKernelGGL((k_dwf_hopsop<1, false>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my);
+      if (dag) hipLaunchKernelGGL((k_dwf_hopsop<1, true>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my, norm_partials);
+      else hipLaunchKernelGGL((k_dwf_hopsop<1, false>), grid, block, 0, c->stream, b, p, -0.5, xs, mx, my, norm_partials);
     }
     LQ_HIP(hipGetLastError());
     return LQCD_OK;
   }
   // out_e = S_ee x_e (dag 0) or S_ee^dag x_e (dag 1); tA, tB: scratch 5-d fields.
   // Each hop is fused with the site-local operator after it (k_dwf_hopsop).
-  int schur(int dag, const void* x, void* out, void* tA, void* tB) const {
+  // norm_partials (dag 0 only): the workgroups' partial sums of |out_e|^2, as
+  // (0, value) pairs, one pair per workgroup of grid.
+  int schur(int dag, const void* x, void* out, void* tA, void* tB, double* norm_partials = nullptr) const {
     if (!dag) {
-      LQ_TRY(sop(0, x, nullptr, EP_B, tA));                       // B x
-      LQ_TRY(hopsop(1, tA, nullptr, 0, EP_BMINV, tB, false));     // B M5^-1 Dhop_oe x
-      return hopsop(0, tB, x, EP_M5, EP_MINUS_I, out, false);     // M5 x - Dhop_eo (that)
+      LQ_TRY(sop(0, x, nullptr, EP_B, tA));                                  // B x
+      LQ_TRY(hopsop(1, tA, nullptr, 0, EP_BMINV, tB, false));                // B M5^-1 Dhop_oe x
+      return hopsop(0, tB, x, EP_M5, EP_MINUS_I, out, false, norm_partials);  // M5 x - Dhop_eo (that)
     }
     LQ_TRY(hopsop(1, x, nullptr, 0, EP_BMINV_T, tA, true));       // M5^-dag B^dag (-1/2 H^dag_oe x)
     return hopsop(0, tA, x, EP_M5_T, EP_MINUS_B_T, out, true);   // M5^dag x - B^dag (-1/2 H^dag_eo that)
@@ -950,7 +962,8 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
   const size_t nh = padded_sites((size_t)c->g.vh * d.Ls), nf = 2 * nh;
   void *bp, *r, *pv, *q, *sx, *tA, *tB, *res;
   for (void** f : {&bp, &r, &pv, &q, &sx, &tA, &tB, &res}) LQ_TRY(w.alloc(c, bytes, f));
-  LQ_HIP(hipMalloc(&w.partials, (size_t)((nf + 255) / 256) * 2 * sizeof(double)));
+  // pairs for the flat reductions (one per 256 sites) and for the norm of S p (one per operator workgroup)
+  LQ_HIP(hipMalloc(&w.partials, std::max((size_t)(nf + 255) / 256, (size_t)e.grid.x) * 2 * sizeof(double)));
   auto ev = [](void* f) { return f; };  // even half = start of the field
   double bb = 0.0;
   LQ_TRY(dot(c, w, nf, b, b, nullptr, &bb));
@@ -968,9 +981,12 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
   LQ_TRY(dot(c, w, nh, ev(sx), ev(sx), nullptr, &sbb));
   int iters = 0, passes = 0, status = LQCD_OK;
   double true_rel = 1.0, target = 0.1 * prm.tol * std::sqrt(sbb);
-  auto normal = [&](void* in, void* out) -> int {  // out_e = S^dag S in_e
-    LQ_TRY(e.schur(0, in, sx, tA, tB));
-    return e.schur(1, sx, out, tA, tB);
+  // out_e = S^dag S in_e and *sn = |S in_e|^2 (= <in_e, out_e>, summed by the
+  // workgroups of the operator's last launch: no separate dot product pass)
+  auto normal = [&](void* in, void* out, double* sn) -> int {
+    LQ_TRY(e.schur(0, in, sx, tA, tB, w.partials));
+    LQ_TRY(e.schur(1, sx, out, tA, tB));
+    return sum_partials_host(c, w, (size_t)e.grid.x * 256, nullptr, sn);
   };
   for (;;) {
     // x_o from x_e, then the true residual with the full operator
@@ -1003,9 +1019,8 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
     LQ_TRY(axpy(c, nh, ev(pv), ev(r), ev(r), 0.0));
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
     while (iters < prm.max_iter) {
-      LQ_TRY(normal(pv, q));
       double pq = 0.0;
-      LQ_TRY(dot(c, w, nh, ev(pv), ev(q), &pq, nullptr));
+      LQ_TRY(normal(pv, q, &pq));
       if (!(pq > 0.0)) break;
       const double alpha = rr / pq;
       double rn = 0.0;
