@@ -54,6 +54,7 @@ struct DwfArgs {
   int hw;
   double d4;         // 4 - M5
   double b5, c5, mf;
+  double* norm;      // k_dwf: partial sums of |out|^2, a (0, value) pair per workgroup, or null
 };
 
 // The 5-d site of this lane, or false past the end. XCD k (the workgroups
@@ -271,27 +272,36 @@ __global__ void __launch_bounds__(DWB) k_dwf(DwfArgs a) {
     put_halves(lp, lm, v);
   }
   __syncthreads();
-  if (!live) return;
-  const SNeighbours<T> nb = neighbours(lp, lm, s, Ls, a.mf);
   cx<T> o[12];
-  if (DAG) {
-    const T b5 = (T)a.b5;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) o[k] = b5 * acc[k] + v[k];
-    add_s<true>(nb, T(1), o);
-  } else if (MOB) {
-    cx<T> f[12];
-    IO<P>::load_spinor(a.phi + (size_t)p * a.hb, j, f);
+  for (int k = 0; k < 12; ++k) o[k] = {T(0), T(0)};
+  if (live) {
+    const SNeighbours<T> nb = neighbours(lp, lm, s, Ls, a.mf);
+    if (DAG) {
+      const T b5 = (T)a.b5;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) o[k] = d4 * f[k] + half * acc[k] + v[k];
-    add_s<false>(nb, T(-1), o);
-  } else {
-    const T b5 = (T)a.b5, dg = b5 * d4 + T(1), sc = half * b5;
+      for (int k = 0; k < 12; ++k) o[k] = b5 * acc[k] + v[k];
+      add_s<true>(nb, T(1), o);
+    } else if (MOB) {
+      cx<T> f[12];
+      IO<P>::load_spinor(a.phi + (size_t)p * a.hb, j, f);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) o[k] = dg * v[k] + sc * acc[k];
-    add_s<false>(nb, T(-1), o);
+      for (int k = 0; k < 12; ++k) o[k] = d4 * f[k] + half * acc[k] + v[k];
+      add_s<false>(nb, T(-1), o);
+    } else {
+      const T b5 = (T)a.b5, dg = b5 * d4 + T(1), sc = half * b5;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) o[k] = dg * v[k] + sc * acc[k];
+      add_s<false>(nb, T(-1), o);
+    }
+    IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, o);
   }
-  IO<P>::store_spinor(a.out + (size_t)p * a.hb, j, o);
+  if (a.norm) {  // uniform over the launch: the workgroup's partial |out|^2, slot 1 of its pair
+    double nv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) nv[1] += (double)o[k].r * (double)o[k].r + (double)o[k].i * (double)o[k].i;
+    block_reduce<2>(nv, a.norm + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2);
+  }
 }
 
 // out = (b5 + c5 S) in, every 5-d site
@@ -571,9 +581,17 @@ int dwf_export(lqcd_ctx* c, int prec, int Ls, const void* f5, double* canon) {
   return LQCD_OK;
 }
 
+// workgroups of one dwf_apply launch (both parities): the pairs its norm_partials receive
+size_t dwf_apply_groups(const Geom& g, int prec, int Ls) {
+  DwfArgs a{};
+  a.spb = (DWB / Ls) * Ls;
+  return 2 * (size_t)dwf_walk(g, a, (size_t)g.vh * Ls, prec);
+}
+
 // out = D in (dag = 0) or D^dag in (dag = 1) on native 5-d fields (in != out;
 // tmp, a third field, holds phi for D with c5 != 0)
-int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tmp) {
+int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tmp,
+              double* norm_partials) {
   if (!c->gauge[prec]) return set_error(LQCD_ESTATE, "gauge field not set");
   if (d.Ls < 1 || d.Ls > DWB) return set_error(LQCD_EINVAL, "domain-wall operator: Ls must be in [1, 256]");
   if (prec != 0 && prec != 1) return set_error(LQCD_EINVAL, "domain-wall operator: precision must be F64 or F32");
@@ -595,9 +613,11 @@ int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const vo
   a.mf = d.mf;
   const unsigned nb = dwf_walk(c->g, a, (size_t)c->g.vh * d.Ls, prec);
   const dim3 grid(nb, 2), block((a.spb + 63) / 64 * 64);
+  a.norm = norm_partials;
   if (mob) {
     DwfArgs f = a;
     f.out = reinterpret_cast<char*>(tmp);
+    f.norm = nullptr;
     if (prec == 0) hipLaunchKernelGGL(k_dwf_phi<0>, grid, block, 0, c->stream, f);
     else hipLaunchKernelGGL(k_dwf_phi<1>, grid, block, 0, c->stream, f);
   }
@@ -686,7 +706,9 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
   const size_t bytes = dwf_field_bytes(0, c->g.vh, d.Ls), n = 2 * padded_sites((size_t)c->g.vh * d.Ls);
   void *bn, *r, *p, *q, *t, *ph;
   for (void** f : {&bn, &r, &p, &q, &t, &ph}) LQ_TRY(w.alloc(c, bytes, f));
-  LQ_HIP(hipMalloc(&w.partials, (size_t)((n + 255) / 256) * 2 * sizeof(double)));
+  // pairs for the flat reductions (one per 256 sites) and for the norm of D p (one per operator workgroup)
+  const size_t ngroups = dwf_apply_groups(c->g, 0, d.Ls);
+  LQ_HIP(hipMalloc(&w.partials, std::max((size_t)(n + 255) / 256, ngroups) * 2 * sizeof(double)));
   double bb = 0.0;
   LQ_TRY(dot(c, w, n, b, b, nullptr, &bb));
   const double bnorm = std::sqrt(bb);
@@ -725,10 +747,10 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
     LQ_TRY(axpy(c, n, p, r, r, 0.0));             // p = r
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
     while (iters < prm.max_iter) {
-      LQ_TRY(dwf_apply(c, 0, d, 0, p, t, ph));
-      LQ_TRY(dwf_apply(c, 0, d, 1, t, q, ph));  // q = D^dag D p
-      double pq = 0.0;
-      LQ_TRY(dot(c, w, n, p, q, &pq, nullptr));
+      LQ_TRY(dwf_apply(c, 0, d, 0, p, t, ph, w.partials));  // t = D p, with the partials of |D p|^2
+      LQ_TRY(dwf_apply(c, 0, d, 1, t, q, ph));              // q = D^dag D p
+      double pq = 0.0;                                       // <p, D^dag D p> = |D p|^2
+      LQ_TRY(sum_partials_host(c, w, ngroups * 256, nullptr, &pq));
       if (!(pq > 0.0)) break;
       const double alpha = rr / pq;
       double rn = 0.0;
