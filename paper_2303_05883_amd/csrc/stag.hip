@@ -69,15 +69,15 @@ struct StagArgs {
   const void* own;     // parity p, or null
   void* out;
   double c_own, c_hop;  // out = c_own own + c_hop H in
+  double* dot_partials;  // if set (with own): per-workgroup pairs (Re <own, out>, 0)
 };
 
-// out = c_own own + c_hop (H in) at the sites of parity p
+// out = c_own own + c_hop (H in) at site i of parity p; with dot_partials,
+// Re <own, out> at the site into red[0]
 template <int P>
-__global__ void __launch_bounds__(SBS) k_stag_hop(StagArgs a) {
+__device__ inline void stag_hop_site(const StagArgs& a, size_t i, double red[2]) {
   using T = typename SIO<P>::T;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Geom& g = a.g;
-  if (i >= (size_t)g.vh) return;
   const int ii = (int)i;
   const int xh = ii % g.lxh;
   int r = ii / g.lxh;
@@ -138,8 +138,20 @@ __global__ void __launch_bounds__(SBS) k_stag_hop(StagArgs a) {
     const T co = (T)a.c_own;
 #pragma unroll
     for (int c = 0; c < 3; ++c) out[c] = out[c] + co * o[c];
+    if (a.dot_partials) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) red[0] += (double)o[c].r * (double)out[c].r + (double)o[c].i * (double)out[c].i;
+    }
   }
   SIO<P>::store(a.out, i, out);
+}
+
+template <int P>
+__global__ void __launch_bounds__(SBS) k_stag_hop(StagArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double red[2] = {0.0, 0.0};
+  if (i < (size_t)a.g.vh) stag_hop_site<P>(a, i, red);
+  if (a.dot_partials) block_reduce<2>(red, a.dot_partials + (size_t)blockIdx.x * 2);  // uniform over the launch
 }
 
 // canonical full-lattice [t, z, y, x, colour] complex128 <-> native half of one parity
@@ -216,6 +228,31 @@ __global__ void __launch_bounds__(SBS) k_stag_dot(const void* a, const void* b, 
   block_reduce<2>(v, partials + (size_t)blockIdx.x * 2);
 }
 
+// FP64 CG update in one pass: x += alpha p, r -= alpha q, per-workgroup
+// pairs (0, |r|^2) of the updated r
+__global__ void __launch_bounds__(SBS) k_stag_xr(void* x, const void* p, void* r, const void* q, double alpha,
+                                                 double* partials, size_t vh) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (i < vh) {
+    cx<double> a[3], b[3];
+    SIO<0>::load(x, i, a);
+    SIO<0>::load(p, i, b);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] = a[k] + alpha * b[k];
+    SIO<0>::store(x, i, a);
+    SIO<0>::load(r, i, a);
+    SIO<0>::load(q, i, b);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] = a[k] + (-alpha) * b[k];
+      v[1] += a[k].r * a[k].r + a[k].i * a[k].i;
+    }
+    SIO<0>::store(r, i, a);
+  }
+  block_reduce<2>(v, partials + (size_t)blockIdx.x * 2);
+}
+
 int grid_for_sites(size_t n) { return (int)((n + SBS - 1) / SBS); }
 
 }  // namespace
@@ -239,7 +276,8 @@ int stag_export(lqcd_ctx* c, int prec, int parity, const void* half, double* can
 }
 
 int stag_hop(lqcd_ctx* c, int prec, int out_parity, const void* in, const void* own, double c_own, double c_hop,
-             void* out) {
+             void* out, double* dot_partials) {
+  if (dot_partials && !own) return set_error(LQCD_EINVAL, "staggered hop: a dot product with no own field");
   StagArgs a;
   a.g = c->g;
   a.p = out_parity;
@@ -250,6 +288,7 @@ int stag_hop(lqcd_ctx* c, int prec, int out_parity, const void* in, const void* 
   a.out = out;
   a.c_own = c_own;
   a.c_hop = c_hop;
+  a.dot_partials = dot_partials;
   const int nb = grid_for_sites(c->g.vh);
   if (prec == 0) hipLaunchKernelGGL(k_stag_hop<0>, dim3(nb), dim3(SBS), 0, c->stream, a);
   else hipLaunchKernelGGL(k_stag_hop<1>, dim3(nb), dim3(SBS), 0, c->stream, a);
@@ -284,11 +323,10 @@ int axpby(lqcd_ctx* c, void* out, const void* a, double ca, const void* b = null
   return LQCD_OK;
 }
 
-// Re <a, b> and <b, b>, summed on the host in a fixed order
-int dot(lqcd_ctx* c, SWork& w, const void* a, const void* b, double* ab, double* bb) {
+// the sums of the pairs of the last reduction (one pair per workgroup of a
+// site-parallel launch), on the host in a fixed order
+int sum_pairs(lqcd_ctx* c, SWork& w, double* ab, double* bb) {
   const int nb = grid_for_sites(c->g.vh);
-  hipLaunchKernelGGL(k_stag_dot, dim3(nb), dim3(SBS), 0, c->stream, a, b, w.partials, (size_t)c->g.vh);
-  LQ_HIP(hipGetLastError());
   w.host.resize((size_t)nb * 2);
   LQ_HIP(hipMemcpyAsync(w.host.data(), w.partials, w.host.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   LQ_HIP(hipStreamSynchronize(c->stream));
@@ -302,11 +340,27 @@ int dot(lqcd_ctx* c, SWork& w, const void* a, const void* b, double* ab, double*
   return LQCD_OK;
 }
 
+// Re <a, b> and <b, b>
+int dot(lqcd_ctx* c, SWork& w, const void* a, const void* b, double* ab, double* bb) {
+  const int nb = grid_for_sites(c->g.vh);
+  hipLaunchKernelGGL(k_stag_dot, dim3(nb), dim3(SBS), 0, c->stream, a, b, w.partials, (size_t)c->g.vh);
+  LQ_HIP(hipGetLastError());
+  return sum_pairs(c, w, ab, bb);
+}
+
+// x += alpha p, r -= alpha q, *rr = |r|^2 after the update
+int xr_update(lqcd_ctx* c, SWork& w, void* x, const void* p, void* r, const void* q, double alpha, double* rr) {
+  const int nb = grid_for_sites(c->g.vh);
+  hipLaunchKernelGGL(k_stag_xr, dim3(nb), dim3(SBS), 0, c->stream, x, p, r, q, alpha, w.partials, (size_t)c->g.vh);
+  LQ_HIP(hipGetLastError());
+  return sum_pairs(c, w, nullptr, rr);
+}
+
 }  // namespace
 
-int stag_schur(lqcd_ctx* c, int prec, double mass, const void* x_e, void* tmp_o, void* out_e) {
-  LQ_TRY(stag_hop(c, prec, 1, x_e, nullptr, 0.0, 1.0, tmp_o));       // H_oe x
-  return stag_hop(c, prec, 0, tmp_o, x_e, mass * mass, -1.0, out_e);  // m^2 x - H_eo H_oe x
+int stag_schur(lqcd_ctx* c, int prec, double mass, const void* x_e, void* tmp_o, void* out_e, double* dot_partials) {
+  LQ_TRY(stag_hop(c, prec, 1, x_e, nullptr, 0.0, 1.0, tmp_o));                     // H_oe x
+  return stag_hop(c, prec, 0, tmp_o, x_e, mass * mass, -1.0, out_e, dot_partials);  // m^2 x - H_eo H_oe x
 }
 
 int stag_solve(lqcd_ctx* c, double mass, const lqcd_solve_params& prm, const void* b_e, const void* b_o, void* x_e,
@@ -370,15 +424,13 @@ int stag_solve(lqcd_ctx* c, double mass, const lqcd_solve_params& prm, const voi
     LQ_TRY(axpby(c, p, r, 1.0));
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
     while (iters < prm.max_iter) {
-      LQ_TRY(stag_schur(c, 0, mass, p, t, q));
+      LQ_TRY(stag_schur(c, 0, mass, p, t, q, w.partials));  // q = (m^2 - H_eo H_oe) p, with Re <p, q>
       double pq = 0.0;
-      LQ_TRY(dot(c, w, p, q, &pq, nullptr));
+      LQ_TRY(sum_pairs(c, w, &pq, nullptr));
       if (!(pq > 0.0)) break;
       const double alpha = rr / pq;
-      LQ_TRY(axpby(c, x_e, x_e, 1.0, p, alpha));
-      LQ_TRY(axpby(c, r, r, 1.0, q, -alpha));
       double rr_new = 0.0;
-      LQ_TRY(dot(c, w, r, r, nullptr, &rr_new));
+      LQ_TRY(xr_update(c, w, x_e, p, r, q, alpha, &rr_new));
       ++iters;
       if (std::sqrt(rr_new) <= tgt) {
         rr = rr_new;
