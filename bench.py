@@ -27,6 +27,12 @@ Other workloads (not the headline line; same JSON shape):
                      flexible BiCGStab with the FP32 SAP preconditioner
   --workload staggered  32^3x64 staggered operator, mass 0.05, FP64 CG on the
                      even-odd normal system
+  --workload mg      the clover workload with the two-level multigrid
+                     preconditioner
+  --workload dwf     64x32x16x8 x Ls 8 Moebius domain wall: FP64 CG on the
+                     normal equations (timed steps), then the even-odd form
+                     with FP64 CG and with FP32 inner CG under FP64 defect
+                     correction
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -966,11 +972,26 @@ def run_dwf(a, torch, lqcd):
     st_eo = lat.dwf_solve_eo(Ls, d["M5"], d["mf"], b, xe, **mob)
     torch.cuda.synchronize()
     ms_eo = 1000 * (time.perf_counter() - t1)
+    # the same with FP32 inner CG under FP64 defect correction (inner tolerance 1e-6)
+    xe.zero_()
+    lat.dwf_solve_eo(Ls, d["M5"], d["mf"], b, xe, inner_prec=lqcd.F32, **mob)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st_mx = lat.dwf_solve_eo(Ls, d["M5"], d["mf"], b, xe, inner_prec=lqcd.F32, **mob)
+    torch.cuda.synchronize()
+    ms_mx = 1000 * (time.perf_counter() - t1)
+    if not max(st_eo.true_rel_resid, st_mx.true_rel_resid) <= 1e-10:
+        log(f"even-odd true residuals {st_eo.true_rel_resid}, {st_mx.true_rel_resid} above 1e-10")
+        sys.exit(1)
     compare = {"full_cg": {"ms": round(ms_step, 2), "cg_iters": stats[-1].inner_iters,
                            "true_rel_resid": stats[-1].true_rel_resid},
                "even_odd_cg": {"ms": round(ms_eo, 2), "cg_iters": st_eo.inner_iters,
                                "true_rel_resid": st_eo.true_rel_resid,
-                               "speedup_vs_full": round(ms_step / ms_eo, 3)}}
+                               "speedup_vs_full": round(ms_step / ms_eo, 3)},
+               "even_odd_cg_mixed_f32": {"ms": round(ms_mx, 2), "cg_iters": st_mx.inner_iters,
+                                         "passes": st_mx.outer_iters, "true_rel_resid": st_mx.true_rel_resid,
+                                         "speedup_vs_full": round(ms_step / ms_mx, 3),
+                                         "speedup_vs_even_odd_f64": round(ms_eo / ms_mx, 3)}}
     log(f"domain-wall solves: {compare}")
     del b, x, xe
     torch.cuda.empty_cache()

@@ -367,10 +367,14 @@ int lqcd_dwf_solve(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, const double* b, d
  * are set to zero. ESINGULAR if M5op is singular; otherwise as lqcd_dwf_apply. */
 int lqcd_dwf_apply_schur(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, int dag, int prec, const double* in, double* out,
                          int on_device);
-/* Solve D x = b through S_ee x_e = b_e - Dhop_eo M5op^-1 b_o, solved by FP64 CG
+/* Solve D x = b through S_ee x_e = b_e - Dhop_eo M5op^-1 b_o, solved by CG
  * on its normal equations, and x_o = M5op^-1 (b_o - Dhop_oe x_e), restarted
  * from the true residual until ||b - D x|| / ||b|| <= prm->tol. Parameters
- * and stats as lqcd_dwf_solve. */
+ * and stats as lqcd_dwf_solve, and prm->inner_prec: LQCD_F64, CG in FP64;
+ * LQCD_F32, defect correction in the manner of the paper's mixed-precision
+ * solver (Sec. 3): each pass solves the normal equations of the FP64 residual
+ * by FP32 CG until its iterated residual has dropped by prm->inner_tol (1e-6
+ * when 0) and adds the correction to x in FP64; LQCD_F16: EINVAL. */
 int lqcd_dwf_solve_eo(lqcd_ctx* ctx, const lqcd_dwf_params* dwf, const double* b, double* x,
                       const lqcd_solve_params* prm, lqcd_solve_stats* stats);
 

@@ -695,6 +695,8 @@ int lqcd_dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params* d, const double* b, do
   lqcd_solve_params prm;
   if (prm_in) prm = *prm_in;
   else lqcd_default_params(&prm);
+  if (prm.inner_prec != LQCD_F64 && prm.inner_prec != LQCD_F32)
+    return set_error(LQCD_EINVAL, "domain-wall even-odd solve: inner precision must be F64 or F32");
   if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
   const size_t cbytes = full_sites(c) * 192 * (size_t)d->Ls;
   const size_t fb = dwf_field_bytes(0, c->g.vh, d->Ls);

@@ -499,58 +499,91 @@ __global__ void __launch_bounds__(256) k_dwf_export(Geom g, int Ls, size_t hb, c
   for (int k = 0; k < 12; ++k) dst[k] = make_double2((double)v[k].r, (double)v[k].i);
 }
 
-// FP64 flat fields: out = a + cb b
+// Flat fields of precision P (the 5-d sites in storage order): out = a + cb b
+template <int P>
 __global__ void __launch_bounds__(256) k_flat_axpy(void* out, const void* a, const void* b, double cb, size_t n) {
+  using T = typename IO<P>::T;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  cx<double> x[12], y[12];
-  IO<0>::load_spinor(a, i, x);
-  IO<0>::load_spinor(b, i, y);
+  cx<T> x[12], y[12];
+  IO<P>::load_spinor(a, i, x);
+  IO<P>::load_spinor(b, i, y);
+  const T c = (T)cb;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) x[k] = x[k] + cb * y[k];
-  IO<0>::store_spinor(out, i, x);
+  for (int k = 0; k < 12; ++k) x[k] = x[k] + c * y[k];
+  IO<P>::store_spinor(out, i, x);
 }
 
 // The CG update in one pass: x += alpha p, r -= alpha q, and the
-// per-workgroup partial sums of |r|^2 (slot 1 of each pair, as k_flat_dot)
+// per-workgroup partial sums of |r|^2 in FP64 (slot 1 of each pair, as k_flat_dot)
+template <int P>
 __global__ void __launch_bounds__(256) k_flat_xr(void* x, const void* p, void* r, const void* q, double alpha,
                                                  double* partials, size_t n) {
+  using T = typename IO<P>::T;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (i < n) {
-    cx<double> a[12], b[12];
-    IO<0>::load_spinor(x, i, a);
-    IO<0>::load_spinor(p, i, b);
+    const T al = (T)alpha, mal = (T)(-alpha);
+    cx<T> a[12], b[12];
+    IO<P>::load_spinor(x, i, a);
+    IO<P>::load_spinor(p, i, b);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) a[k] = a[k] + alpha * b[k];
-    IO<0>::store_spinor(x, i, a);
-    IO<0>::load_spinor(r, i, a);
-    IO<0>::load_spinor(q, i, b);
+    for (int k = 0; k < 12; ++k) a[k] = a[k] + al * b[k];
+    IO<P>::store_spinor(x, i, a);
+    IO<P>::load_spinor(r, i, a);
+    IO<P>::load_spinor(q, i, b);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      a[k] = a[k] + (-alpha) * b[k];
-      v[1] += a[k].r * a[k].r + a[k].i * a[k].i;
+      a[k] = a[k] + mal * b[k];
+      v[1] += (double)a[k].r * (double)a[k].r + (double)a[k].i * (double)a[k].i;
     }
-    IO<0>::store_spinor(r, i, a);
+    IO<P>::store_spinor(r, i, a);
   }
   block_reduce<2>(v, partials + (size_t)blockIdx.x * 2);
 }
 
-// per-workgroup partial sums of Re <a, b> and <b, b>
+// per-workgroup partial sums of Re <a, b> and <b, b> (FP64 sums)
+template <int P>
 __global__ void __launch_bounds__(256) k_flat_dot(const void* a, const void* b, double* partials, size_t n) {
+  using T = typename IO<P>::T;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (i < n) {
-    cx<double> x[12], y[12];
-    IO<0>::load_spinor(a, i, x);
-    IO<0>::load_spinor(b, i, y);
+    cx<T> x[12], y[12];
+    IO<P>::load_spinor(a, i, x);
+    IO<P>::load_spinor(b, i, y);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      v[0] += x[k].r * y[k].r + x[k].i * y[k].i;
-      v[1] += y[k].r * y[k].r + y[k].i * y[k].i;
+      v[0] += (double)x[k].r * (double)y[k].r + (double)x[k].i * (double)y[k].i;
+      v[1] += (double)y[k].r * (double)y[k].r + (double)y[k].i * (double)y[k].i;
     }
   }
   block_reduce<2>(v, partials + (size_t)blockIdx.x * 2);
+}
+
+// FP64 flat field rounded to FP32
+__global__ void __launch_bounds__(256) k_flat_down(const void* in64, void* out32, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cx<double> a[12];
+  cx<float> b[12];
+  IO<0>::load_spinor(in64, i, a);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) b[k] = {(float)a[k].r, (float)a[k].i};
+  IO<1>::store_spinor(out32, i, b);
+}
+
+// x (FP64) += e (FP32)
+__global__ void __launch_bounds__(256) k_flat_accum_up(void* x64, const void* e32, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cx<double> a[12];
+  cx<float> b[12];
+  IO<0>::load_spinor(x64, i, a);
+  IO<1>::load_spinor(e32, i, b);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a[k] = a[k] + cx<double>{(double)b[k].r, (double)b[k].i};
+  IO<0>::store_spinor(x64, i, a);
 }
 
 size_t half_bytes(int prec, size_t vh, int Ls) { return spinor_bytes(prec, vh * (size_t)Ls); }
@@ -656,28 +689,45 @@ struct DWork {
   }
 };
 
-int axpy(lqcd_ctx* c, size_t n, void* out, const void* a, const void* b, double cb) {
-  hipLaunchKernelGGL(k_flat_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, out, a, b, cb, n);
+// The flat vector operations on n 5-d sites of precision prec (0 FP64, 1 FP32)
+int axpy(lqcd_ctx* c, size_t n, void* out, const void* a, const void* b, double cb, int prec = 0) {
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (prec == 0) hipLaunchKernelGGL(k_flat_axpy<0>, grid, dim3(256), 0, c->stream, out, a, b, cb, n);
+  else hipLaunchKernelGGL(k_flat_axpy<1>, grid, dim3(256), 0, c->stream, out, a, b, cb, n);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }
 
 int sum_partials_host(lqcd_ctx* c, DWork& w, size_t n, double* ab, double* bb);
 
-int dot(lqcd_ctx* c, DWork& w, size_t n, const void* a, const void* b, double* ab, double* bb) {
+int dot(lqcd_ctx* c, DWork& w, size_t n, const void* a, const void* b, double* ab, double* bb, int prec = 0) {
   const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(k_flat_dot, dim3(nb), dim3(256), 0, c->stream, a, b, w.partials, n);
+  if (prec == 0) hipLaunchKernelGGL(k_flat_dot<0>, dim3(nb), dim3(256), 0, c->stream, a, b, w.partials, n);
+  else hipLaunchKernelGGL(k_flat_dot<1>, dim3(nb), dim3(256), 0, c->stream, a, b, w.partials, n);
   LQ_HIP(hipGetLastError());
   return sum_partials_host(c, w, n, ab, bb);
 }
 
 // x += alpha p, r -= alpha q, *rr = |r|^2 (after the update)
 int xr_update(lqcd_ctx* c, DWork& w, size_t n, void* x, const void* p, void* r, const void* q, double alpha,
-              double* rr) {
+              double* rr, int prec = 0) {
   const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(k_flat_xr, dim3(nb), dim3(256), 0, c->stream, x, p, r, q, alpha, w.partials, n);
+  if (prec == 0) hipLaunchKernelGGL(k_flat_xr<0>, dim3(nb), dim3(256), 0, c->stream, x, p, r, q, alpha, w.partials, n);
+  else hipLaunchKernelGGL(k_flat_xr<1>, dim3(nb), dim3(256), 0, c->stream, x, p, r, q, alpha, w.partials, n);
   LQ_HIP(hipGetLastError());
   return sum_partials_host(c, w, n, nullptr, rr);
+}
+
+int flat_down(lqcd_ctx* c, size_t n, const void* in64, void* out32) {
+  hipLaunchKernelGGL(k_flat_down, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, in64, out32, n);
+  LQ_HIP(hipGetLastError());
+  return LQCD_OK;
+}
+
+int flat_accum_up(lqcd_ctx* c, size_t n, void* x64, const void* e32) {
+  hipLaunchKernelGGL(k_flat_accum_up, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, x64, e32, n);
+  LQ_HIP(hipGetLastError());
+  return LQCD_OK;
 }
 
 // the sums of the (Re <a, b>, <b, b>) partials of the last reduction, on the host
@@ -984,8 +1034,20 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
   const size_t nh = padded_sites((size_t)c->g.vh * d.Ls), nf = 2 * nh;
   void *bp, *r, *pv, *q, *sx, *tA, *tB, *res;
   for (void** f : {&bp, &r, &pv, &q, &sx, &tA, &tB, &res}) LQ_TRY(w.alloc(c, bytes, f));
+  // mixed precision: the inner CG in FP32 on its own operator context and fields
+  const bool mixed = prm.inner_prec == LQCD_F32;
+  const double delta = prm.inner_tol > 0.0 && prm.inner_tol < 1.0 ? prm.inner_tol : 1e-6;
+  EoCtx e32{};
+  void *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *sx32 = nullptr, *tA32 = nullptr, *tB32 = nullptr,
+       *e32f = nullptr;
+  if (mixed) {
+    LQ_TRY(eo_setup(c, 1, d, m.p, e32));
+    const size_t bytes32 = dwf_field_bytes(1, c->g.vh, d.Ls);
+    for (void** f : {&r32, &p32, &q32, &sx32, &tA32, &tB32, &e32f}) LQ_TRY(w.alloc(c, bytes32, f));
+  }
   // pairs for the flat reductions (one per 256 sites) and for the norm of S p (one per operator workgroup)
-  LQ_HIP(hipMalloc(&w.partials, std::max((size_t)(nf + 255) / 256, (size_t)e.grid.x) * 2 * sizeof(double)));
+  const size_t npairs = std::max({(size_t)(nf + 255) / 256, (size_t)e.grid.x, mixed ? (size_t)e32.grid.x : 0});
+  LQ_HIP(hipMalloc(&w.partials, npairs * 2 * sizeof(double)));
   auto ev = [](void* f) { return f; };  // even half = start of the field
   double bb = 0.0;
   LQ_TRY(dot(c, w, nf, b, b, nullptr, &bb));
@@ -1009,6 +1071,11 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
     LQ_TRY(e.schur(0, in, sx, tA, tB, w.partials));
     LQ_TRY(e.schur(1, sx, out, tA, tB));
     return sum_partials_host(c, w, (size_t)e.grid.x * 256, nullptr, sn);
+  };
+  auto normal32 = [&](void* in, void* out, double* sn) -> int {  // the same in FP32
+    LQ_TRY(e32.schur(0, in, sx32, tA32, tB32, w.partials));
+    LQ_TRY(e32.schur(1, sx32, out, tA32, tB32));
+    return sum_partials_host(c, w, (size_t)e32.grid.x * 256, nullptr, sn);
   };
   for (;;) {
     // x_o from x_e, then the true residual with the full operator
@@ -1038,6 +1105,33 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
     LQ_TRY(e.schur(1, res, r, tA, tB));
     double rr = 0.0;
     LQ_TRY(dot(c, w, nh, ev(r), ev(r), nullptr, &rr));
+    if (mixed) {
+      // defect correction: S^dag S e = r by CG in FP32 from e = 0 until the
+      // iterated residual has dropped by delta (or reached the normal
+      // target), then x_e += e in FP64 and the next pass starts from the
+      // true residual
+      LQ_TRY(flat_down(c, nh, ev(r), ev(r32)));
+      LQ_HIP(hipMemsetAsync(e32f, 0, half_bytes(1, c->g.vh, d.Ls), c->stream));
+      LQ_TRY(axpy(c, nh, ev(p32), ev(r32), ev(r32), 0.0, 1));
+      double rr32 = 0.0;
+      LQ_TRY(dot(c, w, nh, ev(r32), ev(r32), nullptr, &rr32, 1));
+      const double tgt32 = std::max(delta * std::sqrt(rr32), target);
+      while (iters < prm.max_iter) {
+        double pq = 0.0;
+        LQ_TRY(normal32(p32, q32, &pq));
+        if (!(pq > 0.0)) break;
+        const double alpha = rr32 / pq;
+        double rn = 0.0;
+        LQ_TRY(xr_update(c, w, nh, ev(e32f), ev(p32), ev(r32), ev(q32), alpha, &rn, 1));
+        ++iters;
+        if (std::sqrt(rn) <= tgt32) break;
+        LQ_TRY(axpy(c, nh, ev(p32), ev(r32), ev(p32), rn / rr32, 1));
+        rr32 = rn;
+      }
+      LQ_TRY(flat_accum_up(c, nh, ev(x), ev(e32f)));
+      target *= 0.5;
+      continue;
+    }
     LQ_TRY(axpy(c, nh, ev(pv), ev(r), ev(r), 0.0));
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
     while (iters < prm.max_iter) {

@@ -521,14 +521,16 @@ class Lattice:
         return out
 
     def dwf_solve_eo(self, Ls, M5, mf, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True, b5=1.0,
-                     c5=0.0) -> Stats:
-        """Moebius domain-wall D x = b through the even-odd Schur complement and FP64 CG."""
+                     c5=0.0, inner_prec=F64, inner_tol=0.0) -> Stats:
+        """Moebius domain-wall D x = b through the even-odd Schur complement and CG
+        (FP64, or FP32 inner solves under FP64 defect correction with inner_prec=F32)."""
         prm = default_params()
         pb, db = _ptr(b)
         px, dx = _ptr(x)
         if db != dx:
             raise ValueError("b and x must both be host or both be device")
         prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
+        prm.inner_prec, prm.inner_tol = int(inner_prec), float(inner_tol)
         d = dwf_params(Ls, M5, mf, b5, c5)
         st = SolveStats()
         status = self._call(self.lib.lqcd_dwf_solve_eo, self.handle, C.byref(d), pb, px, C.byref(prm), C.byref(st))

@@ -2,7 +2,7 @@
 adjoint and the normal-equation CG against the oracle (oracle/dwf.py),
 through the C ABI. Tolerances:
 rel-L2 1e-13 (FP64) and 1e-5 (FP32) per application; solves to a true FP64
-residual of 1e-10."""
+residual of 1e-10 (also with FP32 inner CG)."""
 
 import numpy as np
 import pytest
@@ -10,6 +10,7 @@ import pytest
 import fieldgen as fg
 from gpuutil import from_dev, lattice, to_dev
 from oracle import dirac, dwf
+from paper_2303_05883_amd import lqcd
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +136,39 @@ def test_dwf_solve_eo_matches_oracle(b5, c5):
     # the even-odd system needs fewer iterations than the full normal equations
     st_full = lat.dwf_solve(Ls, 1.8, 0.1, to_dev(b), to_dev(np.zeros_like(b)), tol=1e-10, b5=b5, c5=c5)
     assert st.inner_iters < st_full.inner_iters, (st, st_full)
+
+
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+@pytest.mark.parametrize("inner_tol", [0.0, 1e-3])
+def test_dwf_solve_eo_mixed_matches_oracle(b5, c5, inner_tol):
+    """FP32 inner CG under FP64 defect correction reaches the FP64 tolerance:
+    the oracle's residual of the GPU's x and the oracle's solution agree as
+    for the FP64 solve."""
+    dims, Ls = (4, 4, 4, 8), 6
+    U = fg.gauge_field(dims, 125, "smooth", 0.3)
+    b = field5(dims, Ls, 126)
+    op = dwf.DomainWall(U, 1.8, 0.1, Ls, -1, b5, c5)
+    lat = lattice(dims, U, 0.12, 0.0)
+    x = to_dev(np.zeros_like(b))
+    st = lat.dwf_solve_eo(Ls, 1.8, 0.1, to_dev(b), x, tol=1e-10, b5=b5, c5=c5, inner_prec=lqcd.F32,
+                          inner_tol=inner_tol)
+    xh = from_dev(x)
+    r = np.linalg.norm(b - op.D(xh)) / np.linalg.norm(b)
+    assert st.true_rel_resid <= 1e-10 and r <= 1e-10, (st, r)
+    assert st.outer_iters >= 2, st  # FP32 alone cannot reach 1e-10: at least one correction pass
+    xo, info = dwf.EvenOdd(op).solve(b, tol=1e-12)
+    assert info.converged
+    assert dirac.rel_l2(xh, xo) <= 1e-8
+
+
+def test_dwf_solve_eo_rejects_fp16_inner():
+    dims, Ls = (4, 4, 4, 4), 4
+    U = fg.gauge_field(dims, 127, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    b = to_dev(field5(dims, Ls, 128))
+    st = lat.dwf_solve_eo(Ls, 1.8, 0.1, b, to_dev(np.zeros(b.shape, dtype=np.complex128)), inner_prec=lqcd.F16,
+                          raise_on_fail=False)
+    assert st.status == lqcd.EINVAL
 
 
 def test_dwf_adjoint_at_benchmark_size():
