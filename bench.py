@@ -26,7 +26,8 @@ Other workloads (not the headline line; same JSON shape):
   --workload sap     the clover workload solved on the full lattice by FP64
                      flexible BiCGStab with the FP32 SAP preconditioner
   --workload staggered  32^3x64 staggered operator, mass 0.05, FP64 CG on the
-                     even-odd normal system
+                     even-odd normal system (timed steps), then the same with
+                     FP32 inner CG under FP64 defect correction
   --workload mg      the clover workload with the two-level multigrid
                      preconditioner
   --workload dwf     64x32x16x8 x Ls 8 Moebius domain wall: FP64 CG on the
@@ -865,6 +866,24 @@ def run_staggered(a, torch, lqcd):
     value = STAG_FLOPS * vh * sum(stag_hops(s) for s in stats) / elapsed / 1e9
     ms_step = 1000 * elapsed / a.steps
     log(f"timed {a.steps} staggered CG solves: {ms_step:.1f} ms each, {stats[-1]}")
+    # the same with FP32 inner CG under FP64 defect correction (inner tolerance 1e-6)
+    xm = torch.zeros_like(b)
+    lat.stag_solve(STAG_MASS, b, xm, inner_prec=lqcd.F32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st_mx = lat.stag_solve(STAG_MASS, b, xm, inner_prec=lqcd.F32)
+    torch.cuda.synchronize()
+    ms_mx = 1000 * (time.perf_counter() - t1)
+    if not st_mx.true_rel_resid <= 1e-10:
+        log(f"mixed true residual {st_mx.true_rel_resid} above 1e-10")
+        sys.exit(1)
+    compare = {"f64_cg": {"ms": round(ms_step, 2), "cg_iters": stats[-1].inner_iters,
+                          "true_rel_resid": stats[-1].true_rel_resid},
+               "mixed_f32_cg": {"ms": round(ms_mx, 2), "cg_iters": st_mx.inner_iters, "passes": st_mx.outer_iters,
+                                "true_rel_resid": st_mx.true_rel_resid,
+                                "speedup_vs_f64": round(ms_step / ms_mx, 3)}}
+    log(f"staggered solves: {compare}")
+    del xm
     hop = {}
     for p, name in ((lqcd.F64, "f64"), (lqcd.F32, "f32")):
         ms = time_stag_hop(torch, lat, p)
@@ -879,7 +898,7 @@ def run_staggered(a, torch, lqcd):
                           "antiperiodic t, FP64 CG on the even-odd normal system to true residual 1e-10",
               "lattice": list(dims), "mass": STAG_MASS, "step": "one whole solve",
               "cg_iters_per_solve": stats[-1].inner_iters, "parallelism": "single GPU"}
-    return value, ms_step, config, roof, hop, None, None, lqcd.F64
+    return value, ms_step, config, roof, hop, compare, None, lqcd.F64
 
 
 DWF = dict(dims=(64, 32, 16, 8), Ls=8, M5=1.8, mf=0.05, b5=1.5, c5=0.5, eps=0.3, seed=1007)

@@ -319,12 +319,17 @@ typedef enum {
  * set_gauge. */
 int lqcd_stag_apply(lqcd_ctx* ctx, int op, int prec, double mass, const double* in, double* out, int on_device);
 
-/* Solve D x = b (mass > 0) by FP64 CG on the even-odd normal system
+/* Solve D x = b (mass > 0) by CG on the even-odd normal system
  * (m^2 + H_eo H_eo^dag on the even sites, Hermitian positive definite), x_o
  * rebuilt as (b_o - H_oe x_e) / m, until the true residual
  * ||b - D x|| / ||b|| <= prm->tol. From prm: tol, max_iter (CG iterations),
- * max_outer (CG restarts from the true residual), on_device. stats:
- * inner_iters = CG iterations, outer_iters = passes, true_rel_resid, timings. */
+ * max_outer (CG restarts from the true residual), on_device, and inner_prec:
+ * LQCD_F64, CG in FP64; LQCD_F32, defect correction in the manner of the
+ * paper's mixed-precision solver (Sec. 3): each pass solves for the FP64
+ * residual by FP32 CG until its iterated residual has dropped by
+ * prm->inner_tol (1e-6 when 0) and adds the correction in FP64; LQCD_F16:
+ * EINVAL. stats: inner_iters = CG iterations, outer_iters = passes,
+ * true_rel_resid, timings. */
 int lqcd_stag_solve(lqcd_ctx* ctx, double mass, const double* b, double* x, const lqcd_solve_params* prm,
                     lqcd_solve_stats* stats);
 

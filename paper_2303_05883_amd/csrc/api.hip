@@ -529,6 +529,8 @@ int lqcd_stag_solve(lqcd_ctx* c, double mass, const double* b, double* x, const 
   lqcd_solve_params prm;
   if (prm_in) prm = *prm_in;
   else lqcd_default_params(&prm);
+  if (prm.inner_prec != LQCD_F64 && prm.inner_prec != LQCD_F32)
+    return set_error(LQCD_EINVAL, "staggered solve: inner precision must be F64 or F32");
   if (!c->have_gauge) return set_error(LQCD_ESTATE, "set_gauge must come first");
   LQ_TRY(ensure_canon(c));
   const size_t bytes = full_sites(c) * 48;

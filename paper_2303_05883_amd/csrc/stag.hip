@@ -9,6 +9,7 @@
 //
 // Field layout: 3 complex per site in 64-site blocks, word k = colour k
 // (FP64 double2, FP32 float2). The links are the context's 12-real links.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -194,63 +195,95 @@ __global__ void __launch_bounds__(SBS) k_stag_export(Geom g, int p, const void* 
   }
 }
 
-// FP64: out = ca a + cb b (b may be null)
+// Fields of precision P: out = ca a + cb b (b may be null)
+template <int P>
 __global__ void __launch_bounds__(SBS) k_stag_axpby(void* out, const void* a, double ca, const void* b, double cb,
                                                     size_t vh) {
+  using T = typename SIO<P>::T;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= vh) return;
-  cx<double> va[3], w[3];
-  SIO<0>::load(a, i, va);
+  cx<T> va[3], w[3];
+  SIO<P>::load(a, i, va);
+  const T fa = (T)ca, fb = (T)cb;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) w[k] = ca * va[k];
+  for (int k = 0; k < 3; ++k) w[k] = fa * va[k];
   if (b) {
-    SIO<0>::load(b, i, va);
+    SIO<P>::load(b, i, va);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) w[k] = w[k] + cb * va[k];
+    for (int k = 0; k < 3; ++k) w[k] = w[k] + fb * va[k];
   }
-  SIO<0>::store(out, i, w);
+  SIO<P>::store(out, i, w);
 }
 
-// FP64: per-workgroup partial sums of Re <a, b> and <b, b>
+// per-workgroup partial sums (FP64) of Re <a, b> and <b, b>
+template <int P>
 __global__ void __launch_bounds__(SBS) k_stag_dot(const void* a, const void* b, double* partials, size_t vh) {
+  using T = typename SIO<P>::T;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (i < vh) {
-    cx<double> x[3], y[3];
-    SIO<0>::load(a, i, x);
-    SIO<0>::load(b, i, y);
+    cx<T> x[3], y[3];
+    SIO<P>::load(a, i, x);
+    SIO<P>::load(b, i, y);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      v[0] += x[k].r * y[k].r + x[k].i * y[k].i;
-      v[1] += y[k].r * y[k].r + y[k].i * y[k].i;
+      v[0] += (double)x[k].r * (double)y[k].r + (double)x[k].i * (double)y[k].i;
+      v[1] += (double)y[k].r * (double)y[k].r + (double)y[k].i * (double)y[k].i;
     }
   }
   block_reduce<2>(v, partials + (size_t)blockIdx.x * 2);
 }
 
-// FP64 CG update in one pass: x += alpha p, r -= alpha q, per-workgroup
-// pairs (0, |r|^2) of the updated r
+// CG update in one pass: x += alpha p, r -= alpha q, per-workgroup pairs
+// (0, |r|^2) of the updated r (FP64 sums)
+template <int P>
 __global__ void __launch_bounds__(SBS) k_stag_xr(void* x, const void* p, void* r, const void* q, double alpha,
                                                  double* partials, size_t vh) {
+  using T = typename SIO<P>::T;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (i < vh) {
-    cx<double> a[3], b[3];
-    SIO<0>::load(x, i, a);
-    SIO<0>::load(p, i, b);
+    const T al = (T)alpha, mal = (T)(-alpha);
+    cx<T> a[3], b[3];
+    SIO<P>::load(x, i, a);
+    SIO<P>::load(p, i, b);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a[k] = a[k] + alpha * b[k];
-    SIO<0>::store(x, i, a);
-    SIO<0>::load(r, i, a);
-    SIO<0>::load(q, i, b);
+    for (int k = 0; k < 3; ++k) a[k] = a[k] + al * b[k];
+    SIO<P>::store(x, i, a);
+    SIO<P>::load(r, i, a);
+    SIO<P>::load(q, i, b);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      a[k] = a[k] + (-alpha) * b[k];
-      v[1] += a[k].r * a[k].r + a[k].i * a[k].i;
+      a[k] = a[k] + mal * b[k];
+      v[1] += (double)a[k].r * (double)a[k].r + (double)a[k].i * (double)a[k].i;
     }
-    SIO<0>::store(r, i, a);
+    SIO<P>::store(r, i, a);
   }
   block_reduce<2>(v, partials + (size_t)blockIdx.x * 2);
+}
+
+// FP64 field rounded to FP32, and x (FP64) += e (FP32)
+__global__ void __launch_bounds__(SBS) k_stag_down(const void* in64, void* out32, size_t vh) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vh) return;
+  cx<double> a[3];
+  cx<float> b[3];
+  SIO<0>::load(in64, i, a);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) b[k] = {(float)a[k].r, (float)a[k].i};
+  SIO<1>::store(out32, i, b);
+}
+
+__global__ void __launch_bounds__(SBS) k_stag_accum_up(void* x64, const void* e32, size_t vh) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vh) return;
+  cx<double> a[3];
+  cx<float> b[3];
+  SIO<0>::load(x64, i, a);
+  SIO<1>::load(e32, i, b);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a[k] = a[k] + cx<double>{(double)b[k].r, (double)b[k].i};
+  SIO<0>::store(x64, i, a);
 }
 
 int grid_for_sites(size_t n) { return (int)((n + SBS - 1) / SBS); }
@@ -316,9 +349,12 @@ struct SWork {
   }
 };
 
-int axpby(lqcd_ctx* c, void* out, const void* a, double ca, const void* b = nullptr, double cb = 0.0) {
-  hipLaunchKernelGGL(k_stag_axpby, dim3(grid_for_sites(c->g.vh)), dim3(SBS), 0, c->stream, out, a, ca, b, cb,
-                     (size_t)c->g.vh);
+// The vector operations on half fields of precision prec (0 FP64, 1 FP32)
+int axpby(lqcd_ctx* c, void* out, const void* a, double ca, const void* b = nullptr, double cb = 0.0, int prec = 0) {
+  const dim3 grid(grid_for_sites(c->g.vh));
+  const size_t vh = c->g.vh;
+  if (prec == 0) hipLaunchKernelGGL(k_stag_axpby<0>, grid, dim3(SBS), 0, c->stream, out, a, ca, b, cb, vh);
+  else hipLaunchKernelGGL(k_stag_axpby<1>, grid, dim3(SBS), 0, c->stream, out, a, ca, b, cb, vh);
   LQ_HIP(hipGetLastError());
   return LQCD_OK;
 }
@@ -341,19 +377,38 @@ int sum_pairs(lqcd_ctx* c, SWork& w, double* ab, double* bb) {
 }
 
 // Re <a, b> and <b, b>
-int dot(lqcd_ctx* c, SWork& w, const void* a, const void* b, double* ab, double* bb) {
+int dot(lqcd_ctx* c, SWork& w, const void* a, const void* b, double* ab, double* bb, int prec = 0) {
   const int nb = grid_for_sites(c->g.vh);
-  hipLaunchKernelGGL(k_stag_dot, dim3(nb), dim3(SBS), 0, c->stream, a, b, w.partials, (size_t)c->g.vh);
+  const size_t vh = c->g.vh;
+  if (prec == 0) hipLaunchKernelGGL(k_stag_dot<0>, dim3(nb), dim3(SBS), 0, c->stream, a, b, w.partials, vh);
+  else hipLaunchKernelGGL(k_stag_dot<1>, dim3(nb), dim3(SBS), 0, c->stream, a, b, w.partials, vh);
   LQ_HIP(hipGetLastError());
   return sum_pairs(c, w, ab, bb);
 }
 
 // x += alpha p, r -= alpha q, *rr = |r|^2 after the update
-int xr_update(lqcd_ctx* c, SWork& w, void* x, const void* p, void* r, const void* q, double alpha, double* rr) {
+int xr_update(lqcd_ctx* c, SWork& w, void* x, const void* p, void* r, const void* q, double alpha, double* rr,
+              int prec = 0) {
   const int nb = grid_for_sites(c->g.vh);
-  hipLaunchKernelGGL(k_stag_xr, dim3(nb), dim3(SBS), 0, c->stream, x, p, r, q, alpha, w.partials, (size_t)c->g.vh);
+  const size_t vh = c->g.vh;
+  if (prec == 0) hipLaunchKernelGGL(k_stag_xr<0>, dim3(nb), dim3(SBS), 0, c->stream, x, p, r, q, alpha, w.partials, vh);
+  else hipLaunchKernelGGL(k_stag_xr<1>, dim3(nb), dim3(SBS), 0, c->stream, x, p, r, q, alpha, w.partials, vh);
   LQ_HIP(hipGetLastError());
   return sum_pairs(c, w, nullptr, rr);
+}
+
+int down(lqcd_ctx* c, const void* in64, void* out32) {
+  hipLaunchKernelGGL(k_stag_down, dim3(grid_for_sites(c->g.vh)), dim3(SBS), 0, c->stream, in64, out32,
+                     (size_t)c->g.vh);
+  LQ_HIP(hipGetLastError());
+  return LQCD_OK;
+}
+
+int accum_up(lqcd_ctx* c, void* x64, const void* e32) {
+  hipLaunchKernelGGL(k_stag_accum_up, dim3(grid_for_sites(c->g.vh)), dim3(SBS), 0, c->stream, x64, e32,
+                     (size_t)c->g.vh);
+  LQ_HIP(hipGetLastError());
+  return LQCD_OK;
 }
 
 }  // namespace
@@ -371,6 +426,12 @@ int stag_solve(lqcd_ctx* c, double mass, const lqcd_solve_params& prm, const voi
   const size_t bytes = stag_field_bytes(0, c->g.vh);
   void *be2, *r, *p, *q, *t;
   for (void** f : {&be2, &r, &p, &q, &t}) LQ_TRY(w.alloc(bytes, f));
+  // mixed precision: the inner CG in FP32 on its own fields
+  const bool mixed = prm.inner_prec == LQCD_F32;
+  const double delta = prm.inner_tol > 0.0 && prm.inner_tol < 1.0 ? prm.inner_tol : 1e-6;
+  void *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *t32 = nullptr, *e32 = nullptr;
+  if (mixed)
+    for (void** f : {&r32, &p32, &q32, &t32, &e32}) LQ_TRY(w.alloc(stag_field_bytes(1, c->g.vh), f));
   LQ_HIP(hipMalloc(&w.partials, (size_t)grid_for_sites(c->g.vh) * 2 * sizeof(double)));
   // full-lattice |b|
   double bb_e = 0.0, bb_o = 0.0;
@@ -421,6 +482,33 @@ int stag_solve(lqcd_ctx* c, double mass, const lqcd_solve_params& prm, const voi
       break;
     }
     ++restarts;
+    if (mixed) {
+      // defect correction: (m^2 - H_eo H_oe) e = r by CG in FP32 from e = 0
+      // until the iterated residual has dropped by delta (or reached the
+      // target), then x_e += e in FP64 and the next pass starts from the true
+      // residual
+      LQ_TRY(down(c, r, r32));
+      LQ_TRY(axpby(c, e32, r32, 0.0, nullptr, 0.0, 1));
+      LQ_TRY(axpby(c, p32, r32, 1.0, nullptr, 0.0, 1));
+      double rr32 = 0.0;
+      LQ_TRY(dot(c, w, r32, r32, nullptr, &rr32, 1));
+      const double tgt32 = std::max(delta * std::sqrt(rr32), target);
+      while (iters < prm.max_iter) {
+        LQ_TRY(stag_schur(c, 1, mass, p32, t32, q32, w.partials));
+        double pq = 0.0;
+        LQ_TRY(sum_pairs(c, w, &pq, nullptr));
+        if (!(pq > 0.0)) break;
+        const double alpha = rr32 / pq;
+        double rn = 0.0;
+        LQ_TRY(xr_update(c, w, e32, p32, r32, q32, alpha, &rn, 1));
+        ++iters;
+        if (std::sqrt(rn) <= tgt32) break;
+        LQ_TRY(axpby(c, p32, r32, 1.0, p32, rn / rr32, 1));
+        rr32 = rn;
+      }
+      LQ_TRY(accum_up(c, x_e, e32));
+      continue;
+    }
     LQ_TRY(axpby(c, p, r, 1.0));
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
     while (iters < prm.max_iter) {

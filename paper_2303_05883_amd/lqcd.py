@@ -589,14 +589,17 @@ class Lattice:
         finally:
             self._exit()
 
-    def stag_solve(self, mass, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True) -> Stats:
-        """Staggered D x = b by FP64 CG on the even-odd normal system."""
+    def stag_solve(self, mass, b, x, tol=1e-10, max_iter=100000, max_outer=20, raise_on_fail=True,
+                   inner_prec=F64, inner_tol=0.0) -> Stats:
+        """Staggered D x = b by CG on the even-odd normal system (FP64, or FP32
+        inner solves under FP64 defect correction with inner_prec=F32)."""
         prm = default_params()
         pb, db = _ptr(b)
         px, dx = _ptr(x)
         if db != dx:
             raise ValueError("b and x must both be host or both be device")
         prm.tol, prm.max_iter, prm.max_outer, prm.on_device = float(tol), int(max_iter), int(max_outer), db
+        prm.inner_prec, prm.inner_tol = int(inner_prec), float(inner_tol)
         st = SolveStats()
         status = self._call(self.lib.lqcd_stag_solve, self.handle, float(mass), pb, px, C.byref(prm), C.byref(st))
         if raise_on_fail:

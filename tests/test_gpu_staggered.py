@@ -9,6 +9,7 @@ import pytest
 import fieldgen as fg
 from gpuutil import from_dev, lattice, to_dev
 from oracle import dirac, staggered
+from paper_2303_05883_amd import lqcd
 
 pytestmark = pytest.mark.gpu
 
@@ -68,6 +69,29 @@ def test_stag_solve_matches_oracle(dims, mass):
     xo, info = staggered.solve(op, b, tol=1e-11)
     assert info.converged
     assert dirac.rel_l2(xh, xo) <= 1e-8
+
+
+@pytest.mark.parametrize("dims,mass", [((4, 4, 4, 4), 0.1), ((8, 8, 8, 16), 0.05)])
+@pytest.mark.parametrize("inner_tol", [0.0, 1e-3])
+def test_stag_solve_mixed_matches_oracle(dims, mass, inner_tol):
+    """FP32 inner CG under FP64 defect correction reaches the FP64 tolerance:
+    the oracle's residual of the GPU's x and the oracle's solution agree as
+    for the FP64 solve; an FP16 inner precision is rejected."""
+    U = fg.gauge_field(dims, 88, "smooth", 0.3)
+    b = colour_field(dims, 89)
+    op = staggered.Staggered(U, mass)
+    lat = lattice(dims, U, 0.12, 0.0)
+    x = to_dev(np.zeros_like(b))
+    st = lat.stag_solve(mass, to_dev(b), x, tol=1e-10, inner_prec=lqcd.F32, inner_tol=inner_tol)
+    xh = from_dev(x)
+    r = np.linalg.norm(b - op.D(xh)) / np.linalg.norm(b)
+    assert st.true_rel_resid <= 1e-10 and r <= 1e-10, (st, r)
+    assert st.outer_iters >= 2, st  # FP32 alone cannot reach 1e-10: at least one correction pass
+    xo, info = staggered.solve(op, b, tol=1e-11)
+    assert info.converged
+    assert dirac.rel_l2(xh, xo) <= 1e-8
+    st = lat.stag_solve(mass, to_dev(b), x, inner_prec=lqcd.F16, raise_on_fail=False)
+    assert st.status == lqcd.EINVAL
 
 
 def test_stag_zero_source():
