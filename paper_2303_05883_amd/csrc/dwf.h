@@ -24,7 +24,8 @@ size_t dwf_apply_groups(const Geom& g, int prec, int Ls);
 int dwf_schur_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tA,
                     void* tB);
 // D x = b (FP64 native 5-d fields) through S_ee and CG on its normal
-// equations, x_o rebuilt, stopping on the true residual of D
+// equations (FP64, or FP32 inner CG under FP64 defect correction when
+// prm.inner_prec is F32), x_o rebuilt, stopping on the true residual of D
 int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& prm, const void* b, void* x,
                  lqcd_solve_stats& st);
 // D x = b (FP64 native 5-d fields, padding zero) by CG on D^dag D x = D^dag b

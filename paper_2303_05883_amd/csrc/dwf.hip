@@ -6,7 +6,9 @@
 // H the Wilson hopping term of hopcore.h, and
 //   D^dag = (b5 + c5 S^dag) D_W^dag + (1 - S^dag),  D_W^dag = gamma5 D_W gamma5,
 // S^dag with the projectors exchanged. Solved by CG on the normal equations
-// D^dag D x = D^dag b in FP64.
+// D^dag D x = D^dag b in FP64, or through the even-odd Schur complement by CG
+// on its normal equations, in FP64 or as FP32 inner solves under FP64 defect
+// correction.
 //
 // The fifth coordinate is an inner degree of freedom of the 4-d site (the
 // paper, Sec. 2, reports this beating a construction from the 4-d Wilson

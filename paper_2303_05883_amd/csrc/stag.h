@@ -19,7 +19,8 @@ int stag_hop(lqcd_ctx* c, int prec, int out_parity, const void* in, const void* 
 // for Re <x_e, out_e>
 int stag_schur(lqcd_ctx* c, int prec, double mass, const void* x_e, void* tmp_o, void* out_e,
                double* dot_partials = nullptr);
-// D x = b (FP64 native halves) by CG on the even-odd normal system
+// D x = b (FP64 native halves) by CG on the even-odd normal system (FP64, or
+// FP32 inner CG under FP64 defect correction when prm.inner_prec is F32)
 int stag_solve(lqcd_ctx* c, double mass, const lqcd_solve_params& prm, const void* b_e, const void* b_o, void* x_e,
                void* x_o, lqcd_solve_stats& st);
 

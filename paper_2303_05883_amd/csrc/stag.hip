@@ -5,7 +5,8 @@
 //   eta_x = 1, eta_y = (-1)^x, eta_z = (-1)^(x+y), eta_t = (-1)^(x+y+z),
 // cross-boundary t hops times the fermion boundary factor; H is anti-Hermitian,
 // so on the even sites m^2 - H_eo H_oe = m^2 + H_eo H_eo^dag is Hermitian
-// positive definite and CG solves it; x_o = (b_o - H_oe x_e) / m.
+// positive definite and CG solves it (in FP64, or as FP32 inner solves under
+// FP64 defect correction); x_o = (b_o - H_oe x_e) / m.
 //
 // Field layout: 3 complex per site in 64-site blocks, word k = colour k
 // (FP64 double2, FP32 float2). The links are the context's 12-real links.
