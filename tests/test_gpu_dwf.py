@@ -161,6 +161,21 @@ def test_dwf_solve_eo_mixed_matches_oracle(b5, c5, inner_tol):
     assert dirac.rel_l2(xh, xo) <= 1e-8
 
 
+@pytest.mark.parametrize("form", ["full", "eo_f64", "eo_f32"])
+def test_dwf_solve_zero_source(form):
+    """b = 0 gives x = 0 with no iteration, whatever x held."""
+    dims, Ls = (4, 4, 4, 4), 4
+    U = fg.gauge_field(dims, 129, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    b = np.zeros((Ls, 4, 4, 4, 4, 4, 3), dtype=np.complex128)
+    x = to_dev(np.ones_like(b))
+    if form == "full":
+        st = lat.dwf_solve(Ls, 1.8, 0.1, to_dev(b), x)
+    else:
+        st = lat.dwf_solve_eo(Ls, 1.8, 0.1, to_dev(b), x, inner_prec=lqcd.F64 if form == "eo_f64" else lqcd.F32)
+    assert st.true_rel_resid == 0.0 and st.inner_iters == 0 and np.all(from_dev(x) == 0), st
+
+
 def test_dwf_solve_eo_rejects_fp16_inner():
     dims, Ls = (4, 4, 4, 4), 4
     U = fg.gauge_field(dims, 127, "smooth", 0.3)

@@ -94,14 +94,15 @@ def test_stag_solve_mixed_matches_oracle(dims, mass, inner_tol):
     assert st.status == lqcd.EINVAL
 
 
-def test_stag_zero_source():
+@pytest.mark.parametrize("inner_prec", [0, 1])
+def test_stag_zero_source(inner_prec):
     dims = (4, 4, 4, 4)
     U = fg.gauge_field(dims, 87, "haar")
     lat = lattice(dims, U, 0.12, 0.0)
     b = np.zeros((4, 4, 4, 4, 3), dtype=np.complex128)
     x = to_dev(np.ones_like(b))
-    st = lat.stag_solve(0.1, to_dev(b), x)
-    assert st.true_rel_resid == 0.0 and np.all(from_dev(x) == 0)
+    st = lat.stag_solve(0.1, to_dev(b), x, inner_prec=inner_prec)
+    assert st.true_rel_resid == 0.0 and st.inner_iters == 0 and np.all(from_dev(x) == 0)
 
 
 def test_stag_native_hop_matches_oracle():
