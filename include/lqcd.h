@@ -120,7 +120,9 @@ typedef struct {
   double tol;           /* stop when ||b - D x|| <= tol ||b|| (full FP64 D); default 1e-10 */
   int max_iter;         /* cap on inner BiCGStab iterations over the whole solve */
   int max_outer;        /* cap on outer (defect-correction) iterations */
-  int inner_prec;       /* LQCD_F64: plain FP64 BiCGStab; F32/F16: mixed precision */
+  int inner_prec;       /* LQCD_F64: plain FP64 BiCGStab; F32/F16: mixed precision
+                           (the staggered and even-odd domain-wall CG solves take
+                           F64 or F32) */
   double inner_tol;     /* relative tolerance of each inner solve (mixed only); with
                            reliable_update, the drop of the iterated residual
                            between two reliable updates (0: 0.1) */
