@@ -255,6 +255,28 @@ def test_dwf_sampled_at_benchmark_size():
             assert dirac.rel_l2(got, want_s) <= TOL[prec], ("S_ee", dag, prec)
 
 
+def test_dwf_mixed_solve_at_benchmark_size():
+    """The even-odd solve with FP32 inner CG at the benchmarked size
+    (64x32x16x8, Ls 8, Moebius): the oracle's D applied to the GPU's x at
+    random and edge sites reproduces b there (sampled residual against the
+    sampled b), independently of the library's own residual."""
+    from oracle import sampled
+    dims, Ls, M5, mf, b5, c5 = (64, 32, 16, 8), 8, 1.8, 0.05, 1.5, 0.5
+    U = fg.gauge_field(dims, 125, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    b = field5(dims, Ls, 130)
+    x = to_dev(np.zeros_like(b))
+    st = lat.dwf_solve_eo(Ls, M5, mf, to_dev(b), x, b5=b5, c5=c5, inner_prec=lqcd.F32)
+    assert st.true_rel_resid <= 1e-10 and st.outer_iters >= 2, st
+    xh = from_dev(x)
+    del x
+    edges = np.array([[xx, yy, zz, tt] for xx in (0, 63) for yy in (0, 31) for zz in (0, 15) for tt in (0, 7)])
+    sites = np.concatenate([sampled.random_sites(dims, 48, 131), edges])
+    dx = sampled.dwf_at(U, xh, M5, mf, b5, c5, -1, sites)
+    bs = sampled.gather5(b, sites)
+    assert np.linalg.norm(bs - dx) / np.linalg.norm(bs) <= 1e-9
+
+
 def test_dwf_walks_agree(monkeypatch):
     """The four XCD walks (linear, z-slabs, y-ranges, x-ranges) only reorder
     the sites: D, D^dag and S_ee agree bit for bit on a lattice all four fit,

@@ -105,6 +105,26 @@ def test_stag_zero_source(inner_prec):
     assert st.true_rel_resid == 0.0 and st.inner_iters == 0 and np.all(from_dev(x) == 0)
 
 
+def test_stag_mixed_solve_at_benchmark_size():
+    """The FP32-inner staggered CG at the benchmarked 32^3x64 size: the
+    oracle's D applied to the GPU's x at random and edge sites reproduces b
+    there (sampled residual against the sampled b)."""
+    from oracle import sampled
+    dims, mass = (32, 32, 32, 64), 0.05
+    U = fg.gauge_field(dims, 93, "smooth", 0.3)
+    lat = lattice(dims, U, 0.12, 0.0)
+    b = colour_field(dims, 96)
+    x = to_dev(np.zeros_like(b))
+    st = lat.stag_solve(mass, to_dev(b), x, inner_prec=lqcd.F32)
+    assert st.true_rel_resid <= 1e-10 and st.outer_iters >= 2, st
+    xh = from_dev(x)
+    edges = np.array([[xx, yy, zz, tt] for xx in (0, 31) for yy in (0, 31) for zz in (0, 31) for tt in (0, 63)])
+    sites = np.concatenate([sampled.random_sites(dims, 64, 97), edges])
+    dx = sampled.stag_dirac_at(U, xh, mass, -1, sites)
+    bs = sampled.gather(b, sites)
+    assert np.linalg.norm(bs - dx) / np.linalg.norm(bs) <= 1e-9
+
+
 def test_stag_native_hop_matches_oracle():
     import torch
     dims = (4, 6, 8, 10)
