@@ -1,4 +1,4 @@
-// Solver workspaces and the even-odd solve driver (solver.hip).
+// Solver workspaces and the even-odd solve (solver.hip).
 #pragma once
 
 #include "blas.h"
