@@ -73,11 +73,11 @@ struct DwfArgs {
 //           columns fastest, then t, then z, then y: the t and z neighbours were
 //           read hw and hw lt sites earlier and the y neighbours one y step
 //           (hw lt lz sites) earlier, so the span between the first and the last
-//           read of a spinor is two y steps (2 hw lt lz sites, about 2.7 MB of
-//           traffic through the XCD's L2 at 64x32x16x8 x 8 in FP32); only the x
-//           neighbours of the two edge columns come from other XCDs (a quarter
-//           of a spinor per site at hw = 4, against half of one for the y edges
-//           of walk 2).
+//           read of a spinor is two y steps (2 hw lt lz sites, about 5.5 MB of
+//           FP64 traffic through the XCD's L2 at 64x32x16x8 x 8, against 11 MB
+//           for the z neighbours of walk 2); only the x neighbours of the two
+//           edge columns come from other XCDs (a quarter of a spinor per site
+//           at hw = 4, against half of one for the y edges of walk 2).
 // All Ls lanes of a 4-d site are in one workgroup in every walk.
 __device__ inline bool dwf_site(const DwfArgs& a, size_t& j) {
   const Geom& g = a.g;
