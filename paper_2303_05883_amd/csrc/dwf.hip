@@ -341,10 +341,12 @@ __global__ void __launch_bounds__(DWB) k_dwf_phi(DwfArgs a) {
 // corner; adjoints are transposes).
 
 // out_s = sum_s' (A_+ P_+ x + A_- P_- x)_s' [+ (C_+ P_+ y + C_- P_- y)_s'] on the
-// parity-p half of 5-d fields; mats = {A_+, A_-, C_+, C_-}, each Ls x Ls row-major
+// parity-p half of 5-d fields; mats = {A_+, A_-, C_+, C_-}, each Ls x Ls row-major.
+// With r5 (x part only), x is first replaced by r + beta x at this lane's site
+// and stored back (a CG search-direction update fused into the operator).
 template <int P>
 __global__ void __launch_bounds__(DWB) k_dwf_sop(DwfArgs a, int p, const char* x5, const char* y5,
-                                                 const double* mats) {
+                                                 const double* mats, const char* r5, double beta) {
   using T = typename IO<P>::T;
   __shared__ cx<T> lp[6][DWB], lm[6][DWB];
   const int Ls = a.Ls;
@@ -363,6 +365,14 @@ __global__ void __launch_bounds__(DWB) k_dwf_sop(DwfArgs a, int p, const char* x
     cx<T> v[12];
     if (live) {
       IO<P>::load_spinor(f + (size_t)p * a.hb, j, v);
+      if (pass == 0 && r5) {
+        cx<T> rv[12];
+        IO<P>::load_spinor(r5 + (size_t)p * a.hb, j, rv);
+        const T bt = (T)beta;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = rv[k] + bt * v[k];
+        IO<P>::store_spinor(const_cast<char*>(f) + (size_t)p * a.hb, j, v);
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < 12; ++k) v[k] = {T(0), T(0)};
@@ -924,13 +934,15 @@ struct EoCtx {
   const double* mats;
   const double* pair(int e) const { return mats + (size_t)e * 2 * d.Ls * d.Ls; }
 
-  int sop(int p, const void* x, const void* y, int e, void* out) const {
+  // r (optional): x is first replaced in place by r + beta x (x then written)
+  int sop(int p, const void* x, const void* y, int e, void* out, const void* r = nullptr, double beta = 0.0) const {
     DwfArgs b = a;
     b.out = reinterpret_cast<char*>(out);
     const char* xs = reinterpret_cast<const char*>(x);
     const char* ys = reinterpret_cast<const char*>(y);
-    if (prec == 0) hipLaunchKernelGGL(k_dwf_sop<0>, grid, block, 0, c->stream, b, p, xs, ys, pair(e));
-    else hipLaunchKernelGGL(k_dwf_sop<1>, grid, block, 0, c->stream, b, p, xs, ys, pair(e));
+    const char* rs = reinterpret_cast<const char*>(r);
+    if (prec == 0) hipLaunchKernelGGL(k_dwf_sop<0>, grid, block, 0, c->stream, b, p, xs, ys, pair(e), rs, beta);
+    else hipLaunchKernelGGL(k_dwf_sop<1>, grid, block, 0, c->stream, b, p, xs, ys, pair(e), rs, beta);
     LQ_HIP(hipGetLastError());
     return LQCD_OK;
   }
@@ -958,9 +970,12 @@ struct EoCtx {
   // Each hop is fused with the site-local operator after it (k_dwf_hopsop).
   // norm_partials (dag 0 only): the workgroups' partial sums of |out_e|^2, as
   // (0, value) pairs, one pair per workgroup of grid.
-  int schur(int dag, const void* x, void* out, void* tA, void* tB, double* norm_partials = nullptr) const {
+  // xr (dag 0 only): x_e is first replaced in place by xr_e + beta x_e, the CG
+  // search-direction update, in the first launch.
+  int schur(int dag, const void* x, void* out, void* tA, void* tB, double* norm_partials = nullptr,
+            const void* xr = nullptr, double beta = 0.0) const {
     if (!dag) {
-      LQ_TRY(sop(0, x, nullptr, EP_B, tA));                                  // B x
+      LQ_TRY(sop(0, x, nullptr, EP_B, tA, xr, beta));                        // B x
       LQ_TRY(hopsop(1, tA, nullptr, 0, EP_BMINV, tB, false));                // B M5^-1 Dhop_oe x
       return hopsop(0, tB, x, EP_M5, EP_MINUS_I, out, false, norm_partials);  // M5 x - Dhop_eo (that)
     }
@@ -1069,13 +1084,15 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
   double true_rel = 1.0, target = 0.1 * prm.tol * std::sqrt(sbb);
   // out_e = S^dag S in_e and *sn = |S in_e|^2 (= <in_e, out_e>, summed by the
   // workgroups of the operator's last launch: no separate dot product pass)
-  auto normal = [&](void* in, void* out, double* sn) -> int {
-    LQ_TRY(e.schur(0, in, sx, tA, tB, w.partials));
+  // With rp, in is first updated in place to rp + beta in (the CG direction
+  // update, fused into the operator's first launch).
+  auto normal = [&](void* in, void* out, double* sn, const void* rp, double beta) -> int {
+    LQ_TRY(e.schur(0, in, sx, tA, tB, w.partials, rp, beta));
     LQ_TRY(e.schur(1, sx, out, tA, tB));
     return sum_partials_host(c, w, (size_t)e.grid.x * 256, nullptr, sn);
   };
-  auto normal32 = [&](void* in, void* out, double* sn) -> int {  // the same in FP32
-    LQ_TRY(e32.schur(0, in, sx32, tA32, tB32, w.partials));
+  auto normal32 = [&](void* in, void* out, double* sn, const void* rp, double beta) -> int {  // the same in FP32
+    LQ_TRY(e32.schur(0, in, sx32, tA32, tB32, w.partials, rp, beta));
     LQ_TRY(e32.schur(1, sx32, out, tA32, tB32));
     return sum_partials_host(c, w, (size_t)e32.grid.x * 256, nullptr, sn);
   };
@@ -1118,16 +1135,19 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
       double rr32 = 0.0;
       LQ_TRY(dot(c, w, nh, ev(r32), ev(r32), nullptr, &rr32, 1));
       const double tgt32 = std::max(delta * std::sqrt(rr32), target);
+      double beta = 0.0;
+      bool first = true;
       while (iters < prm.max_iter) {
         double pq = 0.0;
-        LQ_TRY(normal32(p32, q32, &pq));
+        LQ_TRY(normal32(p32, q32, &pq, first ? nullptr : r32, beta));  // p = r + beta p first, after the first
         if (!(pq > 0.0)) break;
         const double alpha = rr32 / pq;
         double rn = 0.0;
         LQ_TRY(xr_update(c, w, nh, ev(e32f), ev(p32), ev(r32), ev(q32), alpha, &rn, 1));
         ++iters;
         if (std::sqrt(rn) <= tgt32) break;
-        LQ_TRY(axpy(c, nh, ev(p32), ev(r32), ev(p32), rn / rr32, 1));
+        beta = rn / rr32;
+        first = false;
         rr32 = rn;
       }
       LQ_TRY(flat_accum_up(c, nh, ev(x), ev(e32f)));
@@ -1136,16 +1156,19 @@ int dwf_solve_eo(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params&
     }
     LQ_TRY(axpy(c, nh, ev(pv), ev(r), ev(r), 0.0));
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
+    double beta = 0.0;
+    bool first = true;
     while (iters < prm.max_iter) {
       double pq = 0.0;
-      LQ_TRY(normal(pv, q, &pq));
+      LQ_TRY(normal(pv, q, &pq, first ? nullptr : r, beta));  // p = r + beta p first, after the first
       if (!(pq > 0.0)) break;
       const double alpha = rr / pq;
       double rn = 0.0;
       LQ_TRY(xr_update(c, w, nh, ev(x), ev(pv), ev(r), ev(q), alpha, &rn));
       ++iters;
       if (std::sqrt(rn) <= tgt) break;
-      LQ_TRY(axpy(c, nh, ev(pv), ev(r), ev(pv), rn / rr));
+      beta = rn / rr;
+      first = false;
       rr = rn;
     }
     target *= 0.5;
