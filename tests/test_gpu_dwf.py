@@ -176,6 +176,23 @@ def test_dwf_solve_zero_source(form):
     assert st.true_rel_resid == 0.0 and st.inner_iters == 0 and np.all(from_dev(x) == 0), st
 
 
+@pytest.mark.parametrize("inner_prec", [0, 1])
+def test_dwf_solve_eo_is_deterministic(inner_prec):
+    """Fixed-order reductions: two even-odd solves of the same system give the
+    same x bit for bit (FP64 and FP32-inner)."""
+    dims, Ls = (4, 4, 8, 8), 6
+    U = fg.gauge_field(dims, 132, "smooth", 0.3)
+    b = to_dev(field5(dims, Ls, 133))
+    lat = lattice(dims, U, 0.12, 0.0)
+    xs, its = [], []
+    for _ in range(2):
+        x = to_dev(np.zeros(b.shape, dtype=np.complex128))
+        st = lat.dwf_solve_eo(Ls, 1.8, 0.1, b, x, b5=1.5, c5=0.5, inner_prec=inner_prec)
+        xs.append(from_dev(x))
+        its.append(st.inner_iters)
+    assert np.array_equal(xs[0], xs[1]) and its[0] == its[1]
+
+
 def test_dwf_solve_eo_rejects_fp16_inner():
     dims, Ls = (4, 4, 4, 4), 4
     U = fg.gauge_field(dims, 127, "smooth", 0.3)

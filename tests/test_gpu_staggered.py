@@ -95,6 +95,23 @@ def test_stag_solve_mixed_matches_oracle(dims, mass, inner_tol):
 
 
 @pytest.mark.parametrize("inner_prec", [0, 1])
+def test_stag_solve_is_deterministic(inner_prec):
+    """Fixed-order reductions: two solves of the same system give the same x
+    bit for bit (FP64 and FP32-inner)."""
+    dims = (4, 6, 8, 10)
+    U = fg.gauge_field(dims, 98, "smooth", 0.3)
+    b = to_dev(colour_field(dims, 99))
+    lat = lattice(dims, U, 0.12, 0.0)
+    xs, its = [], []
+    for _ in range(2):
+        x = to_dev(np.zeros(b.shape, dtype=np.complex128))
+        st = lat.stag_solve(0.05, b, x, inner_prec=inner_prec)
+        xs.append(from_dev(x))
+        its.append(st.inner_iters)
+    assert np.array_equal(xs[0], xs[1]) and its[0] == its[1]
+
+
+@pytest.mark.parametrize("inner_prec", [0, 1])
 def test_stag_zero_source(inner_prec):
     dims = (4, 4, 4, 4)
     U = fg.gauge_field(dims, 87, "haar")
