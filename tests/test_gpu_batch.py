@@ -46,6 +46,31 @@ def test_batch_matches_oracle(prec, csw):
             k += 1
 
 
+@pytest.mark.parametrize("prec", [lqcd.F32, lqcd.F16])
+def test_batch_is_deterministic(prec):
+    """Fixed-order per-RHS reductions: two batched solves give the same x bit
+    for bit."""
+    torch = torch_cuda()
+    stream = torch.cuda.Stream()
+    specs = [((4, 6, 8, 10), 3, 31), ((4, 4, 4, 4), 2, 32)]
+    lats, bs = [], []
+    for dims, n, seed in specs:
+        U = fg.gauge_field(dims, seed, "smooth", 0.3)
+        lat = lqcd.Lattice(dims, -1, stream=stream)
+        lat.set_gauge(to_dev(U))
+        lat.set_clover(0.136, 1.0)
+        lats.append(lat)
+        bs.append(to_dev(np.stack([fg.gaussian_spinor(dims, seed + 100 + k) for k in range(n)])))
+    runs = []
+    for _ in range(2):
+        xs = [to_dev(np.zeros(tuple(b.shape), dtype=np.complex128)) for b in bs]
+        st = lqcd.solve_batch(lats, bs, xs, inner_prec=prec)
+        runs.append(([from_dev(x) for x in xs], [s.inner_iters for s in st]))
+    assert runs[0][1] == runs[1][1]
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, b)
+
+
 def test_batch_host_pointers_and_zero_rhs():
     specs = [((4, 4, 4, 8), 4, 21), ((4, 4, 4, 4), 2, 22)]
     lats, ops, bs, xs = [], [], [], []

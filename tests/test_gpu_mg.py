@@ -118,6 +118,20 @@ def test_solve_mg_matches_oracle(iters, csw):
     assert dirac.rel_l2(xh, xo) <= 1e-8
 
 
+def test_solve_mg_is_deterministic():
+    """Two multigrid-preconditioned solves after one setup give the same x bit
+    for bit."""
+    U, op, lat, start, kw, P = build(4, 2)
+    lat.mg_setup(to_dev(start), **kw)
+    b = to_dev(fg.gaussian_spinor(DIMS, 65))
+    xs = []
+    for _ in range(2):
+        x = to_dev(np.zeros(tuple(b.shape), dtype=np.complex128))
+        lat.solve_mg(b, x, tol=1e-10)
+        xs.append(from_dev(x))
+    assert np.array_equal(xs[0], xs[1])
+
+
 def test_mg_errors_and_state():
     from paper_2303_05883_amd import lqcd
     U, op, lat, start, kw, P = build(2, 0)

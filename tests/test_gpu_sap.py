@@ -126,3 +126,17 @@ def test_sap_properties_at_benchmark_size():
         sites, want = sampled.sap_one_cycle_at(U, kappa, 1.0, -1, eta_h, (16, 4, 2, 2), origin, 6)
         got = sampled.gather(got_all, sites)
         assert dirac.rel_l2(got, want) <= SAP_TOL, origin
+
+
+def test_sap_solve_is_deterministic():
+    """Two SAP-preconditioned solves of one system give the same x bit for bit."""
+    dims = (8, 8, 8, 16)
+    U = fg.gauge_field(dims, 51, "smooth", 0.3)
+    b = to_dev(fg.gaussian_spinor(dims, 52))
+    lat = lattice(dims, U, 0.137, 1.0)
+    xs = []
+    for _ in range(2):
+        x = to_dev(np.zeros(tuple(b.shape), dtype=np.complex128))
+        lat.solve_sap(b, x, (4, 4, 4, 4), 2, 4, tol=1e-10)
+        xs.append(from_dev(x))
+    assert np.array_equal(xs[0], xs[1])

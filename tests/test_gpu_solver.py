@@ -64,14 +64,17 @@ def test_matches_dense_solve():
     assert dirac.rel_l2(x, xd) <= 1e-9
 
 
-def test_fp64_solve_is_deterministic():
+@pytest.mark.parametrize("inner_prec", [0, 1, 2])
+def test_solve_is_deterministic(inner_prec):
+    """Fixed-order reductions: repeated solves of one system give the same x
+    bit for bit, in FP64 and with FP32 or FP16 inner solves."""
     dims = (4, 6, 8, 10)
     U = fg.gauge_field(dims, 11, "smooth", 0.3)
     b = fg.gaussian_spinor(dims, 12)
     lat = lattice(dims, U, 0.135, 1.0)
     x1, x2 = np.zeros_like(b), np.zeros_like(b)
-    s1 = lat.solve(b, x1)
-    s2 = lat.solve(b, x2)
+    s1 = lat.solve(b, x1, inner_prec=inner_prec)
+    s2 = lat.solve(b, x2, inner_prec=inner_prec)
     assert np.array_equal(x1, x2) and s1.inner_iters == s2.inner_iters
 
 
