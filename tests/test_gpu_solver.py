@@ -34,6 +34,25 @@ def test_wilson_haar_8(prec, graph):
 
 
 @pytest.mark.parametrize("prec", [lqcd.F64, lqcd.F32, lqcd.F16])
+def test_graph_replays_match_eager(prec):
+    """The captured iteration chunk, replayed many times per solve with the
+    solver's own host checks and FP64 outer work between the replays, gives the
+    eager launches' x bit for bit, solve after solve."""
+    dims = (8, 8, 8, 8)
+    U = fg.gauge_field(dims, 1004, "smooth", 0.3)
+    b = to_dev(fg.gaussian_spinor(dims, 1004))
+    lat = lattice(dims, U, 0.137, 1.0)
+    res = {}
+    for graph in (False, True, True):
+        x = to_dev(np.zeros(tuple(b.shape), dtype=np.complex128))
+        st = lat.solve(b, x, inner_prec=prec, use_graph=graph, check_every=4)
+        res.setdefault(graph, []).append((from_dev(x), st.inner_iters))
+    eager_x, eager_it = res[False][0]
+    for gx, git in res[True]:
+        assert git == eager_it and np.array_equal(gx, eager_x)
+
+
+@pytest.mark.parametrize("prec", [lqcd.F64, lqcd.F32, lqcd.F16])
 @pytest.mark.parametrize("split", [1, 4, 0])
 @pytest.mark.parametrize("reliable", [True, False])
 def test_clover_smooth(prec, split, reliable):
