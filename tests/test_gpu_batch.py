@@ -71,6 +71,32 @@ def test_batch_is_deterministic(prec):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", [lqcd.F32, lqcd.F16])
+def test_batch_graph_replays_match_eager(prec):
+    """The batched solve's captured iteration chunks, replayed with the host
+    checks between them, give the eager launches' x bit for bit."""
+    torch = torch_cuda()
+    stream = torch.cuda.Stream()
+    specs = [((4, 6, 8, 10), 3, 33), ((4, 4, 4, 4), 2, 34)]
+    lats, bs = [], []
+    for dims, n, seed in specs:
+        U = fg.gauge_field(dims, seed, "smooth", 0.3)
+        lat = lqcd.Lattice(dims, -1, stream=stream)
+        lat.set_gauge(to_dev(U))
+        lat.set_clover(0.136, 1.0)
+        lats.append(lat)
+        bs.append(to_dev(np.stack([fg.gaussian_spinor(dims, seed + 100 + k) for k in range(n)])))
+    runs = []
+    for graph in (False, True, True):
+        xs = [to_dev(np.zeros(tuple(b.shape), dtype=np.complex128)) for b in bs]
+        st = lqcd.solve_batch(lats, bs, xs, inner_prec=prec, use_graph=graph, check_every=4)
+        runs.append(([from_dev(x) for x in xs], [s.inner_iters for s in st]))
+    for xs_g, it_g in runs[1:]:
+        assert it_g == runs[0][1]
+        for a, b in zip(runs[0][0], xs_g):
+            assert np.array_equal(a, b)
+
+
 def test_batch_host_pointers_and_zero_rhs():
     specs = [((4, 4, 4, 8), 4, 21), ((4, 4, 4, 4), 2, 22)]
     lats, ops, bs, xs = [], [], [], []
