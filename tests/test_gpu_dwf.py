@@ -193,6 +193,24 @@ def test_dwf_solve_eo_is_deterministic(inner_prec):
     assert np.array_equal(xs[0], xs[1]) and its[0] == its[1]
 
 
+@pytest.mark.parametrize("Ls", [256, 255])
+def test_dwf_largest_ls_matches_oracle(Ls):
+    """The largest fifth dimension a workgroup holds (one 4-d site of 256
+    lanes) and an odd one just below (255 lanes of 256 live): D and D^dag
+    against the oracle in FP64 and FP32."""
+    dims = (2, 2, 2, 4)
+    U = fg.gauge_field(dims, 134, "haar")
+    psi = field5(dims, Ls, 135)
+    op = dwf.DomainWall(U, 1.8, 0.05, Ls, -1, 1.5, 0.5)
+    lat = lattice(dims, U, 0.12, 0.0)
+    for prec in (0, 1):
+        for dag in (False, True):
+            out = to_dev(np.zeros_like(psi))
+            lat.dwf_apply(Ls, 1.8, 0.05, prec, to_dev(psi), out, dag=dag, b5=1.5, c5=0.5)
+            want = op.Ddag(psi) if dag else op.D(psi)
+            assert dirac.rel_l2(from_dev(out), want) <= TOL[prec], (prec, dag)
+
+
 def test_dwf_solve_eo_rejects_fp16_inner():
     dims, Ls = (4, 4, 4, 4), 4
     U = fg.gauge_field(dims, 127, "smooth", 0.3)
