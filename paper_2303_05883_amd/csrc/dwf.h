@@ -14,9 +14,10 @@ int dwf_export(lqcd_ctx* c, int prec, int Ls, const void* f5, double* canon);
 // out = D in (dag 0) or D^dag in (dag 1); in != out; 1 <= Ls <= 256; tmp: a
 // third 5-d field, needed (phi) by D with c5 != 0 only; norm_partials: if
 // given, the launch's workgroups write their partial sums of |out|^2 as
-// (0, value) pairs, dwf_apply_groups of them
+// (0, value) pairs, dwf_apply_groups of them; upd (D with c5 != 0 only): in
+// is first replaced in place by upd + upd_beta in (a CG direction update)
 int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tmp,
-              double* norm_partials = nullptr);
+              double* norm_partials = nullptr, const void* upd = nullptr, double upd_beta = 0.0);
 size_t dwf_apply_groups(const Geom& g, int prec, int Ls);
 // Even-odd form (4-d parity): out_e = S_ee in_e (dag 0) or S_ee^dag in_e (dag
 // 1), S_ee = M5op - Dhop_eo M5op^-1 Dhop_oe; only the even halves of in and

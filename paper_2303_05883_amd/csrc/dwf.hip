@@ -57,6 +57,8 @@ struct DwfArgs {
   double d4;         // 4 - M5
   double b5, c5, mf;
   double* norm;      // k_dwf: partial sums of |out|^2, a (0, value) pair per workgroup, or null
+  const char* upd;   // k_dwf_phi: in is first replaced in place by upd + upd_beta in (or null)
+  double upd_beta;
 };
 
 // The 5-d site of this lane, or false past the end. XCD k (the workgroups
@@ -306,7 +308,9 @@ __global__ void __launch_bounds__(DWB) k_dwf(DwfArgs a) {
   }
 }
 
-// out = (b5 + c5 S) in, every 5-d site
+// out = (b5 + c5 S) in, every 5-d site; with a.upd, in is first replaced at
+// this lane's site by upd + upd_beta in and stored back (a CG search-direction
+// update fused into the operator, whose later kernel reads in at its own site)
 template <int P>
 __global__ void __launch_bounds__(DWB) k_dwf_phi(DwfArgs a) {
   using T = typename IO<P>::T;
@@ -318,6 +322,14 @@ __global__ void __launch_bounds__(DWB) k_dwf_phi(DwfArgs a) {
   cx<T> v[12];
   if (live) {
     IO<P>::load_spinor(a.in + (size_t)p * a.hb, j, v);
+    if (a.upd) {
+      cx<T> rv[12];
+      IO<P>::load_spinor(a.upd + (size_t)p * a.hb, j, rv);
+      const T bt = (T)a.upd_beta;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = rv[k] + bt * v[k];
+      IO<P>::store_spinor(const_cast<char*>(a.in) + (size_t)p * a.hb, j, v);
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = {T(0), T(0)};
@@ -636,12 +648,13 @@ size_t dwf_apply_groups(const Geom& g, int prec, int Ls) {
 // out = D in (dag = 0) or D^dag in (dag = 1) on native 5-d fields (in != out;
 // tmp, a third field, holds phi for D with c5 != 0)
 int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const void* in, void* out, void* tmp,
-              double* norm_partials) {
+              double* norm_partials, const void* upd, double upd_beta) {
   if (!c->gauge[prec]) return set_error(LQCD_ESTATE, "gauge field not set");
   if (d.Ls < 1 || d.Ls > DWB) return set_error(LQCD_EINVAL, "domain-wall operator: Ls must be in [1, 256]");
   if (prec != 0 && prec != 1) return set_error(LQCD_EINVAL, "domain-wall operator: precision must be F64 or F32");
   const bool mob = !dag && d.c5 != 0.0;
   if (mob && !tmp) return set_error(LQCD_EINVAL, "domain-wall operator: D with c5 != 0 needs a scratch field");
+  if (upd && !mob) return set_error(LQCD_EINVAL, "domain-wall operator: a fused update needs D with c5 != 0");
   DwfArgs a{};
   a.gauge = reinterpret_cast<const char*>(c->gauge[prec]);
   a.link_stride = link_bytes(prec, c->g.vh);
@@ -663,6 +676,8 @@ int dwf_apply(lqcd_ctx* c, int prec, const lqcd_dwf_params& d, int dag, const vo
     DwfArgs f = a;
     f.out = reinterpret_cast<char*>(tmp);
     f.norm = nullptr;
+    f.upd = reinterpret_cast<const char*>(upd);
+    f.upd_beta = upd_beta;
     if (prec == 0) hipLaunchKernelGGL(k_dwf_phi<0>, grid, block, 0, c->stream, f);
     else hipLaunchKernelGGL(k_dwf_phi<1>, grid, block, 0, c->stream, f);
   }
@@ -808,8 +823,14 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
     LQ_TRY(dot(c, w, n, r, r, nullptr, &rr));
     LQ_TRY(axpy(c, n, p, r, r, 0.0));             // p = r
     const double tgt = std::min(target, 0.5 * std::sqrt(rr));
+    // Moebius D forms phi = (b5 + c5 S) p first, at each site from p there:
+    // that pass also does the direction update p = r + beta p
+    const bool fuse = d.c5 != 0.0;
+    double beta = 0.0;
+    bool first = true;
     while (iters < prm.max_iter) {
-      LQ_TRY(dwf_apply(c, 0, d, 0, p, t, ph, w.partials));  // t = D p, with the partials of |D p|^2
+      // t = D p, with the partials of |D p|^2
+      LQ_TRY(dwf_apply(c, 0, d, 0, p, t, ph, w.partials, fuse && !first ? r : nullptr, beta));
       LQ_TRY(dwf_apply(c, 0, d, 1, t, q, ph));              // q = D^dag D p
       double pq = 0.0;                                       // <p, D^dag D p> = |D p|^2
       LQ_TRY(sum_partials_host(c, w, ngroups * 256, nullptr, &pq));
@@ -822,7 +843,9 @@ int dwf_solve(lqcd_ctx* c, const lqcd_dwf_params& d, const lqcd_solve_params& pr
         rr = rn;
         break;
       }
-      LQ_TRY(axpy(c, n, p, r, p, rn / rr));
+      beta = rn / rr;
+      first = false;
+      if (!fuse) LQ_TRY(axpy(c, n, p, r, p, beta));
       rr = rn;
     }
     // the next pass iterates on the recomputed residual to a tighter normal target if needed
